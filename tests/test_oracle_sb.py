@@ -1,0 +1,207 @@
+"""Pins of the oracle's Ising map, SB integrator, energy and brute force."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import trackgen as tg
+from oracle import brute, energy, ising, qubo, sb, tracks
+
+
+def _qubo_csr(n, seed, density=0.3):
+    a, b = tg.random_qubo(n, seed, density=density)
+    return a, sp.csr_matrix(b), b
+
+
+# ------------------------------------------------------------- Ising map
+
+def test_qubo_ising_identity_random_T():
+    ev = tg.generate(tg.plain_spec(60), 4)
+    q = qubo.build_event(ev)
+    isg = ising.from_qubo(q.a, q.b)
+    rng = np.random.default_rng(0)
+    T = (rng.random((q.n, 16)) < 0.5).astype(np.int8)
+    s = 2.0 * T - 1.0
+    O = energy.qubo_energy(q.a, q.b, T)
+    E = ising.ising_energy(isg, s)
+    assert np.allclose(O, E + isg.C, rtol=1e-12, atol=1e-12 * np.abs(O).max())
+
+
+def test_c0_is_population_std_of_all_entries():
+    a, bcsr, bdense = _qubo_csr(15, 3)
+    isg = ising.from_qubo(a, bcsr)
+    Jd = -bdense / 4.0
+    assert isg.c0 == pytest.approx(0.5 / (math.sqrt(15) * np.std(Jd)), rel=1e-12)
+    assert np.array_equal(isg.J.toarray(), Jd)
+    assert np.allclose(isg.h, -(a / 2 + bdense.sum(axis=1) / 4), rtol=0, atol=1e-15)
+
+
+def test_c0_without_couplings():
+    isg = ising.from_qubo(np.array([0.1, 0.2, 0.3, 0.4]), sp.csr_matrix((4, 4)))
+    assert isg.c0 == 0.25
+
+
+# ------------------------------------------------------ energy and brute
+
+def test_energy_matches_quadratic_form():
+    a, bcsr, bdense = _qubo_csr(18, 5)
+    rng = np.random.default_rng(1)
+    T = (rng.random((18, 40)) < 0.5).astype(np.int8)
+    O = energy.qubo_energy(a, bcsr, T)
+    Tf = T.astype(float)
+    expect = Tf.T @ a + np.array([sum(bdense[i, j] * Tf[i, k] * Tf[j, k]
+                                      for i in range(18) for j in range(i))
+                                  for k in range(40)])
+    assert np.allclose(O, expect, rtol=0, atol=1e-12)
+
+
+def test_brute_force_against_plain_loop():
+    a, _, bdense = _qubo_csr(8, 6)
+    best = math.inf
+    for code in range(256):
+        T = [(code >> i) & 1 for i in range(8)]
+        o = sum(a[i] * T[i] for i in range(8))
+        o += sum(bdense[i, j] * T[i] * T[j] for i in range(8) for j in range(i))
+        best = min(best, o)
+    e, winners = brute.ground_states(a, bdense)
+    assert e == pytest.approx(best, abs=1e-12)
+    for w in winners:
+        assert energy.qubo_energy(a, sp.csr_matrix(bdense), w) == pytest.approx(best, abs=1e-12)
+
+
+def test_best_agent_ties_lowest_index():
+    assert energy.best_agent(np.array([3.0, -1.0, 2.0, -1.0])) == 1
+
+
+# -------------------------------------------------------- SB integrator
+
+def _closed_form_free(x0, y0, steps, dt, a0):
+    """J = 0, h = 0: each spin follows (x, y) <- M_k (x, y) with
+    M_k = [[1 - dt^2 a0 (a0 - a_k), dt a0], [-dt (a0 - a_k), 1]]."""
+    v = np.array([x0, y0], dtype=np.float64)
+    for k in range(steps):
+        g = a0 - a0 * k / steps
+        M = np.array([[1.0 - dt * dt * a0 * g, dt * a0], [-dt * g, 1.0]])
+        v = M @ v
+    return v
+
+
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+def test_free_oscillator_matches_matrix_product(mode):
+    n, m, K = 6, 3, 40
+    J = sp.csr_matrix((n, n))
+    h = np.zeros(n)
+    r = sb.run(J, h, 0.7, mode, m, K, dt=0.5, a0=1.3, seed=9)
+    from oracle.philox import initial_state
+    x0, y0 = initial_state(n, m, 9)
+    for i in range(n):
+        for k in range(m):
+            v = _closed_form_free(x0[i, k], y0[i, k], K, 0.5, 1.3)
+            assert np.all(np.abs(v) < 1.0)       # no wall in this window
+            assert r.x[i, k] == pytest.approx(v[0], rel=1e-13, abs=1e-15)
+            assert r.y[i, k] == pytest.approx(v[1], rel=1e-13, abs=1e-15)
+
+
+def test_wall_is_strict_and_inelastic():
+    """One spin, J = 0, h = 1, c0 = 1, a0 = dt = 1, from rest at x = y = 0.
+    With K = 1 (a_0 = 0): y = 1, x = 1, which is on the wall but not past it,
+    so nothing is clamped.  With K = 2 (a = 0, 1/2): step 0 as before, then
+    y = 1 + (1 - 1/2) = 1.5, x = 2.5 -> clamped to (1, 0)."""
+    J = sp.csr_matrix((1, 1))
+    z = np.zeros((1, 1))
+    r = sb.run(J, np.array([1.0]), 1.0, "bsb", 1, 1, x0=z, y0=z)
+    assert (r.x[0, 0], r.y[0, 0]) == (1.0, 1.0)
+    r = sb.run(J, np.array([1.0]), 1.0, "bsb", 1, 2, x0=z, y0=z)
+    assert (r.x[0, 0], r.y[0, 0]) == (1.0, 0.0)
+    r = sb.run(J, np.array([-1.0]), 1.0, "dsb", 1, 2, x0=z, y0=z)
+    assert (r.x[0, 0], r.y[0, 0]) == (-1.0, 0.0)
+
+
+def test_coupled_pair_dsb_vs_bsb_by_hand():
+    """Two spins, J_01 = 1, h = 0, c0 = 1, a0 = dt = 1, one step (a_0 = 0):
+    bSB: y' = y + (x_other - x), x' = x + y';  dSB: y' = y + (sgn(x_other) - x)."""
+    J = sp.csr_matrix(np.array([[0.0, 1.0], [1.0, 0.0]]))
+    x0 = np.array([[0.1], [-0.05]])
+    y0 = np.array([[0.02], [0.03]])
+    rb = sb.run(J, np.zeros(2), 1.0, "bsb", 1, 1, x0=x0, y0=y0)
+    rd = sb.run(J, np.zeros(2), 1.0, "dsb", 1, 1, x0=x0, y0=y0)
+    yb = [0.02 + (-0.05 - 0.1), 0.03 + (0.1 + 0.05)]
+    yd = [0.02 + (-1.0 - 0.1), 0.03 + (1.0 + 0.05)]
+    assert np.allclose(rb.y[:, 0], yb, rtol=0, atol=1e-16)
+    assert np.allclose(rb.x[:, 0], [0.1 + yb[0], -0.05 + yb[1]], rtol=0, atol=1e-16)
+    # dSB: x0 + y' = 0.1 - 1.08 = -0.98 (inside), -0.05 + 1.08 = 1.03 (wall)
+    assert np.allclose(rd.x[:, 0], [0.1 + yd[0], 1.0], rtol=0, atol=1e-16)
+    assert np.allclose(rd.y[:, 0], [yd[0], 0.0], rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+def test_sign_symmetry_without_field(mode):
+    ev = tg.generate(tg.plain_spec(40), 8)
+    q = qubo.build_event(ev)
+    isg = ising.from_qubo(q.a, q.b)
+    from oracle.philox import initial_state
+    x0, y0 = initial_state(q.n, 4, 17)
+    assert np.all(x0 != 0)
+    h0 = np.zeros(q.n)
+    r1 = sb.run(isg.J, h0, isg.c0, mode, 4, 200, x0=x0, y0=y0)
+    r2 = sb.run(isg.J, h0, isg.c0, mode, 4, 200, x0=-x0, y0=-y0)
+    assert np.array_equal(r1.x, -r2.x) and np.array_equal(r1.y, -r2.y)
+
+
+def test_agents_are_independent_shots():
+    ev = tg.generate(tg.plain_spec(30), 9)
+    q = qubo.build_event(ev)
+    isg = ising.from_qubo(q.a, q.b)
+    r_all = sb.run(isg.J, isg.h, isg.c0, "dsb", 6, 100, seed=3)
+    from oracle.philox import initial_state
+    x0, y0 = initial_state(q.n, 6, 3)
+    r_one = sb.run(isg.J, isg.h, isg.c0, "dsb", 1, 100, x0=x0[:, 4:5], y0=y0[:, 4:5])
+    assert np.array_equal(r_all.x[:, 4:5], r_one.x)
+
+
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+def test_sb_reaches_brute_force_ground_state(mode):
+    """Heuristic: 32 agents x 2000 steps find the exact minimum of most
+    small random QUBOs with track-like sparsity (about two couplings per
+    variable); the rate is asserted at 90%."""
+    hits = 0
+    total = 0
+    for seed in range(40):
+        a, bcsr, bdense = _qubo_csr(14, 100 + seed, density=0.15)
+        e_min, _ = brute.ground_states(a, bdense)
+        isg = ising.from_qubo(a, bcsr)
+        r = sb.run(isg.J, isg.h, isg.c0, mode, 32, 2000, seed=seed)
+        E = energy.qubo_energy(a, bcsr, sb.readout(r.x))
+        total += 1
+        hits += int(E.min() <= e_min + 1e-9)
+        assert E.min() >= e_min - 1e-9
+    assert hits >= 0.9 * total
+
+
+def test_true_tracks_are_single_flip_local_minimum():
+    """Noise-free 4-layer events: switching a true triplet off loses its
+    quadruplet reward (S <= 1 outweighs a_i), switching a fake on adds a
+    conflict (+1) that no reward S <= 1 pays back."""
+    for seed in range(1, 6):
+        ev = tg.generate(tg.tiny_spec(), seed)
+        q = qubo.build_event(ev)
+        T = tracks.true_triplet_mask(ev, q.trip_hits)
+        e0 = energy.qubo_energy(q.a, q.b, T)
+        for i in range(q.n):
+            T2 = T.copy()
+            T2[i] ^= 1
+            assert energy.qubo_energy(q.a, q.b, T2) > e0
+
+
+def test_tiny_event_solution_reconstructs_every_track():
+    ev = tg.generate(tg.tiny_spec(), 2)
+    q = qubo.build_event(ev)
+    isg = ising.from_qubo(q.a, q.b)
+    r = sb.run(isg.J, isg.h, isg.c0, "dsb", 32, 2000, seed=1)
+    E = energy.qubo_energy(q.a, q.b, sb.readout(r.x))
+    best = energy.best_agent(E)
+    T = sb.readout(r.x)[:, best]
+    assert np.array_equal(T, tracks.true_triplet_mask(ev, q.trip_hits))
+    eff, pur, *_ = tracks.evaluate(ev, q.trip_hits, T)
+    assert eff == 1.0 and pur == 1.0
