@@ -1,0 +1,224 @@
+/*
+ * sbtrack.h -- C ABI of the MI355X simulated-bifurcation track-QUBO library.
+ *
+ * The library implements the method of Okawa, Zeng, Tao, Yung,
+ * "Quantum-Annealing-Inspired Algorithms for Track Reconstruction at
+ * High-Energy Colliders":
+ *   hits -> QUBO over hit triplets   (sections "QUBO Formulation" and
+ *                                     "QUBO Generation and Track Finding")
+ *   QUBO -> lowest-energy assignment by ballistic / discrete simulated
+ *           bifurcation               (section "Simulated Bifurcation")
+ * The solver runs entirely in HIP kernels for gfx950 (CDNA4).
+ *
+ * Conventions for every function:
+ *   - the return value is a status: SBT_OK (0) or a negative SBT_E* code;
+ *     sbt_last_error() then returns a thread-local message.  No C++
+ *     exception crosses this interface.
+ *   - inputs are borrowed for the duration of the call; outputs go into
+ *     caller-owned buffers, except an sbt_qubo, which the library allocates
+ *     and sbt_qubo_free releases.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device allocations on the current device.
+ *   - results are deterministic: the same inputs, parameters and seed give
+ *     bit-identical outputs on every run.
+ */
+#ifndef SBTRACK_H
+#define SBTRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBT_OK 0
+#define SBT_EINVAL (-1)       /* invalid argument; nothing was written        */
+#define SBT_ENOMEM (-2)       /* host or device allocation failed             */
+#define SBT_EDEVICE (-3)      /* a HIP runtime call or kernel launch failed   */
+#define SBT_EUNSUPPORTED (-4) /* valid request outside what is implemented    */
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *sbt_last_error(void);
+
+/* Library version string. */
+const char *sbt_version(void);
+
+/* ------------------------------------------------------------------------
+ * Hits and QUBO construction (host, FP64)
+ * ---------------------------------------------------------------------- */
+
+/* One silicon hit (paper, Dataset section: barrel layers only).  Lengths in
+ * mm.  layer counts outward from 0; doublets join layers L and L+1. */
+typedef struct {
+    int64_t hit_id; /* caller's id; triplets are ordered by these ids      */
+    int32_t layer;
+    int32_t pad;    /* ignored                                            */
+    double x, y, z;
+} sbt_hit;
+
+/* Construction parameters.  sbt_build_params_default() fills the values
+ * used throughout: doublet window |dphi| < 0.1 rad; Eq. 16: |kappa| <=
+ * 8e-4 mm^-1, dtheta <= 0.1 rad, holes <= 1; Eq. 17: |dkappa| <= 1e-4,
+ * S > 0.2; five-hit rule with min(5, layers); Eq. 15 alpha, beta, gamma,
+ * lambda = 0.5, 0.2, 1.0, 0.5 (d0, z0 in mm). */
+typedef struct {
+    double dphi_tan;       /* tan of the doublet azimuth window             */
+    double z0_max;         /* doublet |z0| cut in mm; <= 0 disables it      */
+    double curv_max;       /* Eq. 16 curvature bound, mm^-1                 */
+    double dtheta_tan;     /* Eq. 16: tan of the r-z angle bound            */
+    double dcurv_max;      /* Eq. 17 curvature-difference bound, mm^-1      */
+    double s_min;          /* Eq. 17 lower bound on S_ij (exclusive)        */
+    int32_t max_holes;     /* Eq. 16                                        */
+    int32_t min_track_hits;/* five-hit rule; -1 = min(5, number of layers); */
+                           /* values above 5 are SBT_EUNSUPPORTED           */
+    double alpha, beta, gamma_, lambda_; /* Eq. 15                          */
+} sbt_build_params;
+
+void sbt_build_params_default(sbt_build_params *p);
+
+/* A QUBO O(a, b, T) = sum_i a_i T_i + sum_{j<i} b_ij T_i T_j (Eq. 13) over
+ * triplets, with b symmetric (both triangles stored, zero diagonal) in CSR
+ * with ascending columns.  Host memory owned by the library. */
+typedef struct {
+    int32_t n;          /* number of triplets (QUBO variables)                */
+    int64_t nnz;        /* stored entries of b                                 */
+    double *a;          /* [n]     bias weights, Eq. 15                        */
+    int64_t *row_ptr;   /* [n+1]                                               */
+    int32_t *col;       /* [nnz]                                               */
+    double *b;          /* [nnz]   +1 conflict, -S_ij quadruplet (Eq. 14)      */
+    int64_t *trip_hits; /* [3n]    hit ids of triplet i, layer order           */
+} sbt_qubo;
+
+/* Build the QUBO of Eq. 13 from hits (paper: "QUBO Formulation", "QUBO
+ * Generation and Track Finding"): adjacent-layer doublets, triplets cut by
+ * Eq. 16, quadruplets cut by Eq. 17 and the five-hit rule, triplets outside
+ * every kept quadruplet dropped, triplets indexed in ascending
+ * (id1, id2, id3) order, a_i from Eq. 15 and b_ij from Eq. 13/14.
+ *   hits    host [n_hits]; any order; hit ids must be distinct
+ *   p       host; NULL = defaults
+ *   out     receives a library-owned QUBO (n may be 0); free with sbt_qubo_free
+ * Errors: SBT_EINVAL for n_hits < 0, non-finite coordinates, negative layers
+ * or duplicate ids. */
+int sbt_build_qubo(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *p,
+                   sbt_qubo **out);
+void sbt_qubo_free(sbt_qubo *q);
+
+/* Exact FP64 value of Eq. 13 for a binary assignment (host, compensated
+ * summation, rows in order, pairs j > i).  T host [n] of 0/1. */
+int sbt_energy(const sbt_qubo *q, const int8_t *T, double *energy);
+
+/* ------------------------------------------------------------------------
+ * Simulated bifurcation (HIP)
+ * ---------------------------------------------------------------------- */
+
+typedef enum { SBT_BSB = 0, SBT_DSB = 1 } sbt_mode;
+
+/* Which step kernel runs.  AUTO picks by problem shape. */
+typedef enum {
+    SBT_KERNEL_AUTO = 0,
+    SBT_KERNEL_RESIDENT = 1, /* one launch for all steps; a workgroup owns
+                                whole agents, positions live in LDS        */
+    SBT_KERNEL_STREAM = 2    /* one launch per step; state streams through
+                                HBM, lanes are agents                       */
+} sbt_kernel;
+
+/* Solver parameters (section "Simulated Bifurcation" and Results: a0 = dt = 1,
+ * fixed c0).  sbt_solve_params_default() fills a0 = dt = 1, c0 = auto,
+ * agents = 32, steps = 2000, seed = 0, event = 0, kernel = AUTO,
+ * energy_every = 0. */
+typedef struct {
+    double a0;            /* a0 > 0                                          */
+    double dt;            /* time step > 0                                   */
+    double c0;            /* coupling scale; <= 0 or NaN: 0.5/(sqrt(N) sd(J)) */
+                          /* with sd the population std of all N^2 entries  */
+    int32_t agents;       /* independent shots M >= 1                        */
+    int32_t steps;        /* symplectic-Euler steps K >= 1                   */
+    uint64_t seed;        /* Philox key                                      */
+    int32_t event;        /* Philox counter word 2 (batch position)          */
+    int32_t kernel;       /* sbt_kernel                                      */
+    int32_t energy_every; /* > 0: record the best O(T) every that many steps */
+    int32_t reserved;
+} sbt_solve_params;
+
+void sbt_solve_params_default(sbt_solve_params *p);
+
+/* Host-memory result of sbt_solve. */
+typedef struct {
+    int8_t *T;            /* caller [n] or NULL: best agent's T = (1+sgn x)/2 */
+    double *agent_energy; /* caller [agents] or NULL: O(T) of every agent     */
+    double *trace;        /* caller [steps/energy_every] or NULL              */
+    float *x_final;       /* caller [n*agents] or NULL: final positions,      */
+    float *y_final;       /*   spin-major, agents contiguous (index i*M + m)  */
+    double energy;        /* out: O(T) of the best agent (Eq. 13, FP64)       */
+    double ising_offset;  /* out: C with O(T) = E_ising(s) + C                */
+    double c0;            /* out: the c0 used                                 */
+    int32_t best_agent;   /* out: argmin of O over agents, lowest on ties     */
+    int32_t kernel_used;  /* out: sbt_kernel that ran                         */
+    double elapsed_s;     /* out: device time of the solve (HIP events)       */
+} sbt_result;
+
+/* Solve one QUBO held in host memory: upload, run every step on the GPU,
+ * download.  Allocates and frees its device memory internally.
+ * Integration (Eq. 5-8 for BSB, Eq. 9-12 for DSB), for k = 0..K-1:
+ *   a_k = a0 k / K
+ *   F   = J x + h            (BSB)   or   J sgn(x) + h   (DSB), sgn(0) = +1
+ *   y  += dt (c0 F - (a0 - a_k) x);   x += dt a0 y
+ *   |x| > 1  ->  x = sgn(x), y = 0
+ * with J = -b/4, h = -(a/2 + rowsum(b)/4), starting from the Philox4x32-10
+ * draw x0, y0 in [-1/8, 1/8) (counter = (spin, agent, event, 0),
+ * key = seed).  Readout T = (1 + sgn x)/2 per agent; energies are FP64.
+ * Errors: SBT_EINVAL for an empty or malformed QUBO (non-finite values,
+ * unsorted or out-of-range columns, diagonal entries, asymmetric b) or
+ * invalid parameters; SBT_EDEVICE for HIP failures. */
+int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_params *p,
+              sbt_result *out);
+
+/* Device-resident form used when the QUBO already lives in HBM (the path
+ * the benchmark times).  All pointers are device pointers; nothing is
+ * allocated: scratch comes from `workspace`.  Contents of the QUBO are not
+ * validated (sbt_solve validates host data); sizes and parameters are. */
+typedef struct {
+    int32_t n;
+    int64_t nnz;
+    const double *a;       /* device [n]                                       */
+    const int32_t *row_ptr;/* device [n+1], row_ptr[0] = 0, row_ptr[n] = nnz  */
+    const int32_t *col;    /* device [nnz], ascending per row, no diagonal     */
+    const double *b;       /* device [nnz], symmetric                          */
+} sbt_dev_qubo;
+
+typedef struct {
+    int8_t *T;            /* device [n]: best agent's assignment              */
+    double *agent_energy; /* device [agents]                                  */
+    double *best_energy;  /* device [1]                                       */
+    int32_t *best_agent;  /* device [1]                                       */
+    double *scalars;      /* device [4] or NULL: c0, C, sum J, sum J^2        */
+    float *x_final;       /* device [n*agents] or NULL                        */
+    float *y_final;       /* device [n*agents] or NULL                        */
+    double *trace;        /* device [steps/energy_every] or NULL              */
+} sbt_dev_result;
+
+/* Bytes of device workspace sbt_solve_dev needs for this shape; 0 on
+ * invalid arguments (message in sbt_last_error). */
+size_t sbt_workspace_bytes(int32_t n, int64_t nnz, sbt_mode mode,
+                           const sbt_solve_params *p);
+
+/* Which kernel AUTO selects for this shape (sbt_kernel), or a negative
+ * status. */
+int sbt_select_kernel(int32_t n, int64_t nnz, int32_t max_row_nnz, sbt_mode mode,
+                      const sbt_solve_params *p);
+
+/* Run a solve on device data, enqueued on `stream` (a hipStream_t; NULL =
+ * the default stream).  Returns after enqueueing; results are ready when
+ * the stream reaches this point.  `max_row_nnz` is the largest row length
+ * of b (used to pick and size kernels).  Calls that share a workspace must
+ * not overlap. */
+int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
+                  const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
+                  const sbt_dev_result *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBTRACK_H */

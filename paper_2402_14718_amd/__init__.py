@@ -1,0 +1,230 @@
+"""Python binding of libsbtrack: MI355X simulated bifurcation for track QUBOs.
+
+Method: Okawa, Zeng, Tao, Yung, "Quantum-Annealing-Inspired Algorithms for
+Track Reconstruction at High-Energy Colliders" -- hits -> triplet QUBO
+(Eq. 13-17) -> ballistic / discrete simulated bifurcation (Eq. 5-12).
+
+Every function here only marshals arguments into the C ABI declared in
+include/sbtrack.h; all computation happens in the library (host C++ for
+the QUBO construction, HIP kernels for the solver).  PyTorch is used only
+to hold device memory and to name the HIP stream for ``solve_dev``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import (SBT_BSB, SBT_DSB, SBT_KERNEL_AUTO, SBT_KERNEL_RESIDENT, SBT_KERNEL_STREAM,
+                   SbtError, check, load)
+
+MODES = {"bsb": SBT_BSB, "dsb": SBT_DSB}
+KERNELS = {"auto": SBT_KERNEL_AUTO, "resident": SBT_KERNEL_RESIDENT, "stream": SBT_KERNEL_STREAM}
+KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
+
+HIT_DTYPE = np.dtype([("hit_id", "<i8"), ("layer", "<i4"), ("pad", "<i4"),
+                      ("x", "<f8"), ("y", "<f8"), ("z", "<f8")])
+
+
+@dataclasses.dataclass
+class Qubo:
+    """Host copy of an sbt_qubo (b symmetric CSR, ascending columns)."""
+    n: int
+    a: np.ndarray          # float64 [n]
+    row_ptr: np.ndarray    # int64 [n+1]
+    col: np.ndarray        # int32 [nnz]
+    b: np.ndarray          # float64 [nnz]
+    trip_hits: np.ndarray  # int64 [n, 3]
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.shape[0])
+
+    def max_row_nnz(self) -> int:
+        return int(np.diff(self.row_ptr).max()) if self.n else 0
+
+    def as_struct(self):
+        """A ctypes sbt_qubo viewing this object's arrays (kept alive by it)."""
+        self.a = np.ascontiguousarray(self.a, dtype=np.float64)
+        self.row_ptr = np.ascontiguousarray(self.row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(self.col, dtype=np.int32)
+        self.b = np.ascontiguousarray(self.b, dtype=np.float64)
+        self.trip_hits = np.ascontiguousarray(self.trip_hits, dtype=np.int64)
+        return _lib.SbtQubo(
+            self.n, self.nnz,
+            self.a.ctypes.data_as(C.POINTER(C.c_double)),
+            self.row_ptr.ctypes.data_as(C.POINTER(C.c_int64)),
+            self.col.ctypes.data_as(C.POINTER(C.c_int32)),
+            self.b.ctypes.data_as(C.POINTER(C.c_double)),
+            self.trip_hits.ctypes.data_as(C.POINTER(C.c_int64)))
+
+
+def version() -> str:
+    return load().sbt_version().decode()
+
+
+def build_params_default() -> _lib.SbtBuildParams:
+    p = _lib.SbtBuildParams()
+    load().sbt_build_params_default(C.byref(p))
+    return p
+
+
+def build_qubo(hits: np.ndarray, params: Optional[_lib.SbtBuildParams] = None) -> Qubo:
+    """sbt_build_qubo: hits (record array of HIT_DTYPE) -> Qubo."""
+    lib = load()
+    hits = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    out = C.POINTER(_lib.SbtQubo)()
+    check(lib.sbt_build_qubo(hits.ctypes.data_as(C.POINTER(_lib.SbtHit)), hits.shape[0],
+                             C.byref(params) if params is not None else None, C.byref(out)))
+    try:
+        q = out.contents
+        n, nnz = int(q.n), int(q.nnz)
+
+        def arr(ptr, count, dtype):
+            if count == 0:
+                return np.zeros(0, dtype=dtype)
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dtype, copy=True)
+
+        res = Qubo(n=n, a=arr(q.a, n, np.float64), row_ptr=arr(q.row_ptr, n + 1, np.int64),
+                   col=arr(q.col, nnz, np.int32), b=arr(q.b, nnz, np.float64),
+                   trip_hits=arr(q.trip_hits, 3 * n, np.int64).reshape(n, 3))
+    finally:
+        lib.sbt_qubo_free(out)
+    return res
+
+
+def energy(q: Qubo, T: np.ndarray) -> float:
+    """sbt_energy: FP64 O(T) of Eq. 13 on the host."""
+    T = np.ascontiguousarray(T, dtype=np.int8)
+    if T.shape != (q.n,):
+        raise ValueError("T must have shape (n,)")
+    s = q.as_struct()
+    e = C.c_double()
+    check(load().sbt_energy(C.byref(s), T.ctypes.data_as(C.POINTER(C.c_int8)), C.byref(e)))
+    return float(e.value)
+
+
+def solve_params(agents: int = 32, steps: int = 2000, dt: float = 1.0, a0: float = 1.0,
+                 c0: float = 0.0, seed: int = 0, event: int = 0, kernel: str = "auto",
+                 energy_every: int = 0) -> _lib.SbtSolveParams:
+    p = _lib.SbtSolveParams()
+    load().sbt_solve_params_default(C.byref(p))
+    p.agents, p.steps, p.dt, p.a0, p.c0 = agents, steps, dt, a0, c0
+    p.seed = seed & 0xFFFFFFFFFFFFFFFF
+    p.event = event
+    p.kernel = KERNELS[kernel]
+    p.energy_every = energy_every
+    return p
+
+
+def solve(q: Qubo, mode: str, agents: int = 32, steps: int = 2000, dt: float = 1.0,
+          a0: float = 1.0, c0: float = 0.0, seed: int = 0, event: int = 0,
+          kernel: str = "auto", energy_every: int = 0, want_state: bool = False,
+          want_trace: bool = False) -> dict:
+    """sbt_solve: host QUBO in, host results out (the library uploads,
+    solves on the GPU and downloads)."""
+    p = solve_params(agents, steps, dt, a0, c0, seed, event, kernel, energy_every)
+    s = q.as_struct()
+    T = np.zeros(q.n, dtype=np.int8)
+    E = np.zeros(agents, dtype=np.float64)
+    n_ck = steps // energy_every if energy_every > 0 else 0
+    trace = np.zeros(n_ck, dtype=np.float64) if want_trace else None
+    xf = np.zeros((q.n, agents), dtype=np.float32) if want_state else None
+    yf = np.zeros((q.n, agents), dtype=np.float32) if want_state else None
+    r = _lib.SbtResult()
+    r.T = T.ctypes.data_as(C.POINTER(C.c_int8))
+    r.agent_energy = E.ctypes.data_as(C.POINTER(C.c_double))
+    if trace is not None:
+        r.trace = trace.ctypes.data_as(C.POINTER(C.c_double))
+    if xf is not None:
+        r.x_final = xf.ctypes.data_as(C.POINTER(C.c_float))
+        r.y_final = yf.ctypes.data_as(C.POINTER(C.c_float))
+    check(load().sbt_solve(C.byref(s), MODES[mode], C.byref(p), C.byref(r)))
+    return {"T": T, "agent_energy": E, "energy": r.energy, "best_agent": int(r.best_agent),
+            "c0": r.c0, "ising_offset": r.ising_offset, "trace": trace, "x": xf, "y": yf,
+            "kernel": KERNEL_NAMES[int(r.kernel_used)], "elapsed_s": r.elapsed_s}
+
+
+def workspace_bytes(n: int, nnz: int, mode: str, params: _lib.SbtSolveParams) -> int:
+    v = load().sbt_workspace_bytes(n, nnz, MODES[mode], C.byref(params))
+    if v == 0:
+        raise SbtError(_lib.SBT_EINVAL, load().sbt_last_error().decode())
+    return int(v)
+
+
+def select_kernel(n: int, nnz: int, max_row_nnz: int, mode: str,
+                  params: _lib.SbtSolveParams) -> str:
+    rc = load().sbt_select_kernel(n, nnz, max_row_nnz, MODES[mode], C.byref(params))
+    if rc < 0:
+        check(rc)
+    return KERNEL_NAMES[rc]
+
+
+class DeviceSolver:
+    """sbt_solve_dev with every buffer held by torch on a HIP device.
+
+    The QUBO is uploaded once; ``run()`` enqueues a complete solve (Ising
+    preparation, initial draw, all SB steps, FP64 energies, best agent) on
+    the current torch stream and returns without synchronising."""
+
+    def __init__(self, q: Qubo, mode: str, params: _lib.SbtSolveParams, device="cuda",
+                 want_state: bool = False, want_trace: bool = False):
+        import torch
+        self.torch = torch
+        self.q = q
+        self.mode = mode
+        self.params = params
+        dev = torch.device(device)
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+        self.a = t(q.a, torch.float64)
+        self.row_ptr = t(q.row_ptr.astype(np.int32), torch.int32)
+        self.col = t(q.col if q.nnz else np.zeros(1, np.int32), torch.int32)
+        self.b = t(q.b if q.nnz else np.zeros(1), torch.float64)
+        M = params.agents
+        self.ws_bytes = workspace_bytes(q.n, q.nnz, mode, params)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.T = torch.empty(q.n, dtype=torch.int8, device=dev)
+        self.agent_energy = torch.empty(M, dtype=torch.float64, device=dev)
+        self.best_energy = torch.empty(1, dtype=torch.float64, device=dev)
+        self.best_agent = torch.empty(1, dtype=torch.int32, device=dev)
+        self.scalars = torch.empty(4, dtype=torch.float64, device=dev)
+        self.x = torch.empty((q.n, M), dtype=torch.float32, device=dev) if want_state else None
+        self.y = torch.empty((q.n, M), dtype=torch.float32, device=dev) if want_state else None
+        n_ck = params.steps // params.energy_every if params.energy_every > 0 else 0
+        self.trace = (torch.empty(n_ck, dtype=torch.float64, device=dev)
+                      if want_trace and n_ck > 0 else None)
+        self._dq = _lib.SbtDevQubo(q.n, q.nnz, self.a.data_ptr(), self.row_ptr.data_ptr(),
+                                   self.col.data_ptr(), self.b.data_ptr())
+        ptr = lambda x: x.data_ptr() if x is not None else None
+        self._dr = _lib.SbtDevResult(self.T.data_ptr(), self.agent_energy.data_ptr(),
+                                     self.best_energy.data_ptr(), self.best_agent.data_ptr(),
+                                     self.scalars.data_ptr(), ptr(self.x), ptr(self.y),
+                                     ptr(self.trace))
+        self.max_row = q.max_row_nnz()
+        self.kernel = select_kernel(q.n, q.nnz, self.max_row, mode, params)
+
+    def run(self, stream=None) -> None:
+        torch = self.torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        check(load().sbt_solve_dev(C.byref(self._dq), self.max_row, MODES[self.mode],
+                                   C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
+                                   self.ws_bytes, C.byref(self._dr), C.c_void_p(st.cuda_stream)))
+
+    def result(self) -> dict:
+        self.torch.cuda.synchronize()
+        return {"T": self.T.cpu().numpy(), "agent_energy": self.agent_energy.cpu().numpy(),
+                "energy": float(self.best_energy.item()),
+                "best_agent": int(self.best_agent.item()),
+                "c0": float(self.scalars[0].item()), "ising_offset": float(self.scalars[1].item()),
+                "x": None if self.x is None else self.x.cpu().numpy(),
+                "y": None if self.y is None else self.y.cpu().numpy(),
+                "trace": None if self.trace is None else self.trace.cpu().numpy(),
+                "kernel": self.kernel}
+
+
+__all__ = ["Qubo", "DeviceSolver", "build_qubo", "energy", "solve", "solve_params",
+           "workspace_bytes", "select_kernel", "build_params_default", "version", "load",
+           "SbtError", "HIT_DTYPE", "MODES", "KERNELS"]

@@ -1,0 +1,84 @@
+// Device-side building blocks shared by the SB kernels: the Philox draw of
+// the initial state and the fused symplectic-Euler update of one
+// (spin, agent) pair.  Both step kernels (resident and streaming) call the
+// same update with the same operation order, so they produce bit-identical
+// trajectories.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbt {
+
+enum : int { kBSB = 0, kDSB = 1 };
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
+// (hi0, lo0) = M0 c0, (hi1, lo1) = M1 c2, c = (hi1^c1^k0, lo1, hi0^c3^k1, lo0),
+// bumping the key by the Weyl constants between rounds.
+struct Philox4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+        const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Philox4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+// ((r >> 8) - 2^23) * 2^-26: uniform on [-1/8, 1/8), exact in FP32.
+__device__ __forceinline__ float philox_word_to_unit(uint32_t r) {
+    return static_cast<float>(static_cast<int32_t>(r >> 8) - (1 << 23)) * 0x1p-26f;
+}
+
+__device__ __forceinline__ float sgnf(float v) { return v >= 0.0f ? 1.0f : -1.0f; }
+
+// The coupling operand: x itself (bSB, Eq. 6) or sgn(x) (dSB, Eq. 10).
+template <int MODE>
+__device__ __forceinline__ float coupling_operand(float v) {
+    if constexpr (MODE == kDSB)
+        return sgnf(v);
+    else
+        return v;
+}
+
+// Schedule factor (a0 - a_k) with a_k = a0 k / K, evaluated in FP64.
+__device__ __forceinline__ float schedule_gap(double a0, int k, int K) {
+    return static_cast<float>(a0 - a0 * static_cast<double>(k) / static_cast<double>(K));
+}
+
+// One symplectic-Euler step of one oscillator (Eq. 5-6 / 9-10) followed by
+// the inelastic wall (Eq. 8 / 12):
+//   y += dt (c0 F - g x),  x += dt a0 y,  |x| > 1 -> x = sgn(x), y = 0.
+// F already holds sum_j J_ij op(x_j) + h_i.  Rounding is pinned with
+// explicit fused multiply-adds.
+__device__ __forceinline__ void sb_update(float &x, float &y, float F, float c0, float g,
+                                          float dt, float dta0) {
+    const float gx = g * x;
+    const float force = __builtin_fmaf(c0, F, -gx);
+    const float yn = __builtin_fmaf(dt, force, y);
+    const float xn = __builtin_fmaf(dta0, yn, x);
+    const bool wall = __builtin_fabsf(xn) > 1.0f;
+    x = wall ? sgnf(xn) : xn;
+    y = wall ? 0.0f : yn;
+}
+
+}  // namespace sbt

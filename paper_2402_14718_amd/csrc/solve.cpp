@@ -1,0 +1,431 @@
+// Host orchestration of the SB solver: argument checks, workspace layout,
+// kernel selection and the sbt_solve / sbt_solve_dev entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "common.hpp"
+#include "sb_kernels.hpp"
+#include "sbtrack.h"
+
+namespace {
+
+using sbt::fail;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t J = 0, h = 0, scal = 0, prep = 0, xa = 0, xb = 0, y = 0, epart = 0, etrace = 0;
+    size_t total = 0;
+    int n_ckpt = 0;
+};
+
+Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    const size_t nm = static_cast<size_t>(n) * static_cast<size_t>(M);
+    const size_t nblk_prep = (static_cast<size_t>(n) + 255) / 256;
+    const size_t nblk_e = (static_cast<size_t>(n) + sbt::kEnergyRows - 1) / sbt::kEnergyRows;
+    L.n_ckpt = every > 0 ? K / every : 0;
+    L.J = take(sizeof(float) * static_cast<size_t>(nnz));
+    L.h = take(sizeof(float) * n);
+    L.scal = take(sizeof(double) * 8);
+    L.prep = take(sizeof(double) * 4 * nblk_prep);
+    L.xa = take(sizeof(float) * nm);
+    L.xb = take(sizeof(float) * nm);
+    L.y = take(sizeof(float) * nm);
+    L.epart = take(sizeof(double) * nblk_e * M);
+    L.etrace = take(sizeof(double) * static_cast<size_t>(L.n_ckpt) * M);
+    L.total = off;
+    return L;
+}
+
+int check_params(const sbt_solve_params &p, const char *who) {
+    if (!(p.a0 > 0.0) || !std::isfinite(p.a0))
+        return fail(SBT_EINVAL, "%s: a0 must be finite and > 0", who);
+    if (!(p.dt > 0.0) || !std::isfinite(p.dt))
+        return fail(SBT_EINVAL, "%s: dt must be finite and > 0", who);
+    if (std::isinf(p.c0)) return fail(SBT_EINVAL, "%s: c0 is infinite", who);
+    if (p.agents < 1) return fail(SBT_EINVAL, "%s: agents must be >= 1", who);
+    if (p.steps < 1) return fail(SBT_EINVAL, "%s: steps must be >= 1", who);
+    if (p.energy_every < 0) return fail(SBT_EINVAL, "%s: energy_every must be >= 0", who);
+    if (p.event < 0) return fail(SBT_EINVAL, "%s: event must be >= 0", who);
+    if (p.kernel < SBT_KERNEL_AUTO || p.kernel > SBT_KERNEL_STREAM)
+        return fail(SBT_EINVAL, "%s: unknown kernel %d", who, p.kernel);
+    return SBT_OK;
+}
+
+int check_shape(int32_t n, int64_t nnz, int32_t M, const char *who) {
+    if (n < 1) return fail(SBT_EINVAL, "%s: n must be >= 1", who);
+    if (nnz < 0 || nnz > std::numeric_limits<int32_t>::max())
+        return fail(SBT_EINVAL, "%s: nnz %lld out of range", who, static_cast<long long>(nnz));
+    if (static_cast<int64_t>(n) * M > (int64_t(1) << 31) - 1)
+        return fail(SBT_EINVAL, "%s: n * agents exceeds 2^31 - 1", who);
+    return SBT_OK;
+}
+
+int device_lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return v;
+}
+
+// Resident-kernel shape for (n, nnz), or tpb = 0 if it does not fit.
+sbt::ResidentShape resident_shape(int32_t n, int64_t nnz, int lds_limit) {
+    sbt::ResidentShape S{0, 0, false, 0};
+    const int tpb = n <= 64 ? 64 : (n <= 1024 ? 256 : 1024);
+    const int need = (n + tpb - 1) / tpb;
+    int spt = 1;
+    while (spt < need) spt <<= 1;
+    if (spt > 16) return S;
+    const size_t red = 16 + sizeof(double) * (tpb / 64);
+    const size_t base = sizeof(float) * 2 * static_cast<size_t>(n) + red;
+    const size_t jbytes = sizeof(int) * (static_cast<size_t>(n) + 1) +
+                          (sizeof(int) + sizeof(float)) * static_cast<size_t>(nnz);
+    if (base > static_cast<size_t>(lds_limit)) return S;
+    S.tpb = tpb;
+    S.spt = spt;
+    S.jlds = base + jbytes <= static_cast<size_t>(lds_limit);
+    S.lds_bytes = S.jlds ? base + jbytes : base;
+    return S;
+}
+
+int pick_kernel(int32_t n, int64_t nnz, const sbt_solve_params &p, int lds_limit,
+                sbt::ResidentShape *shape) {
+    sbt::ResidentShape S = resident_shape(n, nnz, lds_limit);
+    if (shape) *shape = S;
+    if (p.kernel == SBT_KERNEL_STREAM) return SBT_KERNEL_STREAM;
+    if (p.kernel == SBT_KERNEL_RESIDENT) {
+        if (S.tpb == 0)
+            return fail(SBT_EUNSUPPORTED, "resident kernel: n = %d does not fit in LDS", n);
+        return SBT_KERNEL_RESIDENT;
+    }
+    return S.tpb != 0 ? SBT_KERNEL_RESIDENT : SBT_KERNEL_STREAM;
+}
+
+#define SBT_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(SBT_EDEVICE, "%s: %s failed: %s", who, #call, hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+extern "C" void sbt_solve_params_default(sbt_solve_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->a0 = 1.0;
+    p->dt = 1.0;
+    p->c0 = 0.0;
+    p->agents = 32;
+    p->steps = 2000;
+    p->seed = 0;
+    p->event = 0;
+    p->kernel = SBT_KERNEL_AUTO;
+    p->energy_every = 0;
+}
+
+extern "C" size_t sbt_workspace_bytes(int32_t n, int64_t nnz, sbt_mode mode,
+                                      const sbt_solve_params *p) {
+    sbt::clear_error();
+    if (!p) {
+        fail(SBT_EINVAL, "sbt_workspace_bytes: params is NULL");
+        return 0;
+    }
+    if (mode != SBT_BSB && mode != SBT_DSB) {
+        fail(SBT_EINVAL, "sbt_workspace_bytes: unknown mode");
+        return 0;
+    }
+    if (check_params(*p, "sbt_workspace_bytes") != SBT_OK) return 0;
+    if (check_shape(n, nnz, p->agents, "sbt_workspace_bytes") != SBT_OK) return 0;
+    return make_layout(n, nnz, p->agents, p->steps, p->energy_every).total;
+}
+
+extern "C" int sbt_select_kernel(int32_t n, int64_t nnz, int32_t max_row_nnz, sbt_mode mode,
+                                 const sbt_solve_params *p) {
+    sbt::clear_error();
+    (void)max_row_nnz;
+    if (!p) return fail(SBT_EINVAL, "sbt_select_kernel: params is NULL");
+    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "sbt_select_kernel: mode");
+    int rc = check_params(*p, "sbt_select_kernel");
+    if (rc) return rc;
+    rc = check_shape(n, nnz, p->agents, "sbt_select_kernel");
+    if (rc) return rc;
+    return pick_kernel(n, nnz, *p, device_lds_limit(), nullptr);
+}
+
+extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
+                             const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
+                             const sbt_dev_result *out, void *stream) {
+    const char *who = "sbt_solve_dev";
+    sbt::clear_error();
+    if (!q || !p || !out) return fail(SBT_EINVAL, "%s: NULL argument", who);
+    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "%s: unknown mode", who);
+    int rc = check_params(*p, who);
+    if (rc) return rc;
+    rc = check_shape(q->n, q->nnz, p->agents, who);
+    if (rc) return rc;
+    if (max_row_nnz < 0 || max_row_nnz > q->n)
+        return fail(SBT_EINVAL, "%s: max_row_nnz %d out of range", who, max_row_nnz);
+    if (!q->a || !q->row_ptr || (q->nnz > 0 && (!q->col || !q->b)))
+        return fail(SBT_EINVAL, "%s: QUBO pointer is NULL", who);
+    if (!out->T || !out->agent_energy || !out->best_energy || !out->best_agent)
+        return fail(SBT_EINVAL, "%s: result pointer is NULL", who);
+    const int32_t n = q->n, M = p->agents, K = p->steps;
+    const int nnz = static_cast<int>(q->nnz);
+    const Layout L = make_layout(n, q->nnz, M, K, p->energy_every);
+    if (!workspace || workspace_bytes < L.total)
+        return fail(SBT_EINVAL, "%s: workspace of %zu bytes is smaller than the %zu needed", who,
+                    workspace_bytes, L.total);
+    if (out->trace && L.n_ckpt == 0)
+        return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
+
+    sbt::ResidentShape shape;
+    const int kernel = pick_kernel(n, q->nnz, *p, device_lds_limit(), &shape);
+    if (kernel < 0) return kernel;
+
+    char *ws = static_cast<char *>(workspace);
+    float *dJ = reinterpret_cast<float *>(ws + L.J);
+    float *dh = reinterpret_cast<float *>(ws + L.h);
+    double *scal = reinterpret_cast<double *>(ws + L.scal);
+    double *prep = reinterpret_cast<double *>(ws + L.prep);
+    float *xa = reinterpret_cast<float *>(ws + L.xa);
+    float *xb = reinterpret_cast<float *>(ws + L.xb);
+    float *dy = reinterpret_cast<float *>(ws + L.y);
+    double *epart = reinterpret_cast<double *>(ws + L.epart);
+    double *etrace = reinterpret_cast<double *>(ws + L.etrace);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    const double c0_fixed = (std::isnan(p->c0) || p->c0 <= 0.0) ? 0.0 : p->c0;
+    SBT_HIP(sbt::launch_prep(n, q->a, q->row_ptr, q->col, q->b, dJ, dh, prep, scal, c0_fixed, st));
+    SBT_HIP(sbt::launch_init(n, M, p->seed, static_cast<uint32_t>(p->event), xa, dy, st));
+
+    const float dt = static_cast<float>(p->dt);
+    const float dta0 = static_cast<float>(p->dt * p->a0);
+    float *xfinal = xa;
+    if (kernel == SBT_KERNEL_RESIDENT) {
+        sbt::ResidentArgs A{};
+        A.n = n;
+        A.nnz = nnz;
+        A.M = M;
+        A.K = K;
+        A.ckpt_every = p->energy_every;
+        A.a0 = p->a0;
+        A.dt = dt;
+        A.dta0 = dta0;
+        A.row_ptr = q->row_ptr;
+        A.col = q->col;
+        A.J = dJ;
+        A.h = dh;
+        A.scal = scal;
+        A.a = q->a;
+        A.b = q->b;
+        A.x = xa;
+        A.y = dy;
+        A.etrace = etrace;
+        SBT_HIP(sbt::launch_resident(mode, A, shape, st));
+    } else {
+        sbt::StreamArgs A{};
+        A.n = n;
+        A.M = M;
+        A.K = K;
+        A.a0 = p->a0;
+        A.dt = dt;
+        A.dta0 = dta0;
+        A.row_ptr = q->row_ptr;
+        A.col = q->col;
+        A.J = dJ;
+        A.h = dh;
+        A.scal = scal;
+        A.y = dy;
+        float *xin = xa, *xout = xb;
+        int ck = 0;
+        for (int k = 0; k < K; ++k) {
+            SBT_HIP(sbt::launch_stream_step(mode, A, k, xin, xout, st));
+            std::swap(xin, xout);
+            if (p->energy_every > 0 && (k + 1) % p->energy_every == 0) {
+                SBT_HIP(sbt::launch_energy(n, M, q->a, q->row_ptr, q->col, q->b, xin, epart,
+                                           etrace + static_cast<size_t>(ck) * M, st));
+                ++ck;
+            }
+        }
+        xfinal = xin;
+    }
+    SBT_HIP(sbt::launch_energy(n, M, q->a, q->row_ptr, q->col, q->b, xfinal, epart,
+                               out->agent_energy, st));
+    SBT_HIP(sbt::launch_select_best(n, M, out->agent_energy, xfinal, out->best_energy,
+                                    out->best_agent, out->T, st));
+    if (out->trace) SBT_HIP(sbt::launch_trace_reduce(L.n_ckpt, M, etrace, out->trace, st));
+    const size_t nm = static_cast<size_t>(n) * M;
+    if (out->x_final)
+        SBT_HIP(hipMemcpyAsync(out->x_final, xfinal, nm * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (out->y_final)
+        SBT_HIP(hipMemcpyAsync(out->y_final, dy, nm * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (out->scalars)
+        SBT_HIP(hipMemcpyAsync(out->scalars, scal, 4 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return SBT_OK;
+}
+
+// ----------------------------------------------------------- host solve
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct HostStream {
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~HostStream() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+int validate_host_qubo(const sbt_qubo *q, int32_t *max_row) {
+    const char *who = "sbt_solve";
+    if (!q) return fail(SBT_EINVAL, "%s: qubo is NULL", who);
+    if (q->n < 1) return fail(SBT_EINVAL, "%s: empty QUBO (n = %d)", who, q->n);
+    if (!q->a || !q->row_ptr || (q->nnz > 0 && (!q->col || !q->b)))
+        return fail(SBT_EINVAL, "%s: QUBO array is NULL", who);
+    if (q->row_ptr[0] != 0 || q->row_ptr[q->n] != q->nnz)
+        return fail(SBT_EINVAL, "%s: row_ptr does not span [0, nnz]", who);
+    int32_t mr = 0;
+    for (int32_t i = 0; i < q->n; ++i) {
+        if (!std::isfinite(q->a[i])) return fail(SBT_EINVAL, "%s: a[%d] is not finite", who, i);
+        const int64_t lo = q->row_ptr[i], hi = q->row_ptr[i + 1];
+        if (hi < lo) return fail(SBT_EINVAL, "%s: row_ptr decreases at row %d", who, i);
+        mr = std::max<int32_t>(mr, static_cast<int32_t>(hi - lo));
+        for (int64_t e = lo; e < hi; ++e) {
+            const int32_t j = q->col[e];
+            if (j < 0 || j >= q->n) return fail(SBT_EINVAL, "%s: column %d out of range", who, j);
+            if (j == i) return fail(SBT_EINVAL, "%s: diagonal entry in row %d", who, i);
+            if (e > lo && q->col[e - 1] >= j)
+                return fail(SBT_EINVAL, "%s: columns of row %d not ascending", who, i);
+            if (!std::isfinite(q->b[e])) return fail(SBT_EINVAL, "%s: b is not finite", who);
+            // symmetry: b_ji must equal b_ij
+            const int32_t *c0 = q->col + q->row_ptr[j];
+            const int32_t *c1 = q->col + q->row_ptr[j + 1];
+            const int32_t *f = std::lower_bound(c0, c1, i);
+            if (f == c1 || *f != i || q->b[q->row_ptr[j] + (f - c0)] != q->b[e])
+                return fail(SBT_EINVAL, "%s: b is not symmetric at (%d, %d)", who, i, j);
+        }
+    }
+    *max_row = mr;
+    return SBT_OK;
+}
+
+}  // namespace
+
+extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_params *pp,
+                         sbt_result *out) {
+    const char *who = "sbt_solve";
+    sbt::clear_error();
+    if (!out) return fail(SBT_EINVAL, "%s: result is NULL", who);
+    sbt_solve_params p;
+    if (pp)
+        p = *pp;
+    else
+        sbt_solve_params_default(&p);
+    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "%s: unknown mode", who);
+    int rc = check_params(p, who);
+    if (rc) return rc;
+    int32_t max_row = 0;
+    rc = validate_host_qubo(q, &max_row);
+    if (rc) return rc;
+    rc = check_shape(q->n, q->nnz, p.agents, who);
+    if (rc) return rc;
+    const int32_t n = q->n, M = p.agents;
+    const int64_t nnz = q->nnz;
+    const int n_ckpt = p.energy_every > 0 ? p.steps / p.energy_every : 0;
+    if (out->trace && n_ckpt == 0)
+        return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
+
+    std::vector<int32_t> rp32(n + 1);
+    for (int32_t i = 0; i <= n; ++i) rp32[i] = static_cast<int32_t>(q->row_ptr[i]);
+    const size_t ws_bytes = make_layout(n, nnz, M, p.steps, p.energy_every).total;
+    const size_t nm = static_cast<size_t>(n) * M;
+
+    DevBuf da, drp, dcol, db, dws, dT, dE, dbe, dbm, dsc, dx, dy, dtr;
+    auto alloc = [&](DevBuf &b, size_t bytes) {
+        return hipMalloc(&b.p, std::max<size_t>(bytes, 1));
+    };
+    if (alloc(da, sizeof(double) * n) != hipSuccess || alloc(drp, sizeof(int32_t) * (n + 1)) ||
+        alloc(dcol, sizeof(int32_t) * nnz) || alloc(db, sizeof(double) * nnz) ||
+        alloc(dws, ws_bytes) || alloc(dT, n) || alloc(dE, sizeof(double) * M) ||
+        alloc(dbe, sizeof(double)) || alloc(dbm, sizeof(int32_t)) || alloc(dsc, 4 * sizeof(double)) ||
+        (out->x_final && alloc(dx, sizeof(float) * nm)) ||
+        (out->y_final && alloc(dy, sizeof(float) * nm)) ||
+        (out->trace && alloc(dtr, sizeof(double) * n_ckpt)))
+        return fail(SBT_ENOMEM, "%s: device allocation failed", who);
+    HostStream hs;
+    SBT_HIP(hipStreamCreateWithFlags(&hs.s, hipStreamNonBlocking));
+    SBT_HIP(hipEventCreate(&hs.e0));
+    SBT_HIP(hipEventCreate(&hs.e1));
+    SBT_HIP(hipMemcpyAsync(da.p, q->a, sizeof(double) * n, hipMemcpyHostToDevice, hs.s));
+    SBT_HIP(hipMemcpyAsync(drp.p, rp32.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, hs.s));
+    if (nnz > 0) {
+        SBT_HIP(hipMemcpyAsync(dcol.p, q->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, hs.s));
+        SBT_HIP(hipMemcpyAsync(db.p, q->b, sizeof(double) * nnz, hipMemcpyHostToDevice, hs.s));
+    }
+    sbt_dev_qubo dq{n, nnz, static_cast<const double *>(da.p), static_cast<const int32_t *>(drp.p),
+                    static_cast<const int32_t *>(dcol.p), static_cast<const double *>(db.p)};
+    sbt_dev_result dr{};
+    dr.T = static_cast<int8_t *>(dT.p);
+    dr.agent_energy = static_cast<double *>(dE.p);
+    dr.best_energy = static_cast<double *>(dbe.p);
+    dr.best_agent = static_cast<int32_t *>(dbm.p);
+    dr.scalars = static_cast<double *>(dsc.p);
+    dr.x_final = static_cast<float *>(dx.p);
+    dr.y_final = static_cast<float *>(dy.p);
+    dr.trace = static_cast<double *>(dtr.p);
+    const int kernel = pick_kernel(n, nnz, p, device_lds_limit(), nullptr);
+    if (kernel < 0) return kernel;
+    SBT_HIP(hipEventRecord(hs.e0, hs.s));
+    rc = sbt_solve_dev(&dq, max_row, mode, &p, dws.p, ws_bytes, &dr, hs.s);
+    if (rc) return rc;
+    SBT_HIP(hipEventRecord(hs.e1, hs.s));
+    double scal[4];
+    int32_t bm = 0;
+    SBT_HIP(hipMemcpyAsync(&out->energy, dbe.p, sizeof(double), hipMemcpyDeviceToHost, hs.s));
+    SBT_HIP(hipMemcpyAsync(&bm, dbm.p, sizeof(int32_t), hipMemcpyDeviceToHost, hs.s));
+    SBT_HIP(hipMemcpyAsync(scal, dsc.p, sizeof scal, hipMemcpyDeviceToHost, hs.s));
+    if (out->T) SBT_HIP(hipMemcpyAsync(out->T, dT.p, n, hipMemcpyDeviceToHost, hs.s));
+    if (out->agent_energy)
+        SBT_HIP(hipMemcpyAsync(out->agent_energy, dE.p, sizeof(double) * M, hipMemcpyDeviceToHost, hs.s));
+    if (out->x_final)
+        SBT_HIP(hipMemcpyAsync(out->x_final, dx.p, sizeof(float) * nm, hipMemcpyDeviceToHost, hs.s));
+    if (out->y_final)
+        SBT_HIP(hipMemcpyAsync(out->y_final, dy.p, sizeof(float) * nm, hipMemcpyDeviceToHost, hs.s));
+    if (out->trace)
+        SBT_HIP(hipMemcpyAsync(out->trace, dtr.p, sizeof(double) * n_ckpt, hipMemcpyDeviceToHost, hs.s));
+    SBT_HIP(hipStreamSynchronize(hs.s));
+    float ms = 0.0f;
+    SBT_HIP(hipEventElapsedTime(&ms, hs.e0, hs.e1));
+    out->best_agent = bm;
+    out->c0 = scal[0];
+    out->ising_offset = scal[1];
+    out->kernel_used = kernel;
+    out->elapsed_s = 1e-3 * ms;
+    return SBT_OK;
+}

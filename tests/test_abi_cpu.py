@@ -1,0 +1,143 @@
+"""C-ABI checks that need no GPU: symbols, host QUBO construction parity
+with the oracle (bit-exact), host FP64 energy, and argument validation."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import trackgen as tg
+from oracle import energy as oenergy
+from oracle import qubo as oqubo
+
+sbt = pytest.importorskip("paper_2402_14718_amd")
+from paper_2402_14718_amd import _lib  # noqa: E402
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sbtrack.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sbt_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = sbt.load()
+    names = _declared_functions()
+    assert "sbt_solve" in names and "sbt_build_qubo" in names and "sbt_solve_dev" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(n for n, _, _ in _lib.EXPORTS) == set(names)
+
+
+def test_struct_sizes_match_c_layout():
+    assert C.sizeof(_lib.SbtHit) == 40
+    assert C.sizeof(_lib.SbtBuildParams) == 6 * 8 + 2 * 4 + 4 * 8
+    assert C.sizeof(_lib.SbtSolveParams) == 3 * 8 + 2 * 4 + 8 + 4 * 4
+    assert sbt.HIT_DTYPE.itemsize == C.sizeof(_lib.SbtHit)
+
+
+def test_default_params_match_oracle():
+    p = sbt.build_params_default()
+    o = oqubo.BuildParams()
+    assert p.dphi_tan == o.dphi_tan and p.dtheta_tan == o.dtheta_tan
+    assert (p.curv_max, p.dcurv_max, p.s_min) == (o.curv_max, o.dcurv_max, o.s_min)
+    assert (p.max_holes, p.min_track_hits) == (o.max_holes, o.min_track_hits)
+    assert (p.alpha, p.beta, p.gamma_, p.lambda_) == (o.alpha, o.beta, o.gamma, o.lam)
+
+
+@pytest.mark.parametrize("spec,seed", [
+    (tg.tiny_spec(), 1), (tg.tiny_spec(), 7), (tg.plain_spec(), 100), (tg.plain_spec(), 103),
+    (tg.plain_spec(120), 5), (tg.EventSpec(n_particles=300, eta_max=0.6, noise_frac=0.3), 9),
+])
+def test_build_qubo_bit_exact_with_oracle(spec, seed):
+    ev = tg.generate(spec, seed)
+    q = sbt.build_qubo(ev.hits_struct())
+    o = oqubo.build_event(ev)
+    assert q.n == o.n
+    assert np.array_equal(q.trip_hits, o.trip_hits)
+    assert np.array_equal(q.row_ptr, o.b.indptr)
+    assert np.array_equal(q.col, o.b.indices)
+    assert np.array_equal(q.b, o.b.data)
+    assert np.array_equal(q.a, o.a)
+
+
+def test_build_qubo_orders_by_hit_id_not_input_order():
+    ev = tg.generate(tg.plain_spec(80), 2)
+    hits = ev.hits_struct()
+    perm = np.random.default_rng(0).permutation(hits.shape[0])
+    q1 = sbt.build_qubo(hits)
+    q2 = sbt.build_qubo(hits[perm])
+    assert np.array_equal(q1.trip_hits, q2.trip_hits)
+    assert np.array_equal(q1.b, q2.b) and np.array_equal(q1.a, q2.a)
+
+
+def test_build_qubo_params_and_edge_cases():
+    ev = tg.generate(tg.tiny_spec(), 3)
+    hits = ev.hits_struct()
+    p = sbt.build_params_default()
+    p.min_track_hits = 5                      # four layers cannot make five hits
+    assert sbt.build_qubo(hits, p).n == 0
+    p.min_track_hits = 6
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.build_qubo(hits, p)
+    assert e.value.code == _lib.SBT_EUNSUPPORTED
+    assert sbt.build_qubo(hits[:0]).n == 0       # no hits: empty QUBO
+    bad = hits.copy()
+    bad["x"][3] = np.nan
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.build_qubo(bad)
+    assert e.value.code == _lib.SBT_EINVAL
+    dup = hits.copy()
+    dup["hit_id"][5] = dup["hit_id"][4]
+    with pytest.raises(sbt.SbtError):
+        sbt.build_qubo(dup)
+
+
+def test_host_energy_matches_oracle():
+    ev = tg.generate(tg.plain_spec(), 101)
+    q = sbt.build_qubo(ev.hits_struct())
+    o = oqubo.build_event(ev)
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        T = (rng.random(q.n) < 0.5).astype(np.int8)
+        e_lib = sbt.energy(q, T)
+        e_or = float(oenergy.qubo_energy(o.a, o.b, T))
+        assert abs(e_lib - e_or) <= 1e-12 * max(1.0, abs(e_or))
+    with pytest.raises(sbt.SbtError):
+        sbt.energy(q, np.full(q.n, 2, dtype=np.int8))
+
+
+def test_workspace_and_param_validation():
+    p = sbt.solve_params(agents=256, steps=5000)
+    ws = sbt.workspace_bytes(1500, 3000, "bsb", p)
+    assert ws >= 3 * 1500 * 256 * 4                 # x ping-pong + y
+    for bad in [dict(agents=0), dict(steps=0), dict(dt=0.0), dict(a0=-1.0), dict(energy_every=-1)]:
+        kw = dict(agents=8, steps=10)
+        kw.update(bad)
+        with pytest.raises(sbt.SbtError):
+            sbt.workspace_bytes(100, 200, "dsb", sbt.solve_params(**kw))
+    with pytest.raises(sbt.SbtError):
+        sbt.workspace_bytes(0, 0, "dsb", sbt.solve_params())
+    with pytest.raises(sbt.SbtError):
+        sbt.workspace_bytes(1 << 20, 0, "dsb", sbt.solve_params(agents=4096))
+
+
+def test_solve_rejects_malformed_qubo_before_touching_a_device():
+    ev = tg.generate(tg.plain_spec(60), 1)
+    q = sbt.build_qubo(ev.hits_struct())
+    asym = sbt.Qubo(q.n, q.a.copy(), q.row_ptr.copy(), q.col.copy(), q.b.copy(), q.trip_hits)
+    asym.b[0] += 0.5
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve(asym, "dsb", agents=4, steps=5)
+    assert e.value.code == _lib.SBT_EINVAL and "symmetric" in str(e.value)
+    empty = sbt.Qubo(0, np.zeros(0), np.zeros(1, np.int64), np.zeros(0, np.int32),
+                     np.zeros(0), np.zeros((0, 3), np.int64))
+    with pytest.raises(sbt.SbtError):
+        sbt.solve(empty, "bsb", agents=4, steps=5)
+    nanq = sbt.Qubo(q.n, q.a.copy(), q.row_ptr, q.col, q.b, q.trip_hits)
+    nanq.a[0] = np.inf
+    with pytest.raises(sbt.SbtError):
+        sbt.solve(nanq, "bsb", agents=4, steps=5)
