@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Simulated-bifurcation throughput on one MI355X.
+
+Workload ("plain"): one synthetic barrel event -- 10 layers at
+r = 32 ... 1020 mm, 2 T, 200 helical particles (pT log-uniform 0.5-20 GeV,
+|eta| < 1.5) plus 10% noise hits, event seed 100 -- turned into the triplet
+QUBO by the library's host builder (not timed, as in the paper).  One bench
+step is a complete solve of that QUBO in both SB forms, bSB and dSB, each
+with 256 agents x 5000 symplectic-Euler steps: Ising preparation, Philox
+start, all steps, FP64 energies of every agent and best-agent selection,
+all on the GPU with the QUBO already resident in HBM.
+
+Prints one JSON line with spin-updates/s (N * agents * steps * 2 forms per
+bench step), the roofline position of the SB step kernel (timed live with
+HIP events on its stream), the time to reach the FP64 oracle's best energy
+within 0.5%, and the oracle timed on the host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MI355X_FP32_VECTOR_TFLOPS = 157.3
+MI355X_HBM_GBS = 8000.0
+EVENT_SEED = 100
+AGENTS = 256
+SB_STEPS = 5000
+SOLVER_SEED = 0
+TTT_EVERY = 50
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def step_flops(n, nnz, agents, steps):
+    """Useful FP32 flops of the SB steps: an FMA per stored coupling and
+    8 per spin update (F + h, g x, c0 F - g x, y + dt f, x + dt a0 y)."""
+    return float(steps) * agents * (2.0 * nnz + 8.0 * n)
+
+
+def step_bytes(n, nnz, agents, steps):
+    """Algorithmic bytes of the SB steps if state streamed through HBM:
+    FP32 x, y read and written per spin update plus J (CSR FP32) per step."""
+    return float(steps) * (16.0 * n * agents + 8.0 * nnz + 4.0 * (n + 1))
+
+
+def cpu_baseline(q, n_target_s=12.0):
+    """The FP64 oracle integrator on the host, both forms, all 256 agents,
+    for a bounded number of steps; returned as spin-updates/s."""
+    import numpy as np
+    import scipy.sparse as sp
+    from threadpoolctl import threadpool_limits
+
+    from oracle import ising as oising
+    from oracle import sb as osb
+
+    b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
+    isg = oising.from_qubo(q.a, b)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for mode in ("bsb", "dsb"):
+            osb.run(isg.J, isg.h, isg.c0, mode, AGENTS, 20, seed=SOLVER_SEED)
+        per_step = (time.perf_counter() - t0) / 40.0
+        k = max(20, int(n_target_s / (2.0 * per_step)))
+        t0 = time.perf_counter()
+        for mode in ("bsb", "dsb"):
+            osb.run(isg.J, isg.h, isg.c0, mode, AGENTS, k, seed=SOLVER_SEED)
+        dt = time.perf_counter() - t0
+    ups = 2.0 * q.n * AGENTS * k / dt
+    return {"value": ups, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FP64 bSB+dSB, {AGENTS} agents x {k} steps on the same event "
+                      f"({dt:.1f} s, one thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10, help="timed bench steps")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ttt", action="store_true")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; the solver shards over agents with "
+              "no per-step communication, so --gpus N > 1 is not run here", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2402_14718_amd as sbt
+    import trackgen as tg
+
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        sys.exit(1)
+    log("building the event QUBO on the host")
+    ev = tg.generate(tg.plain_spec(), EVENT_SEED)
+    q = sbt.build_qubo(ev.hits_struct())
+    log(f"N={q.n} nnz={q.nnz} agents={AGENTS} sb_steps={SB_STEPS}")
+
+    solvers = []
+    for mode in ("bsb", "dsb"):
+        p = sbt.solve_params(agents=AGENTS, steps=SB_STEPS, seed=SOLVER_SEED, kernel=args.kernel)
+        solvers.append(sbt.DeviceSolver(q, mode, p))
+    kernel = solvers[0].kernel
+    stream = torch.cuda.current_stream()
+
+    def event_pair():
+        b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.record(stream)   # materialise the HIP events so their handles exist
+        e.record(stream)
+        return b, e
+
+    for _ in range(args.warmup):
+        for s in solvers:
+            s.run()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps), kernel={kernel}")
+
+    pairs = [[event_pair() for _ in solvers] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        for s, (b, e) in zip(solvers, pairs[k]):
+            s._dr.step_begin = b.cuda_event
+            s._dr.step_end = e.cuda_event
+            s.run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_ms = [b.elapsed_time(e) for row in pairs for (b, e) in row]
+    for s in solvers:
+        s._dr.step_begin = s._dr.step_end = None
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+
+    updates = 2.0 * q.n * AGENTS * SB_STEPS * args.steps
+    value = updates / elapsed
+    launches_per_solve = 1 if kernel == "resident" else SB_STEPS
+    phase_s = float(np.mean(step_ms)) * 1e-3
+    launch_s = phase_s / launches_per_solve
+    flops = step_flops(q.n, q.nnz, AGENTS, SB_STEPS) / launches_per_solve
+    bytes_ = step_bytes(q.n, q.nnz, AGENTS, SB_STEPS) / launches_per_solve
+    if kernel == "resident":
+        achieved = flops / launch_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": MI355X_FP32_VECTOR_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_VECTOR_TFLOPS,
+                "traffic": None, "kernel": "sb_resident",
+                "launch_ms": launch_s * 1e3,
+                "effective_state_GBs": bytes_ / launch_s / 1e9}
+    else:
+        achieved = bytes_ / launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / MI355X_HBM_GBS, "traffic": None, "kernel": "sb_stream",
+                "launch_ms": launch_s * 1e3}
+
+    result = {
+        "metric": "SB spin-updates/s + time-to-best-energy, BF16/FP8 batched vs plain FP32 SB",
+        "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain: 10-layer barrel, 200 particles + 10% noise, event seed 100; "
+                               "bSB and dSB, 256 agents x 5000 steps, CSR FP32",
+                   "n": q.n, "nnz": q.nnz, "agents": AGENTS, "sb_steps": SB_STEPS,
+                   "forms": ["bsb", "dsb"], "kernel": kernel},
+        "roofline": roof,
+    }
+
+    if not args.no_ttt:
+        gold = os.path.join(ROOT, "tests", "golden", "oracle_best_plain.json")
+        with open(gold) as f:
+            ref = json.load(f)
+        ttt = {"target": "oracle best O(T) + 0.5% |O|, checkpoints every 50 steps (timed)"}
+        for mode in ("bsb", "dsb"):
+            e_star = ref["modes"][mode]["best"]
+            target = e_star + 0.005 * abs(e_star)
+            p = sbt.solve_params(agents=AGENTS, steps=SB_STEPS, seed=SOLVER_SEED,
+                                 kernel=args.kernel, energy_every=TTT_EVERY)
+            ds = sbt.DeviceSolver(q, mode, p, want_trace=True)
+            ds.run()
+            torch.cuda.synchronize()
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ds.run()
+            torch.cuda.synchronize()
+            t_solve = (time.perf_counter() - t0) / reps
+            res = ds.result()
+            hit = np.nonzero(res["trace"] <= target)[0]
+            entry = {"oracle_best": e_star, "gpu_best": res["energy"],
+                     "gap_to_oracle": res["energy"] - e_star, "solve_s": t_solve}
+            if hit.size:
+                frac = (hit[0] + 1) * TTT_EVERY / SB_STEPS
+                entry["ttt_s"] = t_solve * frac
+                entry["ttt_step"] = int((hit[0] + 1) * TTT_EVERY)
+            else:
+                entry["ttt_s"] = None
+            ttt[mode] = entry
+        result["time_to_target"] = ttt
+        log("time-to-target done")
+
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host (bounded sample)")
+        result["cpu_baseline"] = cpu_baseline(q)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

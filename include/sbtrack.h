@@ -126,7 +126,7 @@ typedef enum {
 /* Solver parameters (section "Simulated Bifurcation" and Results: a0 = dt = 1,
  * fixed c0).  sbt_solve_params_default() fills a0 = dt = 1, c0 = auto,
  * agents = 32, steps = 2000, seed = 0, event = 0, kernel = AUTO,
- * energy_every = 0. */
+ * energy_every = 0, tpb = 0. */
 typedef struct {
     double a0;            /* a0 > 0                                          */
     double dt;            /* time step > 0                                   */
@@ -138,7 +138,8 @@ typedef struct {
     int32_t event;        /* Philox counter word 2 (batch position)          */
     int32_t kernel;       /* sbt_kernel                                      */
     int32_t energy_every; /* > 0: record the best O(T) every that many steps */
-    int32_t reserved;
+    int32_t tpb;          /* resident kernel threads per workgroup (64, 256,  */
+                          /* 512, 1024); 0 = chosen from the shape           */
 } sbt_solve_params;
 
 void sbt_solve_params_default(sbt_solve_params *p);
@@ -196,6 +197,9 @@ typedef struct {
     float *x_final;       /* device [n*agents] or NULL                        */
     float *y_final;       /* device [n*agents] or NULL                        */
     double *trace;        /* device [steps/energy_every] or NULL              */
+    void *step_begin;     /* hipEvent_t or NULL: recorded on the stream just  */
+    void *step_end;       /*   before the first and after the last SB-step    */
+                          /*   kernel, to time the step phase                 */
 } sbt_dev_result;
 
 /* Bytes of device workspace sbt_solve_dev needs for this shape; 0 on

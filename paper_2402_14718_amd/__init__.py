@@ -109,7 +109,7 @@ def energy(q: Qubo, T: np.ndarray) -> float:
 
 def solve_params(agents: int = 32, steps: int = 2000, dt: float = 1.0, a0: float = 1.0,
                  c0: float = 0.0, seed: int = 0, event: int = 0, kernel: str = "auto",
-                 energy_every: int = 0) -> _lib.SbtSolveParams:
+                 energy_every: int = 0, tpb: int = 0) -> _lib.SbtSolveParams:
     p = _lib.SbtSolveParams()
     load().sbt_solve_params_default(C.byref(p))
     p.agents, p.steps, p.dt, p.a0, p.c0 = agents, steps, dt, a0, c0
@@ -117,16 +117,17 @@ def solve_params(agents: int = 32, steps: int = 2000, dt: float = 1.0, a0: float
     p.event = event
     p.kernel = KERNELS[kernel]
     p.energy_every = energy_every
+    p.tpb = tpb
     return p
 
 
 def solve(q: Qubo, mode: str, agents: int = 32, steps: int = 2000, dt: float = 1.0,
           a0: float = 1.0, c0: float = 0.0, seed: int = 0, event: int = 0,
           kernel: str = "auto", energy_every: int = 0, want_state: bool = False,
-          want_trace: bool = False) -> dict:
+          want_trace: bool = False, tpb: int = 0) -> dict:
     """sbt_solve: host QUBO in, host results out (the library uploads,
     solves on the GPU and downloads)."""
-    p = solve_params(agents, steps, dt, a0, c0, seed, event, kernel, energy_every)
+    p = solve_params(agents, steps, dt, a0, c0, seed, event, kernel, energy_every, tpb)
     s = q.as_struct()
     T = np.zeros(q.n, dtype=np.int8)
     E = np.zeros(agents, dtype=np.float64)

@@ -48,7 +48,7 @@ class SbtSolveParams(C.Structure):
     _fields_ = [("a0", C.c_double), ("dt", C.c_double), ("c0", C.c_double),
                 ("agents", C.c_int32), ("steps", C.c_int32), ("seed", C.c_uint64),
                 ("event", C.c_int32), ("kernel", C.c_int32), ("energy_every", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("tpb", C.c_int32)]
 
 
 class SbtResult(C.Structure):
@@ -67,7 +67,8 @@ class SbtDevQubo(C.Structure):
 class SbtDevResult(C.Structure):
     _fields_ = [("T", C.c_void_p), ("agent_energy", C.c_void_p), ("best_energy", C.c_void_p),
                 ("best_agent", C.c_void_p), ("scalars", C.c_void_p), ("x_final", C.c_void_p),
-                ("y_final", C.c_void_p), ("trace", C.c_void_p)]
+                ("y_final", C.c_void_p), ("trace", C.c_void_p), ("step_begin", C.c_void_p),
+                ("step_end", C.c_void_p)]
 
 
 # (name, restype, argtypes) of every exported function, as in sbtrack.h

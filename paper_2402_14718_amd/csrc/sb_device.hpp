@@ -81,4 +81,46 @@ __device__ __forceinline__ void sb_update(float &x, float &y, float F, float c0,
     y = wall ? 0.0f : yn;
 }
 
+// ------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Deterministic sum over the workgroup of one double per thread (fixed
+// tree order); the result is valid in thread 0.  `red` holds one double
+// per wave.  Every thread of the workgroup must call it.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        const int nw = static_cast<int>(blockDim.x + 63) >> 6;
+        for (int w = 0; w < nw; ++w) s += red[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+// Launch with a dynamic-LDS request beyond the default limit.
+template <class F, class... Args>
+hipError_t launch_with_lds(F fn, dim3 grid, dim3 block, size_t lds, hipStream_t st, Args... args) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    fn<<<grid, block, lds, st>>>(args...);
+    return hipGetLastError();
+}
+
 }  // namespace sbt

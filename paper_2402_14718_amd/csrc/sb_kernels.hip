@@ -29,30 +29,6 @@
 
 namespace sbt {
 
-// ---------------------------------------------------------------- helpers
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Deterministic block sum of one double per thread (fixed tree order).
-template <int TPB>
-__device__ __forceinline__ double block_sum(double v, double *red) {
-    v = wave_sum(v);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int w = 0; w < TPB / 64; ++w) s += red[w];
-    }
-    __syncthreads();
-    return s;  // valid in thread 0
-}
-
 // ------------------------------------------------------------ Ising prep
 
 // One thread per row: J = -b/4 in FP32, h_i = -(a_i/2 + 1/4 sum_j b_ij),
@@ -81,10 +57,10 @@ __global__ __launch_bounds__(256) void prep_ising_rows(int n, const double *__re
         h[i] = static_cast<float>(-(0.5 * a[i] + 0.25 * rs));
         sa = a[i];
     }
-    const double t0 = block_sum<256>(sj, red);
-    const double t1 = block_sum<256>(sj2, red);
-    const double t2 = block_sum<256>(sup, red);
-    const double t3 = block_sum<256>(sa, red);
+    const double t0 = block_sum(sj, red);
+    const double t1 = block_sum(sj2, red);
+    const double t2 = block_sum(sup, red);
+    const double t3 = block_sum(sa, red);
     if (threadIdx.x == 0) {
         part[4 * blockIdx.x + 0] = t0;
         part[4 * blockIdx.x + 1] = t1;
@@ -105,7 +81,7 @@ __global__ __launch_bounds__(256) void prep_finalize(int n, int nblk, double c0_
     for (int k = threadIdx.x; k < nblk; k += 256)
         for (int c = 0; c < 4; ++c) v[c] += part[4 * k + c];
     double t[4];
-    for (int c = 0; c < 4; ++c) t[c] = block_sum<256>(v[c], red);
+    for (int c = 0; c < 4; ++c) t[c] = block_sum(v[c], red);
     if (threadIdx.x == 0) {
         const double n2 = static_cast<double>(n) * static_cast<double>(n);
         const double mean = t[0] / n2;
@@ -137,6 +113,15 @@ __global__ __launch_bounds__(256) void init_state(int n, int M, uint32_t k0, uin
     const Philox4 r = philox4x32_10(i, m, event, 0u, k0, k1);
     x[idx] = philox_word_to_unit(r.v[0]);
     y[idx] = philox_word_to_unit(r.v[1]);
+}
+
+// ------------------------------------------------------- schedule table
+
+// sched[k] = a0 - a_k with a_k = a0 k / K (linear ramp from zero), FP64
+// evaluated and rounded once to FP32; every step kernel reads this table.
+__global__ __launch_bounds__(256) void schedule_table(int K, double a0, float *__restrict__ sched) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k < K) sched[k] = schedule_gap(a0, k, K);
 }
 
 // ------------------------------------------------------ resident kernel
@@ -193,7 +178,7 @@ __global__ __launch_bounds__(TPB) void sb_resident(ResidentArgs A) {
     const float dt = A.dt, dta0 = A.dta0;
     int cur = 0, ck = 0;
     for (int k = 0; k < A.K; ++k) {
-        const float g = schedule_gap(A.a0, k, A.K);
+        const float g = A.sched[k];
         const float *xc = xs + cur * n;
         float *xn = xs + (cur ^ 1) * n;
 #pragma unroll
@@ -225,7 +210,7 @@ __global__ __launch_bounds__(TPB) void sb_resident(ResidentArgs A) {
                     e += er;
                 }
             }
-            const double tot = block_sum<TPB>(e, red);
+            const double tot = block_sum(e, red);
             if (t == 0) A.etrace[static_cast<size_t>(ck) * M + m] = tot;
             ++ck;
         }
@@ -257,7 +242,7 @@ __global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const floa
     if (m >= A.M) return;
     const int M = A.M;
     const float c0 = static_cast<float>(A.scal[0]);
-    const float g = schedule_gap(A.a0, k, A.K);
+    const float g = A.sched[k];
     const int p0 = A.row_ptr[i], p1 = A.row_ptr[i + 1];
     float acc = 0.0f;
     for (int p = p0; p < p1; ++p) {
@@ -389,6 +374,11 @@ hipError_t launch_prep(int n, const double *a, const int *row_ptr, const int *co
     return hipGetLastError();
 }
 
+hipError_t launch_schedule(int K, double a0, float *sched, hipStream_t st) {
+    schedule_table<<<(K + 255) / 256, 256, 0, st>>>(K, a0, sched);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(int n, int M, uint64_t seed, uint32_t event, float *x, float *y,
                        hipStream_t st) {
     const int64_t total = static_cast<int64_t>(n) * M;
@@ -399,44 +389,30 @@ hipError_t launch_init(int n, int M, uint64_t seed, uint32_t event, float *x, fl
     return hipGetLastError();
 }
 
-template <int MODE, int TPB, int SPT, bool JLDS>
-static hipError_t launch_resident_t(const ResidentArgs &A, size_t lds, hipStream_t st) {
-    auto fn = sb_resident<MODE, TPB, SPT, JLDS>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
-    if (e != hipSuccess) return e;
-    fn<<<A.M, TPB, lds, st>>>(A);
-    return hipGetLastError();
-}
-
 template <int MODE, int TPB, bool JLDS>
-static hipError_t launch_resident_spt(const ResidentArgs &A, int spt, size_t lds, hipStream_t st) {
-    switch (spt) {
-        case 1: return launch_resident_t<MODE, TPB, 1, JLDS>(A, lds, st);
-        case 2: return launch_resident_t<MODE, TPB, 2, JLDS>(A, lds, st);
-        case 4: return launch_resident_t<MODE, TPB, 4, JLDS>(A, lds, st);
-        case 8: return launch_resident_t<MODE, TPB, 8, JLDS>(A, lds, st);
-        case 16: return launch_resident_t<MODE, TPB, 16, JLDS>(A, lds, st);
+static hipError_t launch_lds_spt(const ResidentArgs &A, const ResidentShape &S, hipStream_t st) {
+    switch (S.spt) {
+        case 1: return launch_with_lds(sb_resident<MODE, TPB, 1, JLDS>, dim3(A.M), dim3(TPB), S.lds_bytes, st, A);
+        case 2: return launch_with_lds(sb_resident<MODE, TPB, 2, JLDS>, dim3(A.M), dim3(TPB), S.lds_bytes, st, A);
+        case 4: return launch_with_lds(sb_resident<MODE, TPB, 4, JLDS>, dim3(A.M), dim3(TPB), S.lds_bytes, st, A);
+        case 8: return launch_with_lds(sb_resident<MODE, TPB, 8, JLDS>, dim3(A.M), dim3(TPB), S.lds_bytes, st, A);
+        case 16: return launch_with_lds(sb_resident<MODE, TPB, 16, JLDS>, dim3(A.M), dim3(TPB), S.lds_bytes, st, A);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int MODE>
 static hipError_t launch_resident_m(const ResidentArgs &A, const ResidentShape &S, hipStream_t st) {
-    if (S.tpb == 64)
-        return S.jlds ? launch_resident_spt<MODE, 64, true>(A, S.spt, S.lds_bytes, st)
-                      : launch_resident_spt<MODE, 64, false>(A, S.spt, S.lds_bytes, st);
-    if (S.tpb == 256)
-        return S.jlds ? launch_resident_spt<MODE, 256, true>(A, S.spt, S.lds_bytes, st)
-                      : launch_resident_spt<MODE, 256, false>(A, S.spt, S.lds_bytes, st);
-    if (S.tpb == 1024)
-        return S.jlds ? launch_resident_spt<MODE, 1024, true>(A, S.spt, S.lds_bytes, st)
-                      : launch_resident_spt<MODE, 1024, false>(A, S.spt, S.lds_bytes, st);
-    return hipErrorInvalidValue;
+    switch (S.tpb) {
+        case 64: return S.jlds ? launch_lds_spt<MODE, 64, true>(A, S, st) : launch_lds_spt<MODE, 64, false>(A, S, st);
+        case 256: return S.jlds ? launch_lds_spt<MODE, 256, true>(A, S, st) : launch_lds_spt<MODE, 256, false>(A, S, st);
+        case 1024: return S.jlds ? launch_lds_spt<MODE, 1024, true>(A, S, st) : launch_lds_spt<MODE, 1024, false>(A, S, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_resident(int mode, const ResidentArgs &A, const ResidentShape &S, hipStream_t st) {
+    if (S.rc > 0) return launch_resident_reg(mode, A, S, st);
     return mode == kDSB ? launch_resident_m<kDSB>(A, S, st) : launch_resident_m<kBSB>(A, S, st);
 }
 

@@ -22,7 +22,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t J = 0, h = 0, scal = 0, prep = 0, xa = 0, xb = 0, y = 0, epart = 0, etrace = 0;
+    size_t J = 0, h = 0, scal = 0, prep = 0, perm = 0, sched = 0, xa = 0, xb = 0, y = 0, epart = 0, etrace = 0;
     size_t total = 0;
     int n_ckpt = 0;
 };
@@ -43,6 +43,8 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every) 
     L.h = take(sizeof(float) * n);
     L.scal = take(sizeof(double) * 8);
     L.prep = take(sizeof(double) * 4 * nblk_prep);
+    L.perm = take(sizeof(int32_t) * n);
+    L.sched = take(sizeof(float) * static_cast<size_t>(K));
     L.xa = take(sizeof(float) * nm);
     L.xb = take(sizeof(float) * nm);
     L.y = take(sizeof(float) * nm);
@@ -64,6 +66,8 @@ int check_params(const sbt_solve_params &p, const char *who) {
     if (p.event < 0) return fail(SBT_EINVAL, "%s: event must be >= 0", who);
     if (p.kernel < SBT_KERNEL_AUTO || p.kernel > SBT_KERNEL_STREAM)
         return fail(SBT_EINVAL, "%s: unknown kernel %d", who, p.kernel);
+    if (p.tpb != 0 && p.tpb != 64 && p.tpb != 256 && p.tpb != 512 && p.tpb != 1024)
+        return fail(SBT_EINVAL, "%s: tpb must be 0, 64, 256, 512 or 1024", who);
     return SBT_OK;
 }
 
@@ -84,13 +88,46 @@ int device_lds_limit() {
     return v;
 }
 
-// Resident-kernel shape for (n, nnz), or tpb = 0 if it does not fit.
-sbt::ResidentShape resident_shape(int32_t n, int64_t nnz, int lds_limit) {
-    sbt::ResidentShape S{0, 0, false, 0};
+// Resident-kernel shape, or tpb = 0 if no resident variant fits.
+// Register-row variant when n <= kRegMaxN and the per-thread rows fit the
+// register budget; otherwise the LDS-row variant while positions fit LDS.
+sbt::ResidentShape resident_shape(int32_t n, int64_t nnz, int32_t max_row, int tpb_hint,
+                                  int lds_limit) {
+    sbt::ResidentShape S{0, 0, 0, false, 0};
+    auto pow2_at_least = [](int v) {
+        int p = 1;
+        while (p < v) p <<= 1;
+        return p;
+    };
+    const bool hinted = tpb_hint == 64 || tpb_hint == 256 || tpb_hint == 512 || tpb_hint == 1024;
+    // register-row variant: the fewest spins per thread whose workgroup
+    // (a multiple of 64 threads) fits in 1024, or the hinted size
+    if (n <= sbt::kRegMaxN) {
+        for (int spt = 1; spt <= 8; spt <<= 1) {
+            const int tpb = ((n + spt - 1) / spt + 63) / 64 * 64;
+            const int cap_tpb = hinted ? tpb_hint : 1024;
+            if (tpb > cap_tpb) continue;
+            const int maxtpb = tpb <= 256 ? 256 : (tpb <= 512 ? 512 : 1024);
+            // VGPR estimate of the kernel (fit to the compiler's counts)
+            const int budget = maxtpb >= 1024 ? 128 : (maxtpb >= 512 ? 256 : 512);
+            auto vgprs = [&](int r) { return (7 * spt * r) / 2 + 12 * spt + 40; };
+            int rc = max_row <= 2 ? 2 : (max_row <= 4 ? 4 : 8);
+            if (spt > 4 && rc > 4) rc = 4;
+            while (rc > 2 && vgprs(rc) > budget) rc >>= 1;
+            if (vgprs(rc) > budget) continue;
+            const size_t lds =
+                sizeof(float) * 2 * sbt::kRegMaxN + sizeof(double) * (maxtpb / 64);
+            if (lds > static_cast<size_t>(lds_limit)) break;
+            S.tpb = tpb;
+            S.spt = spt;
+            S.rc = rc;
+            S.lds_bytes = lds;
+            return S;
+        }
+    }
+    // LDS-row variant
     const int tpb = n <= 64 ? 64 : (n <= 1024 ? 256 : 1024);
-    const int need = (n + tpb - 1) / tpb;
-    int spt = 1;
-    while (spt < need) spt <<= 1;
+    const int spt = pow2_at_least((n + tpb - 1) / tpb);
     if (spt > 16) return S;
     const size_t red = 16 + sizeof(double) * (tpb / 64);
     const size_t base = sizeof(float) * 2 * static_cast<size_t>(n) + red;
@@ -99,14 +136,15 @@ sbt::ResidentShape resident_shape(int32_t n, int64_t nnz, int lds_limit) {
     if (base > static_cast<size_t>(lds_limit)) return S;
     S.tpb = tpb;
     S.spt = spt;
+    S.rc = 0;
     S.jlds = base + jbytes <= static_cast<size_t>(lds_limit);
     S.lds_bytes = S.jlds ? base + jbytes : base;
     return S;
 }
 
-int pick_kernel(int32_t n, int64_t nnz, const sbt_solve_params &p, int lds_limit,
+int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, const sbt_solve_params &p, int lds_limit,
                 sbt::ResidentShape *shape) {
-    sbt::ResidentShape S = resident_shape(n, nnz, lds_limit);
+    sbt::ResidentShape S = resident_shape(n, nnz, max_row, p.tpb, lds_limit);
     if (shape) *shape = S;
     if (p.kernel == SBT_KERNEL_STREAM) return SBT_KERNEL_STREAM;
     if (p.kernel == SBT_KERNEL_RESIDENT) {
@@ -159,14 +197,14 @@ extern "C" size_t sbt_workspace_bytes(int32_t n, int64_t nnz, sbt_mode mode,
 extern "C" int sbt_select_kernel(int32_t n, int64_t nnz, int32_t max_row_nnz, sbt_mode mode,
                                  const sbt_solve_params *p) {
     sbt::clear_error();
-    (void)max_row_nnz;
     if (!p) return fail(SBT_EINVAL, "sbt_select_kernel: params is NULL");
     if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "sbt_select_kernel: mode");
     int rc = check_params(*p, "sbt_select_kernel");
     if (rc) return rc;
     rc = check_shape(n, nnz, p->agents, "sbt_select_kernel");
     if (rc) return rc;
-    return pick_kernel(n, nnz, *p, device_lds_limit(), nullptr);
+    if (max_row_nnz < 0) return fail(SBT_EINVAL, "sbt_select_kernel: max_row_nnz < 0");
+    return pick_kernel(n, nnz, max_row_nnz, *p, device_lds_limit(), nullptr);
 }
 
 extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
@@ -196,7 +234,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
 
     sbt::ResidentShape shape;
-    const int kernel = pick_kernel(n, q->nnz, *p, device_lds_limit(), &shape);
+    const int kernel = pick_kernel(n, q->nnz, max_row_nnz, *p, device_lds_limit(), &shape);
     if (kernel < 0) return kernel;
 
     char *ws = static_cast<char *>(workspace);
@@ -204,6 +242,8 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
     float *dh = reinterpret_cast<float *>(ws + L.h);
     double *scal = reinterpret_cast<double *>(ws + L.scal);
     double *prep = reinterpret_cast<double *>(ws + L.prep);
+    int *perm = reinterpret_cast<int *>(ws + L.perm);
+    float *sched = reinterpret_cast<float *>(ws + L.sched);
     float *xa = reinterpret_cast<float *>(ws + L.xa);
     float *xb = reinterpret_cast<float *>(ws + L.xb);
     float *dy = reinterpret_cast<float *>(ws + L.y);
@@ -214,10 +254,12 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
     const double c0_fixed = (std::isnan(p->c0) || p->c0 <= 0.0) ? 0.0 : p->c0;
     SBT_HIP(sbt::launch_prep(n, q->a, q->row_ptr, q->col, q->b, dJ, dh, prep, scal, c0_fixed, st));
     SBT_HIP(sbt::launch_init(n, M, p->seed, static_cast<uint32_t>(p->event), xa, dy, st));
+    SBT_HIP(sbt::launch_schedule(K, p->a0, sched, st));
 
     const float dt = static_cast<float>(p->dt);
     const float dta0 = static_cast<float>(p->dt * p->a0);
     float *xfinal = xa;
+    if (out->step_begin) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_begin), st));
     if (kernel == SBT_KERNEL_RESIDENT) {
         sbt::ResidentArgs A{};
         A.n = n;
@@ -238,6 +280,9 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         A.x = xa;
         A.y = dy;
         A.etrace = etrace;
+        A.perm = perm;
+        A.sched = sched;
+        if (shape.rc > 0) SBT_HIP(sbt::launch_row_order(n, q->row_ptr, perm, st));
         SBT_HIP(sbt::launch_resident(mode, A, shape, st));
     } else {
         sbt::StreamArgs A{};
@@ -253,6 +298,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         A.h = dh;
         A.scal = scal;
         A.y = dy;
+        A.sched = sched;
         float *xin = xa, *xout = xb;
         int ck = 0;
         for (int k = 0; k < K; ++k) {
@@ -266,6 +312,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         }
         xfinal = xin;
     }
+    if (out->step_end) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_end), st));
     SBT_HIP(sbt::launch_energy(n, M, q->a, q->row_ptr, q->col, q->b, xfinal, epart,
                                out->agent_energy, st));
     SBT_HIP(sbt::launch_select_best(n, M, out->agent_energy, xfinal, out->best_energy,
@@ -399,7 +446,7 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
     dr.x_final = static_cast<float *>(dx.p);
     dr.y_final = static_cast<float *>(dy.p);
     dr.trace = static_cast<double *>(dtr.p);
-    const int kernel = pick_kernel(n, nnz, p, device_lds_limit(), nullptr);
+    const int kernel = pick_kernel(n, nnz, max_row, p, device_lds_limit(), nullptr);
     if (kernel < 0) return kernel;
     SBT_HIP(hipEventRecord(hs.e0, hs.s));
     rc = sbt_solve_dev(&dq, max_row, mode, &p, dws.p, ws_bytes, &dr, hs.s);
