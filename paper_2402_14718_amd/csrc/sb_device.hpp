@@ -68,8 +68,9 @@ __device__ __forceinline__ float schedule_gap(double a0, int k, int K) {
 // One symplectic-Euler step of one oscillator (Eq. 5-6 / 9-10) followed by
 // the inelastic wall (Eq. 8 / 12):
 //   y += dt (c0 F - g x),  x += dt a0 y,  |x| > 1 -> x = sgn(x), y = 0.
-// F already holds sum_j J_ij op(x_j) + h_i.  Rounding is pinned with
-// explicit fused multiply-adds.
+// F holds h_i + sum_j J_ij op(x_j) (the field seeds the sum).  Rounding is
+// pinned with explicit fused multiply-adds.  Past the wall, sgn(x) equals
+// x clamped to [-1, 1] (one v_med3), and inside it the clamp is exact.
 __device__ __forceinline__ void sb_update(float &x, float &y, float F, float c0, float g,
                                           float dt, float dta0) {
     const float gx = g * x;
@@ -77,8 +78,17 @@ __device__ __forceinline__ void sb_update(float &x, float &y, float F, float c0,
     const float yn = __builtin_fmaf(dt, force, y);
     const float xn = __builtin_fmaf(dta0, yn, x);
     const bool wall = __builtin_fabsf(xn) > 1.0f;
-    x = wall ? sgnf(xn) : xn;
+    x = __builtin_amdgcn_fmed3f(xn, -1.0f, 1.0f);
     y = wall ? 0.0f : yn;
+}
+
+// What the coupling reads of a neighbour: its position (bSB) or sign (dSB).
+template <int MODE>
+__device__ __forceinline__ float shared_value(float x) {
+    if constexpr (MODE == kDSB)
+        return sgnf(x);
+    else
+        return x;
 }
 
 // ------------------------------------------------------------ reductions

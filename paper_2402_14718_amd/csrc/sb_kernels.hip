@@ -169,7 +169,7 @@ __global__ __launch_bounds__(TPB) void sb_resident(ResidentArgs A) {
             hr[s] = A.h[i];
             p0[s] = A.row_ptr[i];
             p1[s] = A.row_ptr[i + 1];
-            xs[i] = xr[s];
+            xs[i] = shared_value<MODE>(xr[s]);
         }
     }
     __syncthreads();
@@ -185,11 +185,10 @@ __global__ __launch_bounds__(TPB) void sb_resident(ResidentArgs A) {
         for (int s = 0; s < SPT; ++s) {
             const int i = t + s * TPB;
             if (i < n) {
-                float acc = 0.0f;
-                for (int p = p0[s]; p < p1[s]; ++p)
-                    acc = __builtin_fmaf(jv[p], coupling_operand<MODE>(xc[cl[p]]), acc);
-                sb_update(xr[s], yr[s], acc + hr[s], c0, g, dt, dta0);
-                xn[i] = xr[s];
+                float acc = hr[s];
+                for (int p = p0[s]; p < p1[s]; ++p) acc = __builtin_fmaf(jv[p], xc[cl[p]], acc);
+                sb_update(xr[s], yr[s], acc, c0, g, dt, dta0);
+                xn[i] = shared_value<MODE>(xr[s]);
             }
         }
         __syncthreads();
@@ -244,14 +243,14 @@ __global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const floa
     const float c0 = static_cast<float>(A.scal[0]);
     const float g = A.sched[k];
     const int p0 = A.row_ptr[i], p1 = A.row_ptr[i + 1];
-    float acc = 0.0f;
+    float acc = A.h[i];
     for (int p = p0; p < p1; ++p) {
         const int c = A.col[p];
         acc = __builtin_fmaf(A.J[p], coupling_operand<MODE>(xin[static_cast<size_t>(c) * M + m]), acc);
     }
     const size_t o = static_cast<size_t>(i) * M + m;
     float x = xin[o], y = A.y[o];
-    sb_update(x, y, acc + A.h[i], c0, g, A.dt, A.dta0);
+    sb_update(x, y, acc, c0, g, A.dt, A.dta0);
     xout[o] = x;
     A.y[o] = y;
 }

@@ -57,10 +57,11 @@ __global__ __launch_bounds__(1024) void row_order(int n, const int *__restrict__
 }
 
 // Gather-and-sum over the first C held couplings of every slot: all LDS
-// loads first, then the FMAs in CSR order.  Entries past a row's length
-// hold J = 0 and column 0, an exact +0 contribution (the running sum is
-// never -0).
-template <int MODE, int SPT, int RC, int C>
+// loads first, then the FMAs in CSR order onto acc (which enters holding
+// h_i).  LDS holds what the coupling reads (x for bSB, sgn x for dSB).
+// Entries past a row's length hold J = 0 and column 0: an exact zero
+// contribution, since the running sum is never -0.
+template <int SPT, int RC, int C>
 __device__ __forceinline__ void reg_dots(const float *__restrict__ xc, const int (&cols)[SPT][RC],
                                          const float (&js)[SPT][RC], float (&acc)[SPT]) {
     float v[SPT][C];
@@ -70,9 +71,9 @@ __device__ __forceinline__ void reg_dots(const float *__restrict__ xc, const int
         for (int e = 0; e < C; ++e) v[s][e] = xc[cols[s][e]];
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
-        float a = 0.0f;
+        float a = acc[s];
 #pragma unroll
-        for (int e = 0; e < C; ++e) a = __builtin_fmaf(js[s][e], coupling_operand<MODE>(v[s][e]), a);
+        for (int e = 0; e < C; ++e) a = __builtin_fmaf(js[s][e], v[s][e], a);
         acc[s] = a;
     }
 }
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
             tail1[s] = p1;
             need = max(need, p1 - p0);
             tail |= (p1 - p0 > RC) ? 1 : 0;
-            xs[i] = xr[s];
+            xs[i] = shared_value<MODE>(xr[s]);
         }
     }
     const int cap = wave_max_int(need);
@@ -138,32 +139,34 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
         float *xn = xs + (B ^ 1) * kRegMaxN;
         const float g = A.sched[k];
         float acc[SPT];
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) acc[s] = hr[s];
         if constexpr (RC <= 2) {
-            reg_dots<MODE, SPT, RC, RC>(xc, cols, js, acc);
+            reg_dots<SPT, RC, RC>(xc, cols, js, acc);
         } else if constexpr (RC <= 4) {
             if (cap <= 2)
-                reg_dots<MODE, SPT, RC, 2>(xc, cols, js, acc);
+                reg_dots<SPT, RC, 2>(xc, cols, js, acc);
             else
-                reg_dots<MODE, SPT, RC, RC>(xc, cols, js, acc);
+                reg_dots<SPT, RC, RC>(xc, cols, js, acc);
         } else {
             if (cap <= 2)
-                reg_dots<MODE, SPT, RC, 2>(xc, cols, js, acc);
+                reg_dots<SPT, RC, 2>(xc, cols, js, acc);
             else if (cap <= 4)
-                reg_dots<MODE, SPT, RC, 4>(xc, cols, js, acc);
+                reg_dots<SPT, RC, 4>(xc, cols, js, acc);
             else
-                reg_dots<MODE, SPT, RC, RC>(xc, cols, js, acc);
+                reg_dots<SPT, RC, RC>(xc, cols, js, acc);
         }
         if (any_tail) {
 #pragma unroll
             for (int s = 0; s < SPT; ++s)
                 for (int p = tail0[s]; p < tail1[s]; ++p)
-                    acc[s] = __builtin_fmaf(A.J[p], coupling_operand<MODE>(xc[A.col[p]]), acc[s]);
+                    acc[s] = __builtin_fmaf(A.J[p], xc[A.col[p]], acc[s]);
         }
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
             if (spin[s] >= 0) {
-                sb_update(xr[s], yr[s], acc[s] + hr[s], c0, g, dt, dta0);
-                xn[spin[s]] = xr[s];
+                sb_update(xr[s], yr[s], acc[s], c0, g, dt, dta0);
+                xn[spin[s]] = shared_value<MODE>(xr[s]);
             }
         }
         __syncthreads();
