@@ -52,6 +52,16 @@ def step_bytes(n, nnz, agents, steps):
     return float(steps) * (16.0 * n * agents + 8.0 * nnz + 4.0 * (n + 1))
 
 
+def measured_traffic(profile_name):
+    """HBM bytes per launch from the committed rocprofv3 counter record, or
+    None when the kernel's sources changed after the counters were taken."""
+    from paper_2402_14718_amd import rocprof_summary as rs
+    rec = rs.read_record(os.path.join(ROOT, "profiles", profile_name))
+    if not rec or rec.get("sources_sha") != rs.sources_hash(rec["family"]):
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(q, n_target_s=12.0):
     """The FP64 oracle integrator on the host, both forms, all 256 agents,
     for a bounded number of steps; returned as spin-updates/s."""
@@ -88,7 +98,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the solver shards over agents with "
               "no per-step communication, so --gpus N > 1 is not run here", file=sys.stderr)
@@ -153,9 +174,9 @@ def main():
         achieved = flops / launch_s / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": MI355X_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_VECTOR_TFLOPS,
-                "traffic": None, "kernel": "sb_resident",
-                "launch_ms": launch_s * 1e3,
-                "effective_state_GBs": bytes_ / launch_s / 1e9}
+                "traffic": measured_traffic("sb_resident_reg_plain.md"),
+                "kernel": "sb_resident_reg", "launch_ms": launch_s * 1e3,
+                "state_bytes_if_streamed_GBs": bytes_ / launch_s / 1e9}
     else:
         achieved = bytes_ / launch_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_GBS, "unit": "GB/s",

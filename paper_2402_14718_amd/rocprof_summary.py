@@ -1,0 +1,157 @@
+"""Summarise rocprofv3 CSV output into a short markdown profile record.
+
+    python -m paper_2402_14718_amd.rocprof_summary --title T --kernel REGEX \\
+        --trace DIR --fetch DIR --write DIR [--sq DIR] \\
+        --copy-fetch DIR --copy-write DIR --command CMD ... > profiles/NAME.md
+
+Each DIR is a rocprofv3 output directory (``-f csv``).  FETCH_SIZE and
+WRITE_SIZE (KiB per dispatch) are scaled by what the same counters read for
+a plain device-to-device copy of known size (``bench.py --copy-calibration``
+copies 256 MiB three times), giving HBM bytes per launch of the kernel that
+matches REGEX.  The record ends with a JSON block (sources hash included) so
+the benchmark can tell whether the counters still describe the current
+kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = {
+    "sb_resident_reg": ["csrc/sb_resident_reg.hip", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
+    "sb_stream": ["csrc/sb_kernels.hip", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
+    "sb_batch": ["csrc/sb_batch.hip", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
+}
+COPY_BYTES = 256 << 20
+
+
+def sources_hash(kernel_family: str) -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kernel_family]:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _one(d, pattern):
+    files = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"{pattern} under {d}")
+    return files[0]
+
+
+def counters(d):
+    """{kernel name: {counter: [values per dispatch]}}"""
+    out = collections.defaultdict(lambda: collections.defaultdict(list))
+    with open(_one(d, "*counter_collection.csv")) as f:
+        for r in csv.DictReader(f):
+            out[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return out
+
+
+def pick(table, regex):
+    for name, v in table.items():
+        if re.search(regex, name):
+            return name, v
+    raise KeyError(regex)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--kernel", required=True, help="regex of the dominant kernel")
+    ap.add_argument("--family", required=True, choices=sorted(KERNEL_SOURCES))
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--sq")
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--note", action="append", default=[])
+    a = ap.parse_args(argv)
+
+    lines = [f"# {a.title}", ""]
+    if a.command:
+        lines += ["Commands (run from /tmp with TMPDIR=/tmp; R = repository root):", "", "```"]
+        lines += a.command + ["```", ""]
+    lines += ["## Kernel time (rocprofv3 --kernel-trace --stats)", "",
+              "| kernel | calls | avg us | total us | % |", "|---|---|---|---|---|"]
+    with open(_one(a.trace, "*kernel_stats.csv")) as f:
+        rows = list(csv.DictReader(f))
+    for r in rows[:12]:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.2f} | "
+                     f"{float(r['TotalDurationNs'])/1e3:.1f} | {float(r['Percentage']):.1f} |")
+    dom = [r for r in rows if re.search(a.kernel, r["Name"])]
+    avg_ns = sum(float(r["TotalDurationNs"]) for r in dom) / max(1, sum(int(r["Calls"]) for r in dom))
+
+    cf = counters(a.copy_fetch)
+    cw = counters(a.copy_write)
+    _, cfv = pick(cf, "copyBuffer")
+    _, cwv = pick(cw, "copyBuffer")
+    fetch_copy_kib = max(cfv["FETCH_SIZE"])
+    write_copy_kib = max(cwv["WRITE_SIZE"])
+    f_fac = COPY_BYTES / 1024.0 / fetch_copy_kib
+    w_fac = COPY_BYTES / 1024.0 / write_copy_kib
+
+    kf = counters(a.fetch)
+    kw = counters(a.write)
+    name_f, vf = pick(kf, a.kernel)
+    name_w, vw = pick(kw, a.kernel)
+    fetch_kib = sum(vf["FETCH_SIZE"]) / len(vf["FETCH_SIZE"])
+    write_kib = sum(vw["WRITE_SIZE"]) / len(vw["WRITE_SIZE"])
+    hbm_bytes = fetch_kib * 1024 * f_fac + write_kib * 1024 * w_fac
+
+    lines += ["", "## HBM bytes of the dominant kernel (rocprofv3 --pmc, one pass each)", "",
+              f"Kernel: `{name_f}`", "",
+              "| counter | KiB per dispatch | copy calibration (KiB read for 256 MiB) | factor | bytes per launch |",
+              "|---|---|---|---|---|",
+              f"| FETCH_SIZE | {fetch_kib:.1f} | {fetch_copy_kib:.1f} | {f_fac:.3f} | {fetch_kib*1024*f_fac:.4g} |",
+              f"| WRITE_SIZE | {write_kib:.1f} | {write_copy_kib:.1f} | {w_fac:.3f} | {write_kib*1024*w_fac:.4g} |",
+              "", f"Average duration of that kernel: {avg_ns/1e3:.2f} us; HBM traffic "
+              f"{hbm_bytes/1e6:.2f} MB per launch = {hbm_bytes/avg_ns:.2f} GB/s.", ""]
+    sq = None
+    if a.sq:
+        ks = counters(a.sq)
+        name_s, vs = pick(ks, a.kernel)
+        sq = {c: sum(v) / len(v) for c, v in vs.items()}
+        lines += ["## Instruction counters (SQ, summed over the chip, per dispatch)", "",
+                  "| counter | value |", "|---|---|"]
+        for c, v in sorted(sq.items()):
+            lines.append(f"| {c} | {v:.4g} |")
+        if "SQ_INSTS_VALU" in sq:
+            slots = 256 * 4 * 2.4e9 * avg_ns * 1e-9 / 4.0
+            lines += ["", f"VALU issue: {sq['SQ_INSTS_VALU']:.4g} wave-instructions against "
+                      f"{slots:.4g} wave64 issue slots in the kernel's duration "
+                      f"(256 CU x 4 SIMD x 2.4 GHz / 4 cycles) = {sq['SQ_INSTS_VALU']/slots:.2f}."]
+        lines.append("")
+    for n in a.note:
+        lines += [n, ""]
+    rec = {"kernel_regex": a.kernel, "family": a.family, "sources_sha": sources_hash(a.family),
+           "avg_launch_us": avg_ns / 1e3, "fetch_kib": fetch_kib, "write_kib": write_kib,
+           "fetch_factor": f_fac, "write_factor": w_fac, "hbm_bytes_per_launch": hbm_bytes,
+           "sq": sq}
+    lines += ["## Record", "", "```json", json.dumps(rec, indent=1), "```", ""]
+    sys.stdout.write("\n".join(lines))
+
+
+def read_record(md_path):
+    """The JSON record of a profile markdown file, or None."""
+    try:
+        text = open(md_path).read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    return json.loads(m.group(1)) if m else None
+
+
+if __name__ == "__main__":
+    main()
