@@ -221,6 +221,86 @@ int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
                   const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
                   const sbt_dev_result *out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of events (HIP)
+ *
+ * Many independent events solved together (the paper solves one event at a
+ * time; batching only changes the scheduling).  Every event gets `agents`
+ * agents and `steps` steps of the same form (section "Simulated
+ * Bifurcation"), event e drawing its start with Philox counter word
+ * p->event + e.  All events run in one persistent kernel: work items are
+ * (event, group of agents) taken from a queue in decreasing-cost order, each
+ * workgroup holding all positions of its agents on chip.  The couplings are
+ * held in 16 bits (the reduced-precision form); accumulation is FP32 and
+ * energies are FP64 of the returned spins.
+ * ---------------------------------------------------------------------- */
+
+typedef enum { SBT_PREC_FP32 = 0, SBT_PREC_FP16 = 1, SBT_PREC_BF16 = 2 } sbt_precision;
+
+/* Events concatenated in device memory. */
+typedef struct {
+    int32_t n_events;
+    const int32_t *n;        /* host [E]: variables of each event (1..9216)       */
+    const int64_t *nnz;      /* host [E]: stored couplings of each event          */
+    const double *a;         /* device [sum n]                                     */
+    const int32_t *row_ptr;  /* device [sum (n + 1)]: each event's own CSR row    */
+                             /*   pointers, starting at 0                          */
+    const int32_t *col;      /* device [sum nnz]: columns local to the event      */
+    const double *b;         /* device [sum nnz]: symmetric, ascending columns    */
+} sbt_dev_batch;
+
+typedef struct {
+    double *best_energy;     /* device [E]: O(T) of each event's best agent       */
+    int32_t *best_agent;     /* device [E]                                         */
+    int8_t *best_T;          /* device [sum n]: best agent's T, events concatenated */
+    double *agent_energy;    /* device [E * agents] or NULL                        */
+    double *offset;          /* device [E] or NULL: Ising offsets C                */
+    double *trace;           /* device [E * (steps / energy_every)] or NULL:      */
+                             /*   best-so-far O(T) per checkpoint                  */
+    void *step_begin;        /* hipEvent_t or NULL, recorded around the kernel    */
+    void *step_end;          /*   that runs every step of every event             */
+    int8_t *agent_T;         /* device [sum n * agents] or NULL: every agent's    */
+                             /*   final T (event e's block spin-major, agents     */
+                             /*   contiguous, starting at agents * sum_{f<e} n_f) */
+    float *agent_x;          /* device [sum n * agents] or NULL: final positions, */
+                             /*   same layout                                     */
+} sbt_dev_batch_result;
+
+/* Device workspace bytes for a batch of these sizes (0 on invalid input). */
+size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                                 const sbt_solve_params *p);
+
+/* Upload the batch's schedule (event descriptors and the ordered work
+ * items) into `workspace` on `stream`.  Call once per (batch shape,
+ * parameters); sbt_batch_run then only launches kernels and may be captured
+ * in a HIP graph.  Returns the number of work items, or a negative status;
+ * SBT_EUNSUPPORTED for an event with more than 9216 variables. */
+int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                   const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
+                   void *stream);
+
+/* Solve every event of a planned batch: per-event Ising preparation and
+ * spin ordering, all steps of all agents of all events in one persistent
+ * kernel, FP64 energies, best agent per event.  `prec` is SBT_PREC_FP16 or
+ * SBT_PREC_BF16 (SBT_EUNSUPPORTED otherwise).  Returns after enqueueing. */
+int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_precision prec,
+                  const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
+                  const sbt_dev_batch_result *out, void *stream);
+
+/* Host-memory results of sbt_solve_batch. */
+typedef struct {
+    double *energy;          /* caller [E]: best O(T) per event                    */
+    int32_t *best_agent;     /* caller [E]                                         */
+    int8_t *T;               /* caller [sum n] or NULL: best T, events concatenated */
+    double *agent_energy;    /* caller [E * agents] or NULL                        */
+    double *trace;           /* caller [E * (steps / energy_every)] or NULL        */
+    double elapsed_s;        /* out: device time of plan + run                     */
+} sbt_batch_result;
+
+/* Host convenience: validate and upload the QUBOs, plan, run, download. */
+int sbt_solve_batch(const sbt_qubo *const *qs, int32_t n_events, sbt_mode mode,
+                    sbt_precision prec, const sbt_solve_params *p, sbt_batch_result *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -226,6 +226,138 @@ class DeviceSolver:
                 "kernel": self.kernel}
 
 
-__all__ = ["Qubo", "DeviceSolver", "build_qubo", "energy", "solve", "solve_params",
-           "workspace_bytes", "select_kernel", "build_params_default", "version", "load",
-           "SbtError", "HIT_DTYPE", "MODES", "KERNELS"]
+PRECISIONS = {"fp32": _lib.SBT_PREC_FP32, "fp16": _lib.SBT_PREC_FP16, "bf16": _lib.SBT_PREC_BF16}
+
+
+def _concat_batch(qubos):
+    n = np.array([q.n for q in qubos], dtype=np.int32)
+    nnz = np.array([q.nnz for q in qubos], dtype=np.int64)
+    a = np.concatenate([q.a for q in qubos]).astype(np.float64)
+    rp = np.concatenate([q.row_ptr.astype(np.int32) for q in qubos])
+    col = np.concatenate([q.col for q in qubos] + [np.zeros(1, np.int32)]).astype(np.int32)
+    b = np.concatenate([q.b for q in qubos] + [np.zeros(1)]).astype(np.float64)
+    return n, nnz, a, rp, col, b
+
+
+def _split(flat, sizes):
+    out, o = [], 0
+    for s in sizes:
+        out.append(flat[o:o + s])
+        o += s
+    return out
+
+
+def solve_batch(qubos, mode: str, precision: str = "fp16", agents: int = 128,
+                steps: int = 3000, dt: float = 1.0, a0: float = 1.0, c0: float = 0.0,
+                seed: int = 0, event: int = 0, energy_every: int = 0,
+                want_agent_energy: bool = False, want_trace: bool = False) -> dict:
+    """sbt_solve_batch: host QUBOs in, per-event host results out."""
+    p = solve_params(agents, steps, dt, a0, c0, seed, event, "auto", energy_every)
+    structs = [q.as_struct() for q in qubos]
+    arr = (C.POINTER(_lib.SbtQubo) * len(qubos))(*[C.pointer(s) for s in structs])
+    E = len(qubos)
+    energy_ = np.zeros(E)
+    best = np.zeros(E, dtype=np.int32)
+    T = np.zeros(sum(q.n for q in qubos), dtype=np.int8)
+    ae = np.zeros(E * agents) if want_agent_energy else None
+    n_ck = steps // energy_every if energy_every > 0 else 0
+    tr = np.zeros(E * n_ck) if want_trace else None
+    r = _lib.SbtBatchResult()
+    r.energy = energy_.ctypes.data_as(C.POINTER(C.c_double))
+    r.best_agent = best.ctypes.data_as(C.POINTER(C.c_int32))
+    r.T = T.ctypes.data_as(C.POINTER(C.c_int8))
+    if ae is not None:
+        r.agent_energy = ae.ctypes.data_as(C.POINTER(C.c_double))
+    if tr is not None:
+        r.trace = tr.ctypes.data_as(C.POINTER(C.c_double))
+    check(load().sbt_solve_batch(arr, E, MODES[mode], PRECISIONS[precision], C.byref(p),
+                                 C.byref(r)))
+    return {"energy": energy_, "best_agent": best, "T": _split(T, [q.n for q in qubos]),
+            "agent_energy": None if ae is None else ae.reshape(E, agents),
+            "trace": None if tr is None else tr.reshape(E, n_ck), "elapsed_s": r.elapsed_s}
+
+
+class DeviceBatchSolver:
+    """sbt_batch_plan once, then sbt_batch_run per call, every buffer held by
+    torch on a HIP device (events concatenated)."""
+
+    def __init__(self, qubos, mode: str, precision: str, params: _lib.SbtSolveParams,
+                 device="cuda", want_agent_energy: bool = False, want_trace: bool = False,
+                 want_agent_state: bool = False):
+        import torch
+        self.torch = torch
+        self.mode, self.precision, self.params = mode, precision, params
+        dev = torch.device(device)
+        n, nnz, a, rp, col, b = _concat_batch(qubos)
+        self.n_host, self.nnz_host = n, nnz
+        self.sizes = [int(v) for v in n]
+        t = lambda x, dt: torch.as_tensor(np.ascontiguousarray(x), dtype=dt).to(dev)
+        self.a, self.rp, self.col, self.b = (t(a, torch.float64), t(rp, torch.int32),
+                                             t(col, torch.int32), t(b, torch.float64))
+        E, M = len(qubos), params.agents
+        self.E = E
+        lib = load()
+        np_ = n.ctypes.data_as(C.POINTER(C.c_int32))
+        nz_ = nnz.ctypes.data_as(C.POINTER(C.c_int64))
+        self.ws_bytes = int(lib.sbt_batch_workspace_bytes(np_, nz_, E, C.byref(params)))
+        if self.ws_bytes == 0:
+            raise SbtError(_lib.SBT_EINVAL, lib.sbt_last_error().decode())
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.best_energy = torch.empty(E, dtype=torch.float64, device=dev)
+        self.best_agent = torch.empty(E, dtype=torch.int32, device=dev)
+        self.best_T = torch.empty(int(n.sum()), dtype=torch.int8, device=dev)
+        self.offset = torch.empty(E, dtype=torch.float64, device=dev)
+        self.agent_energy = (torch.empty(E * M, dtype=torch.float64, device=dev)
+                             if want_agent_energy else None)
+        n_ck = params.steps // params.energy_every if params.energy_every > 0 else 0
+        self.n_ckpt = n_ck
+        self.trace = (torch.empty(E * n_ck, dtype=torch.float64, device=dev)
+                      if want_trace and n_ck > 0 else None)
+        st = torch.cuda.current_stream()
+        rc = lib.sbt_batch_plan(np_, nz_, E, C.byref(params),
+                                C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                C.c_void_p(st.cuda_stream))
+        if rc < 0:
+            check(rc)
+        self.n_items = rc
+        self._db = _lib.SbtDevBatch(E, np_, nz_, self.a.data_ptr(), self.rp.data_ptr(),
+                                    self.col.data_ptr(), self.b.data_ptr())
+        tot = int(n.sum()) * M
+        self.agent_T = torch.empty(tot, dtype=torch.int8, device=dev) if want_agent_state else None
+        self.agent_x = torch.empty(tot, dtype=torch.float32, device=dev) if want_agent_state else None
+        ptr = lambda x: x.data_ptr() if x is not None else None
+        self._dr = _lib.SbtDevBatchResult(self.best_energy.data_ptr(), self.best_agent.data_ptr(),
+                                          self.best_T.data_ptr(), ptr(self.agent_energy),
+                                          self.offset.data_ptr(), ptr(self.trace), None, None,
+                                          ptr(self.agent_T), ptr(self.agent_x))
+
+    def run(self, stream=None) -> None:
+        st = stream if stream is not None else self.torch.cuda.current_stream()
+        check(load().sbt_batch_run(C.byref(self._db), MODES[self.mode],
+                                   PRECISIONS[self.precision], C.byref(self.params),
+                                   C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                   C.byref(self._dr), C.c_void_p(st.cuda_stream)))
+
+    def result(self) -> dict:
+        self.torch.cuda.synchronize()
+        M = self.params.agents
+        return {"energy": self.best_energy.cpu().numpy(),
+                "best_agent": self.best_agent.cpu().numpy(),
+                "T": _split(self.best_T.cpu().numpy(), self.sizes),
+                "offset": self.offset.cpu().numpy(),
+                "agent_energy": (None if self.agent_energy is None
+                                 else self.agent_energy.cpu().numpy().reshape(self.E, M)),
+                "trace": (None if self.trace is None
+                          else self.trace.cpu().numpy().reshape(self.E, self.n_ckpt)),
+                "agent_T": (None if self.agent_T is None else
+                            [v.reshape(-1, M) for v in _split(self.agent_T.cpu().numpy(),
+                                                              [s * M for s in self.sizes])]),
+                "agent_x": (None if self.agent_x is None else
+                            [v.reshape(-1, M) for v in _split(self.agent_x.cpu().numpy(),
+                                                              [s * M for s in self.sizes])])}
+
+
+__all__ = ["Qubo", "DeviceSolver", "DeviceBatchSolver", "build_qubo", "energy", "solve",
+           "solve_batch", "solve_params", "workspace_bytes", "select_kernel",
+           "build_params_default", "version", "load", "SbtError", "HIT_DTYPE", "MODES",
+           "KERNELS", "PRECISIONS"]

@@ -71,6 +71,29 @@ class SbtDevResult(C.Structure):
                 ("step_end", C.c_void_p)]
 
 
+SBT_PREC_FP32 = 0
+SBT_PREC_FP16 = 1
+SBT_PREC_BF16 = 2
+
+
+class SbtDevBatch(C.Structure):
+    _fields_ = [("n_events", C.c_int32), ("n", C.POINTER(C.c_int32)), ("nnz", C.POINTER(C.c_int64)),
+                ("a", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("b", C.c_void_p)]
+
+
+class SbtDevBatchResult(C.Structure):
+    _fields_ = [("best_energy", C.c_void_p), ("best_agent", C.c_void_p), ("best_T", C.c_void_p),
+                ("agent_energy", C.c_void_p), ("offset", C.c_void_p), ("trace", C.c_void_p),
+                ("step_begin", C.c_void_p), ("step_end", C.c_void_p), ("agent_T", C.c_void_p),
+                ("agent_x", C.c_void_p)]
+
+
+class SbtBatchResult(C.Structure):
+    _fields_ = [("energy", C.POINTER(C.c_double)), ("best_agent", C.POINTER(C.c_int32)),
+                ("T", C.POINTER(C.c_int8)), ("agent_energy", C.POINTER(C.c_double)),
+                ("trace", C.POINTER(C.c_double)), ("elapsed_s", C.c_double)]
+
+
 # (name, restype, argtypes) of every exported function, as in sbtrack.h
 EXPORTS = [
     ("sbt_last_error", C.c_char_p, []),
@@ -90,6 +113,15 @@ EXPORTS = [
     ("sbt_solve_dev", C.c_int, [C.POINTER(SbtDevQubo), C.c_int32, C.c_int,
                                 C.POINTER(SbtSolveParams), C.c_void_p, C.c_size_t,
                                 C.POINTER(SbtDevResult), C.c_void_p]),
+    ("sbt_batch_workspace_bytes", C.c_size_t, [C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                               C.c_int32, C.POINTER(SbtSolveParams)]),
+    ("sbt_batch_plan", C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int32,
+                                 C.POINTER(SbtSolveParams), C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("sbt_batch_run", C.c_int, [C.POINTER(SbtDevBatch), C.c_int, C.c_int,
+                                C.POINTER(SbtSolveParams), C.c_void_p, C.c_size_t,
+                                C.POINTER(SbtDevBatchResult), C.c_void_p]),
+    ("sbt_solve_batch", C.c_int, [C.POINTER(C.POINTER(SbtQubo)), C.c_int32, C.c_int, C.c_int,
+                                  C.POINTER(SbtSolveParams), C.POINTER(SbtBatchResult)]),
 ]
 
 _LIB = None

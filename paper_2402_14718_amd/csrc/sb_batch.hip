@@ -1,0 +1,467 @@
+// Batched SB over many events in one persistent kernel (gfx950).
+//
+// Paper section "Simulated Bifurcation" (bSB Eq. 5-8, dSB Eq. 9-12) applied
+// to a batch of independent events (the paper solves one event at a time;
+// batching is this library's scheduling, not a change of the method).
+//
+// Work items are (event, group of A agents) with A a power of two chosen so
+// that n_event * A fills one workgroup's slots; items are ordered by
+// decreasing cost and handed out by an atomic counter to a persistent grid
+// of one 1024-thread workgroup per CU.  Inside an item the structure is the
+// register-row resident kernel: positions of the A agents in LDS
+// (spin-major, agent-minor: index i*A + a), momenta and couplings in
+// VGPRs.  Couplings are stored in 16 bits (FP16 or BF16, the reduced
+// precision form) next to a full LDS byte address; accumulation is FP32 and
+// energies FP64.
+//
+// Slot s of thread t is position j = s*1024 + t of the item, spin rank
+// q = j / A in decreasing-row-length order, agent a = j % A (so a thread's
+// slots all belong to agent t % A).  Register capacity per slot follows the
+// row-length profile by rank: slot 0 holds the longest rows.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "sb_device.hpp"
+#include "sb_kernels.hpp"
+
+namespace sbt {
+
+namespace {
+
+constexpr int kB = kBatchTPB;     // threads per workgroup
+constexpr int kS = kBatchSPT;     // slots per thread
+// couplings held in registers per slot (rank profile); rows beyond a
+// slot's capacity continue from global memory
+constexpr int kCap[kS] = {16, 8, 5, 4, 3, 2, 2, 2, 1};
+
+// A held coupling is one VGPR: LDS byte address of the neighbour in the
+// low 16 bits, the 16-bit coupling in the high 16 bits.  FP16 converts
+// inside the multiply-add (v_fma_mix); BF16 is the upper half of an FP32.
+template <int JP>
+__device__ __forceinline__ float packed_j(uint32_t cp) {
+    if constexpr (JP == kJFp16) {
+        return static_cast<float>(__ushort_as_half(static_cast<uint16_t>(cp >> 16)));
+    } else {
+        return __uint_as_float(cp & 0xFFFF0000u);
+    }
+}
+
+template <int JP>
+__device__ __forceinline__ float j16_to_f32(uint16_t bits) {
+    return packed_j<JP>(static_cast<uint32_t>(bits) << 16);
+}
+
+__device__ __forceinline__ float lds_at(const unsigned char *base, uint32_t cp) {
+    return *reinterpret_cast<const float *>(base + (cp & 0xFFFFu));
+}
+
+// Hides a loop-invariant register from the optimiser (an empty asm that
+// "modifies" it) so that values derived from it are recomputed where used
+// instead of being hoisted out of the step loop and kept live: the packed
+// couplings exist to save registers.  Emits no instruction.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+}  // namespace
+
+// Per-event preparation, one workgroup per event: FP32 field h, 16-bit
+// couplings J = -b/4, c0 and the Ising offset C (FP64, fixed order), and
+// the spin order by decreasing row length.
+__global__ __launch_bounds__(256) void batch_prep(BatchArgs B, int jprec) {
+    __shared__ double red[4];
+    __shared__ int wave_tot[4];
+    const int e = blockIdx.x;
+    const BatchEvent E = B.ev[e];
+    const int t = threadIdx.x;
+    double sj = 0.0, sj2 = 0.0, sup = 0.0, sa = 0.0;
+    for (int i = t; i < E.n; i += 256) {
+        const int r0 = B.row_ptr[E.rp_off + i], r1 = B.row_ptr[E.rp_off + i + 1];
+        double rs = 0.0;
+        for (int p = r0; p < r1; ++p) {
+            const double bv = B.b[E.nz_off + p];
+            const double jv = -0.25 * bv;
+            uint16_t bits;
+            if (jprec == kJFp16) {
+                bits = __half_as_ushort(static_cast<__half>(static_cast<_Float16>(jv)));
+            } else {  // BF16: FP32 first, then round to nearest even on the upper half
+                const uint32_t u = __float_as_uint(static_cast<float>(jv));
+                bits = static_cast<uint16_t>((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+            }
+            B.J16[E.nz_off + p] = bits;
+            rs += bv;
+            sj += jv;
+            sj2 += jv * jv;
+            if (B.col[E.nz_off + p] > i) sup += bv;
+        }
+        B.h[E.row_off + i] = static_cast<float>(-(0.5 * B.a[E.row_off + i] + 0.25 * rs));
+        sa += B.a[E.row_off + i];
+    }
+    const double t0 = block_sum(sj, red);
+    const double t1 = block_sum(sj2, red);
+    const double t2 = block_sum(sup, red);
+    const double t3 = block_sum(sa, red);
+    if (t == 0) {
+        const double n2 = static_cast<double>(E.n) * E.n;
+        const double mean = t0 / n2;
+        const double var = t1 / n2 - mean * mean;
+        const double sd = var > 0.0 ? sqrt(var) : 0.0;
+        double c0 = B.c0_fixed > 0.0 ? B.c0_fixed
+                                     : (sd == 0.0 ? 0.5 / sqrt(static_cast<double>(E.n))
+                                                  : 0.5 / (sqrt(static_cast<double>(E.n)) * sd));
+        B.c0[e] = static_cast<float>(c0);
+        B.offset[e] = 0.5 * t3 + 0.25 * t2;
+    }
+    // spin order: decreasing min(row length, 63), ascending id within a length
+    const int lane = t & 63, wave = t >> 6;
+    int base = 0;
+    for (int cls = 63; cls >= 0; --cls) {
+        for (int c0i = 0; c0i < E.n; c0i += 256) {
+            const int i = c0i + t;
+            bool f = false;
+            if (i < E.n) {
+                const int len = B.row_ptr[E.rp_off + i + 1] - B.row_ptr[E.rp_off + i];
+                f = min(len, 63) == cls;
+            }
+            const uint64_t bal = __ballot(f);
+            const int below = __popcll(bal & ((uint64_t(1) << lane) - 1));
+            if (lane == 0) wave_tot[wave] = __popcll(bal);
+            __syncthreads();
+            int woff = 0, tot = 0;
+            for (int w = 0; w < 4; ++w) {
+                woff += (w < wave) ? wave_tot[w] : 0;
+                tot += wave_tot[w];
+            }
+            if (f) B.perm[E.row_off + base + woff + below] = i;
+            base += tot;
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void batch_reset(int *counter) { *counter = 0; }
+
+// Calls f(integral_constant<int, S>) for S = 0 .. kS-1, so per-slot
+// capacities are constant expressions and every register array is indexed
+// with constants.
+template <int S = 0, class F>
+__device__ __forceinline__ void for_slots(F &&f) {
+    if constexpr (S < kS) {
+        f(std::integral_constant<int, S>{});
+        for_slots<S + 1>(f);
+    }
+}
+
+template <int MODE, int JP>
+__global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *xs = reinterpret_cast<float *>(smem);                     // [2][kBatchSlots]
+    double *red = reinterpret_cast<double *>(xs + 2 * kBatchSlots);  // [16][64]
+    int *item_s = reinterpret_cast<int *>(red + 16 * 64);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+
+    for (;;) {
+        if (t == 0) *item_s = atomicAdd(B.counter, 1);
+        __syncthreads();
+        const int item = *item_s;
+        __syncthreads();
+        if (item >= B.n_items) return;
+        const int e = B.item_event[item];
+        const int agent0 = B.item_agent0[item];
+        const BatchEvent E = B.ev[e];
+        const int n = E.n, lgA = E.lg_agents, A = 1 << lgA;
+        const int a = t & (A - 1);
+        const int agent = agent0 + a;
+        const bool agent_ok = agent < B.M;
+
+        float xr[kS], yr[kS], hr[kS];
+        int spin[kS];
+        uint32_t cp0[kCap[0]], cp1[kCap[1]], cp2[kCap[2]], cp3[kCap[3]], cp4[kCap[4]],
+            cp5[kCap[5]], cp6[kCap[6]], cp7[kCap[7]], cp8[kCap[8]];
+        auto cps = [&](auto sc) __attribute__((always_inline)) -> uint32_t * {
+            constexpr int S = decltype(sc)::value;
+            if constexpr (S == 0) return cp0;
+            else if constexpr (S == 1) return cp1;
+            else if constexpr (S == 2) return cp2;
+            else if constexpr (S == 3) return cp3;
+            else if constexpr (S == 4) return cp4;
+            else if constexpr (S == 5) return cp5;
+            else if constexpr (S == 6) return cp6;
+            else if constexpr (S == 7) return cp7;
+            else return cp8;
+        };
+        int need0 = 0, tail = 0, act = 0;
+        for_slots([&](auto sc) __attribute__((always_inline)) {
+            constexpr int S = decltype(sc)::value;
+            constexpr int CAP = kCap[S];
+            uint32_t *cp = cps(sc);
+            const int j = S * kB + t;
+            const int q = j >> lgA;
+            const int i = (q < n && agent_ok) ? B.perm[E.row_off + q] : -1;
+            spin[S] = i;
+            xr[S] = yr[S] = hr[S] = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CAP; ++c) cp[c] = 0;
+            if (i >= 0) {
+                const Philox4 r = philox4x32_10(static_cast<uint32_t>(i), static_cast<uint32_t>(agent),
+                                                static_cast<uint32_t>(E.event_id), 0u, B.seed_lo,
+                                                B.seed_hi);
+                xr[S] = philox_word_to_unit(r.v[0]);
+                yr[S] = philox_word_to_unit(r.v[1]);
+                hr[S] = B.h[E.row_off + i];
+                const int p0 = B.row_ptr[E.rp_off + i], p1 = B.row_ptr[E.rp_off + i + 1];
+#pragma unroll
+                for (int c = 0; c < CAP; ++c) {
+                    if (p0 + c < p1)
+                        cp[c] = static_cast<uint32_t>((B.col[E.nz_off + p0 + c] * A + a) * 4) |
+                                (static_cast<uint32_t>(B.J16[E.nz_off + p0 + c]) << 16);
+                }
+                if (S == 0) need0 = p1 - p0;
+                tail |= (p1 - p0 > CAP) ? 1 : 0;
+                act |= 1 << S;
+                xs[i * A + a] = shared_value<MODE>(xr[S]);
+            }
+        });
+        const int cap0 = wave_max_int(need0);
+        const int any_tail = wave_max_int(tail);
+        int act_w = act;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) act_w |= __shfl_xor(act_w, off, 64);
+        act_w = __builtin_amdgcn_readfirstlane(act_w);
+        __syncthreads();
+
+        const float c0 = B.c0[e];
+        const float dt = B.dt, dta0 = B.dta0;
+        int ck = 0;
+
+        // per-agent FP64 energy of the current state (Eq. 13); the total of
+        // agent t is returned in threads t < A
+        auto agent_energy = [&](const float *xv) __attribute__((always_inline)) -> double {
+            double v = 0.0;
+            for_slots([&](auto sc) __attribute__((always_inline)) {
+                constexpr int S = decltype(sc)::value;
+                const int i = static_cast<int>(opaque(static_cast<uint32_t>(spin[S])));
+                if (i >= 0 && xr[S] >= 0.0f) {
+                    double er = B.a[E.row_off + i];
+                    const int p0 = B.row_ptr[E.rp_off + i], p1 = B.row_ptr[E.rp_off + i + 1];
+                    for (int p = p0; p < p1; ++p) {
+                        const int c = B.col[E.nz_off + p];
+                        if (c > i && xv[c * A + a] >= 0.0f) er += B.b[E.nz_off + p];
+                    }
+                    v += er;
+                }
+            });
+            // lanes with equal t % A hold the same agent
+            for (int off = 32; off >= A; off >>= 1) v += __shfl_xor(v, off, 64);
+            red[wave * 64 + lane] = v;
+            __syncthreads();
+            // agent t: lane t of every wave when A <= 64; otherwise lane
+            // t % 64 of the waves whose first agent is t rounded down to 64
+            double tot = 0.0;
+            if (t < A) {
+                for (int w = 0; w < kB / 64; ++w) {
+                    if (A <= 64)
+                        tot += red[w * 64 + t];
+                    else if (((w * 64) & (A - 1)) == (t & ~63))
+                        tot += red[w * 64 + (t & 63)];
+                }
+            }
+            __syncthreads();
+            return tot;
+        };
+
+        auto step = [&](auto bufc, int k) __attribute__((always_inline)) {
+            constexpr int BUF = decltype(bufc)::value;
+            const unsigned char *xc = smem + BUF * kBatchSlots * 4;
+            float *xn = xs + (BUF ^ 1) * kBatchSlots;
+            const float g = B.sched[k];
+            float acc[kS];
+            for_slots([&](auto sc) __attribute__((always_inline)) { acc[decltype(sc)::value] = hr[decltype(sc)::value]; });
+            // slots 1..: fixed capacity; their gathers are issued after slot 0
+            // has been summed, which bounds the registers in flight
+            float v1[kCap[1]], v2[kCap[2]], v3[kCap[3]], v4[kCap[4]], v5[kCap[5]], v6[kCap[6]],
+                v7[kCap[7]], v8[kCap[8]];
+            auto vs = [&](auto sc) __attribute__((always_inline)) -> float * {
+                constexpr int S = decltype(sc)::value;
+                if constexpr (S == 1) return v1;
+                else if constexpr (S == 2) return v2;
+                else if constexpr (S == 3) return v3;
+                else if constexpr (S == 4) return v4;
+                else if constexpr (S == 5) return v5;
+                else if constexpr (S == 6) return v6;
+                else if constexpr (S == 7) return v7;
+                else return v8;
+            };
+            // slot 0: as many gathers as the wave's longest row needs
+            auto slot0 = [&](auto cc) __attribute__((always_inline)) {
+                constexpr int C = decltype(cc)::value;
+                float v0[C];
+                uint32_t w0[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) w0[c] = opaque(cp0[c]);
+#pragma unroll
+                for (int c = 0; c < C; ++c) v0[c] = lds_at(xc, w0[c]);
+#pragma unroll
+                for (int c = 0; c < C; ++c) acc[0] = __builtin_fmaf(packed_j<JP>(w0[c]), v0[c], acc[0]);
+            };
+            if (cap0 <= 4)
+                slot0(std::integral_constant<int, 4>{});
+            else if (cap0 <= 8)
+                slot0(std::integral_constant<int, 8>{});
+            else
+                slot0(std::integral_constant<int, kCap[0]>{});
+            for_slots([&](auto sc) __attribute__((always_inline)) {
+                constexpr int S = decltype(sc)::value;
+                if constexpr (S > 0) {
+                    if (act_w & (1 << S)) {
+                        float *v = vs(sc);
+                        const uint32_t *cp = cps(sc);
+#pragma unroll
+                        for (int c = 0; c < kCap[S]; ++c) v[c] = lds_at(xc, opaque(cp[c]));
+                    }
+                }
+            });
+            for_slots([&](auto sc) __attribute__((always_inline)) {
+                constexpr int S = decltype(sc)::value;
+                if constexpr (S > 0) {
+                    if (act_w & (1 << S)) {
+                        const float *v = vs(sc);
+                        const uint32_t *cp = cps(sc);
+#pragma unroll
+                        for (int c = 0; c < kCap[S]; ++c)
+                            acc[S] = __builtin_fmaf(packed_j<JP>(opaque(cp[c])), v[c], acc[S]);
+                    }
+                }
+            });
+            if (any_tail) {
+                const float *xcf = reinterpret_cast<const float *>(xc);
+                for_slots([&](auto sc) __attribute__((always_inline)) {
+                    constexpr int S = decltype(sc)::value;
+                    const int i = static_cast<int>(opaque(static_cast<uint32_t>(spin[S])));
+                    if (i >= 0) {
+                        const int p1 = B.row_ptr[E.rp_off + i + 1];
+                        for (int p = B.row_ptr[E.rp_off + i] + kCap[S]; p < p1; ++p)
+                            acc[S] = __builtin_fmaf(j16_to_f32<JP>(B.J16[E.nz_off + p]),
+                                                    xcf[B.col[E.nz_off + p] * A + a], acc[S]);
+                    }
+                });
+            }
+            for_slots([&](auto sc) __attribute__((always_inline)) {
+                constexpr int S = decltype(sc)::value;
+                if (spin[S] >= 0) {
+                    sb_update(xr[S], yr[S], acc[S], c0, g, dt, dta0);
+                    const uint32_t w = opaque(static_cast<uint32_t>(spin[S]));
+                    xn[static_cast<int>(w) * A + a] = shared_value<MODE>(xr[S]);
+                }
+            });
+            __syncthreads();
+            if (B.ckpt_every > 0 && (k + 1) % B.ckpt_every == 0) {
+                const double en = agent_energy(xn);
+                if (t < A && agent0 + t < B.M)
+                    B.etrace[(static_cast<size_t>(e) * B.n_ckpt + ck) * B.M + agent0 + t] = en;
+                ++ck;
+            }
+        };
+        int k = 0;
+        for (; k + 1 < B.K; k += 2) {
+            step(std::integral_constant<int, 0>{}, k);
+            step(std::integral_constant<int, 1>{}, k + 1);
+        }
+        if (k < B.K) step(std::integral_constant<int, 0>{}, k);
+        const float *xfin = xs + (B.K & 1) * kBatchSlots;
+        const double en = agent_energy(xfin);
+        if (t < A && agent0 + t < B.M) B.energy[static_cast<size_t>(e) * B.M + agent0 + t] = en;
+        for_slots([&](auto sc) __attribute__((always_inline)) {
+            constexpr int S = decltype(sc)::value;
+            const int i = spin[S];
+            if (i >= 0) {
+                const size_t o = (static_cast<size_t>(E.row_off) + i) * B.M + agent;
+                B.T[o] = xr[S] >= 0.0f ? 1 : 0;
+                if (B.x_out) B.x_out[o] = xr[S];
+            }
+        });
+        __syncthreads();
+    }
+}
+
+// Per event: best agent (minimum energy, lowest index on ties), its T,
+// and the best-so-far trace over checkpoints.
+__global__ __launch_bounds__(256) void batch_select(BatchArgs B) {
+    __shared__ double se[256];
+    __shared__ int sm[256];
+    const int e = blockIdx.x, t = threadIdx.x;
+    const BatchEvent E = B.ev[e];
+    double be = INFINITY;
+    int bm = 0x7fffffff;
+    for (int m = t; m < B.M; m += 256) {
+        const double v = B.energy[static_cast<size_t>(e) * B.M + m];
+        if (v < be || (v == be && m < bm)) {
+            be = v;
+            bm = m;
+        }
+    }
+    se[t] = be;
+    sm[t] = bm;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (t < w && (se[t + w] < se[t] || (se[t + w] == se[t] && sm[t + w] < sm[t]))) {
+            se[t] = se[t + w];
+            sm[t] = sm[t + w];
+        }
+        __syncthreads();
+    }
+    const int best = sm[0];
+    if (t == 0) {
+        B.best_energy[e] = se[0];
+        B.best_agent[e] = best;
+    }
+    if (best >= 0 && best < B.M)
+        for (int i = t; i < E.n; i += 256)
+            B.best_T[E.row_off + i] = B.T[(static_cast<size_t>(E.row_off) + i) * B.M + best];
+    if (B.trace && B.n_ckpt > 0) {
+        double bsf = INFINITY;
+        for (int c = 0; c < B.n_ckpt; ++c) {
+            double v = INFINITY;
+            for (int m = t; m < B.M; m += 256)
+                v = fmin(v, B.etrace[(static_cast<size_t>(e) * B.n_ckpt + c) * B.M + m]);
+            se[t] = v;
+            __syncthreads();
+            for (int w = 128; w >= 1; w >>= 1) {
+                if (t < w) se[t] = fmin(se[t], se[t + w]);
+                __syncthreads();
+            }
+            bsf = fmin(bsf, se[0]);
+            if (t == 0) B.trace[static_cast<size_t>(e) * B.n_ckpt + c] = bsf;
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_batch_prep(int jprec, const BatchArgs &B, hipStream_t st) {
+    batch_prep<<<B.E, 256, 0, st>>>(B, jprec);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream_t st) {
+    batch_reset<<<1, 1, 0, st>>>(B.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = sizeof(float) * 2 * kBatchSlots + sizeof(double) * 16 * 64 + 16;
+    const dim3 grid(B.grid), block(kB);
+    if (mode == kDSB)
+        return jprec == kJFp16 ? launch_with_lds(sb_batch<kDSB, kJFp16>, grid, block, lds, st, B)
+                               : launch_with_lds(sb_batch<kDSB, kJBf16>, grid, block, lds, st, B);
+    return jprec == kJFp16 ? launch_with_lds(sb_batch<kBSB, kJFp16>, grid, block, lds, st, B)
+                           : launch_with_lds(sb_batch<kBSB, kJBf16>, grid, block, lds, st, B);
+}
+
+hipError_t launch_batch_select(const BatchArgs &B, hipStream_t st) {
+    batch_select<<<B.E, 256, 0, st>>>(B);
+    return hipGetLastError();
+}
+
+}  // namespace sbt

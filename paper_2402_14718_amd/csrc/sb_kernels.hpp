@@ -53,6 +53,56 @@ struct StreamArgs {
     const float *sched;          // [K] a0 - a_k
 };
 
+// ---------------------------------------------------------------- batch
+
+constexpr int kBatchTPB = 1024;                     // threads per workgroup
+constexpr int kBatchSPT = 9;                        // slots per thread
+constexpr int kBatchSlots = kBatchTPB * kBatchSPT;  // largest n * agents per item
+enum : int { kJFp16 = 0, kJBf16 = 1 };              // 16-bit coupling formats
+
+struct BatchEvent {
+    int n, nnz;
+    int row_off;                 // offset into per-spin arrays (a, h, perm, best_T, T rows)
+    int rp_off;                  // offset into row_ptr (row_off + event index)
+    int nz_off;                  // offset into col, b, J16
+    int lg_agents;               // log2 of the agents one work item holds
+    int event_id;                // Philox counter word 2
+    int pad;
+};
+
+struct BatchArgs {
+    int E, M, K, n_items, grid, ckpt_every, n_ckpt;
+    uint32_t seed_lo, seed_hi;
+    float dt, dta0;
+    double c0_fixed;             // > 0: fixed c0 for every event
+    const BatchEvent *ev;        // [E]
+    const int *item_event;       // [n_items], decreasing cost
+    const int *item_agent0;      // [n_items]
+    const int *row_ptr;          // [sum (n + 1)] per-event row pointers (local)
+    const int *col;              // [sum nnz] per-event spin ids (local)
+    const double *a;             // [sum n]
+    const double *b;             // [sum nnz]
+    uint16_t *J16;               // [sum nnz] 16-bit couplings (prep output)
+    float *h;                    // [sum n]
+    float *c0;                   // [E]
+    double *offset;              // [E] Ising offset C
+    int *perm;                   // [sum n] spin order per event
+    const float *sched;          // [K]
+    int *counter;                // work queue
+    double *etrace;              // [E * n_ckpt * M]
+    double *energy;              // [E * M] final O(T)
+    double *trace;               // [E * n_ckpt] best so far, or null
+    double *best_energy;         // [E]
+    int *best_agent;             // [E]
+    int8_t *T;                   // [sum n * M] final T per agent
+    float *x_out;                // [sum n * M] final positions, or null
+    int8_t *best_T;              // [sum n]
+};
+
+hipError_t launch_batch_prep(int jprec, const BatchArgs &B, hipStream_t st);
+hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream_t st);
+hipError_t launch_batch_select(const BatchArgs &B, hipStream_t st);
+
 hipError_t launch_prep(int n, const double *a, const int *row_ptr, const int *col, const double *b,
                        float *J, float *h, double *part, double *scal, double c0_fixed,
                        hipStream_t st);

@@ -1,0 +1,405 @@
+// Host side of the batched solver: workspace layout, the work-item
+// schedule, and the sbt_batch_* / sbt_solve_batch entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "common.hpp"
+#include "sb_kernels.hpp"
+#include "sbtrack.h"
+
+namespace {
+
+using sbt::fail;
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Schedule {
+    std::vector<sbt::BatchEvent> ev;
+    std::vector<int32_t> item_event, item_agent0;
+    int64_t sum_n = 0, sum_nnz = 0;
+};
+
+// Agents per work item: the largest power of two with n * A within one
+// workgroup's slots (and A <= agents, A <= threads per workgroup).
+int lg_agents_for(int32_t n, int32_t M) {
+    int lg = 0;
+    while ((2 << lg) <= M && (2 << lg) <= sbt::kBatchTPB &&
+           static_cast<int64_t>(n) * (2 << lg) <= sbt::kBatchSlots)
+        ++lg;
+    return lg;
+}
+
+int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const sbt_solve_params &p,
+                  Schedule &S, const char *who) {
+    if (E < 1) return fail(SBT_EINVAL, "%s: n_events must be >= 1", who);
+    if (!n || !nnz) return fail(SBT_EINVAL, "%s: n or nnz is NULL", who);
+    S.ev.resize(E);
+    struct Item {
+        int64_t cost;
+        int32_t e, a0;
+    };
+    std::vector<Item> items;
+    int64_t row_off = 0, nz_off = 0;
+    for (int32_t e = 0; e < E; ++e) {
+        if (n[e] < 1) return fail(SBT_EINVAL, "%s: event %d has n = %d", who, e, n[e]);
+        if (n[e] > sbt::kBatchSlots)
+            return fail(SBT_EUNSUPPORTED, "%s: event %d has %d variables (batched limit %d)", who,
+                        e, n[e], sbt::kBatchSlots);
+        if (nnz[e] < 0) return fail(SBT_EINVAL, "%s: event %d has nnz < 0", who, e);
+        sbt::BatchEvent &d = S.ev[e];
+        d.n = n[e];
+        d.nnz = static_cast<int>(nnz[e]);
+        d.row_off = static_cast<int>(row_off);
+        d.rp_off = static_cast<int>(row_off + e);
+        d.nz_off = static_cast<int>(nz_off);
+        d.lg_agents = lg_agents_for(n[e], p.agents);
+        d.event_id = p.event + e;
+        d.pad = 0;
+        const int A = 1 << d.lg_agents;
+        for (int a0 = 0; a0 < p.agents; a0 += A) {
+            const int used = std::min(A, p.agents - a0);
+            items.push_back({(static_cast<int64_t>(n[e]) + nnz[e]) * used, e, a0});
+        }
+        row_off += n[e];
+        nz_off += nnz[e];
+        if (row_off + e + 1 > INT32_MAX / 2 || nz_off > INT32_MAX / 2)
+            return fail(SBT_EINVAL, "%s: batch too large for 32-bit offsets", who);
+    }
+    // longest items first (ties: event, then agent order)
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item &l, const Item &r) { return l.cost > r.cost; });
+    S.item_event.resize(items.size());
+    S.item_agent0.resize(items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+        S.item_event[k] = items[k].e;
+        S.item_agent0[k] = items[k].a0;
+    }
+    S.sum_n = row_off;
+    S.sum_nnz = nz_off;
+    return SBT_OK;
+}
+
+struct BatchLayout {
+    size_t ev, item_e, item_a, J16, h, c0, offset, perm, sched, counter, etrace, energy, T;
+    size_t total;
+    int n_ckpt;
+};
+
+BatchLayout make_layout(const Schedule &S, const sbt_solve_params &p) {
+    BatchLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    const size_t E = S.ev.size(), I = S.item_event.size(), M = static_cast<size_t>(p.agents);
+    L.n_ckpt = p.energy_every > 0 ? p.steps / p.energy_every : 0;
+    L.ev = take(sizeof(sbt::BatchEvent) * E);
+    L.item_e = take(sizeof(int32_t) * I);
+    L.item_a = take(sizeof(int32_t) * I);
+    L.J16 = take(sizeof(uint16_t) * static_cast<size_t>(S.sum_nnz));
+    L.h = take(sizeof(float) * static_cast<size_t>(S.sum_n));
+    L.c0 = take(sizeof(float) * E);
+    L.offset = take(sizeof(double) * E);
+    L.perm = take(sizeof(int32_t) * static_cast<size_t>(S.sum_n));
+    L.sched = take(sizeof(float) * static_cast<size_t>(p.steps));
+    L.counter = take(sizeof(int32_t));
+    L.etrace = take(sizeof(double) * E * static_cast<size_t>(L.n_ckpt) * M);
+    L.energy = take(sizeof(double) * E * M);
+    L.T = take(static_cast<size_t>(S.sum_n) * M);
+    L.total = off;
+    return L;
+}
+
+int check_batch_params(const sbt_solve_params &p, const char *who) {
+    if (!(p.a0 > 0.0) || !std::isfinite(p.a0) || !(p.dt > 0.0) || !std::isfinite(p.dt))
+        return fail(SBT_EINVAL, "%s: a0 and dt must be finite and > 0", who);
+    if (std::isinf(p.c0)) return fail(SBT_EINVAL, "%s: c0 is infinite", who);
+    if (p.agents < 1 || p.steps < 1 || p.energy_every < 0 || p.event < 0)
+        return fail(SBT_EINVAL, "%s: invalid agents, steps, energy_every or event", who);
+    return SBT_OK;
+}
+
+int cu_count() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 256;
+    return v > 0 ? v : 256;
+}
+
+#define SBT_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(SBT_EDEVICE, "%s: %s failed: %s", who, #call, hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+extern "C" size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                                            const sbt_solve_params *p) {
+    sbt::clear_error();
+    const char *who = "sbt_batch_workspace_bytes";
+    if (!p) {
+        fail(SBT_EINVAL, "%s: params is NULL", who);
+        return 0;
+    }
+    if (check_batch_params(*p, who)) return 0;
+    Schedule S;
+    if (make_schedule(n, nnz, n_events, *p, S, who)) return 0;
+    return make_layout(S, *p).total;
+}
+
+extern "C" int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                              const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
+                              void *stream) {
+    const char *who = "sbt_batch_plan";
+    sbt::clear_error();
+    if (!p) return fail(SBT_EINVAL, "%s: params is NULL", who);
+    int rc = check_batch_params(*p, who);
+    if (rc) return rc;
+    Schedule S;
+    rc = make_schedule(n, nnz, n_events, *p, S, who);
+    if (rc) return rc;
+    const BatchLayout L = make_layout(S, *p);
+    if (!workspace || workspace_bytes < L.total)
+        return fail(SBT_EINVAL, "%s: workspace of %zu bytes is smaller than the %zu needed", who,
+                    workspace_bytes, L.total);
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SBT_HIP(hipMemcpyAsync(ws + L.ev, S.ev.data(), sizeof(sbt::BatchEvent) * S.ev.size(),
+                           hipMemcpyHostToDevice, st));
+    SBT_HIP(hipMemcpyAsync(ws + L.item_e, S.item_event.data(), sizeof(int32_t) * S.item_event.size(),
+                           hipMemcpyHostToDevice, st));
+    SBT_HIP(hipMemcpyAsync(ws + L.item_a, S.item_agent0.data(),
+                           sizeof(int32_t) * S.item_agent0.size(), hipMemcpyHostToDevice, st));
+    SBT_HIP(hipStreamSynchronize(st));
+    return static_cast<int>(S.item_event.size());
+}
+
+extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_precision prec,
+                             const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
+                             const sbt_dev_batch_result *out, void *stream) {
+    const char *who = "sbt_batch_run";
+    sbt::clear_error();
+    if (!batch || !p || !out) return fail(SBT_EINVAL, "%s: NULL argument", who);
+    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "%s: unknown mode", who);
+    if (prec != SBT_PREC_FP16 && prec != SBT_PREC_BF16)
+        return fail(SBT_EUNSUPPORTED, "%s: batches hold 16-bit couplings (FP16 or BF16)", who);
+    int rc = check_batch_params(*p, who);
+    if (rc) return rc;
+    Schedule S;
+    rc = make_schedule(batch->n, batch->nnz, batch->n_events, *p, S, who);
+    if (rc) return rc;
+    const BatchLayout L = make_layout(S, *p);
+    if (!workspace || workspace_bytes < L.total)
+        return fail(SBT_EINVAL, "%s: workspace of %zu bytes is smaller than the %zu needed", who,
+                    workspace_bytes, L.total);
+    if (!batch->a || !batch->row_ptr || (S.sum_nnz > 0 && (!batch->col || !batch->b)))
+        return fail(SBT_EINVAL, "%s: batch array is NULL", who);
+    if (!out->best_energy || !out->best_agent || !out->best_T)
+        return fail(SBT_EINVAL, "%s: result pointer is NULL", who);
+    if (out->trace && L.n_ckpt == 0)
+        return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    sbt::BatchArgs B{};
+    B.E = batch->n_events;
+    B.M = p->agents;
+    B.K = p->steps;
+    B.n_items = static_cast<int>(S.item_event.size());
+    B.grid = std::min(B.n_items, cu_count());
+    B.ckpt_every = p->energy_every;
+    B.n_ckpt = L.n_ckpt;
+    B.seed_lo = static_cast<uint32_t>(p->seed & 0xffffffffu);
+    B.seed_hi = static_cast<uint32_t>(p->seed >> 32);
+    B.dt = static_cast<float>(p->dt);
+    B.dta0 = static_cast<float>(p->dt * p->a0);
+    B.c0_fixed = (std::isnan(p->c0) || p->c0 <= 0.0) ? 0.0 : p->c0;
+    B.ev = reinterpret_cast<const sbt::BatchEvent *>(ws + L.ev);
+    B.item_event = reinterpret_cast<const int *>(ws + L.item_e);
+    B.item_agent0 = reinterpret_cast<const int *>(ws + L.item_a);
+    B.row_ptr = batch->row_ptr;
+    B.col = batch->col;
+    B.a = batch->a;
+    B.b = batch->b;
+    B.J16 = reinterpret_cast<uint16_t *>(ws + L.J16);
+    B.h = reinterpret_cast<float *>(ws + L.h);
+    B.c0 = reinterpret_cast<float *>(ws + L.c0);
+    B.offset = out->offset ? out->offset : reinterpret_cast<double *>(ws + L.offset);
+    B.perm = reinterpret_cast<int *>(ws + L.perm);
+    B.sched = reinterpret_cast<const float *>(ws + L.sched);
+    B.counter = reinterpret_cast<int *>(ws + L.counter);
+    B.etrace = reinterpret_cast<double *>(ws + L.etrace);
+    B.energy = out->agent_energy ? out->agent_energy : reinterpret_cast<double *>(ws + L.energy);
+    B.trace = out->trace;
+    B.best_energy = out->best_energy;
+    B.best_agent = out->best_agent;
+    B.T = out->agent_T ? out->agent_T : reinterpret_cast<int8_t *>(ws + L.T);
+    B.x_out = out->agent_x;
+    B.best_T = out->best_T;
+
+    SBT_HIP(sbt::launch_schedule(p->steps, p->a0, reinterpret_cast<float *>(ws + L.sched), st));
+    const int jprec = prec == SBT_PREC_FP16 ? sbt::kJFp16 : sbt::kJBf16;
+    rc = 0;
+    {
+        hipError_t e = sbt::launch_batch_prep(jprec, B, st);
+        if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch prep: %s", who, hipGetErrorString(e));
+        if (out->step_begin) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_begin), st));
+        e = sbt::launch_batch_steps(static_cast<int>(mode), jprec, B, st);  // SBT_BSB/DSB = 0/1
+        if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch kernel: %s", who, hipGetErrorString(e));
+        if (out->step_end) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_end), st));
+        e = sbt::launch_batch_select(B, st);
+        if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch select: %s", who, hipGetErrorString(e));
+    }
+    return SBT_OK;
+}
+
+// ----------------------------------------------------------- host batch
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+extern "C" int sbt_solve_batch(const sbt_qubo *const *qs, int32_t E, sbt_mode mode,
+                               sbt_precision prec, const sbt_solve_params *pp,
+                               sbt_batch_result *out) {
+    const char *who = "sbt_solve_batch";
+    sbt::clear_error();
+    if (!qs || !out || !out->energy || !out->best_agent)
+        return fail(SBT_EINVAL, "%s: NULL argument", who);
+    if (E < 1) return fail(SBT_EINVAL, "%s: n_events must be >= 1", who);
+    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "%s: unknown mode", who);
+    if (prec != SBT_PREC_FP16 && prec != SBT_PREC_BF16)
+        return fail(SBT_EUNSUPPORTED, "%s: batches hold 16-bit couplings (FP16 or BF16)", who);
+    sbt_solve_params p;
+    if (pp)
+        p = *pp;
+    else
+        sbt_solve_params_default(&p);
+    std::vector<int32_t> n(E);
+    std::vector<int64_t> nnz(E);
+    int64_t sum_n = 0, sum_nnz = 0;
+    for (int32_t e = 0; e < E; ++e) {
+        const sbt_qubo *q = qs[e];
+        if (!q || q->n < 1 || !q->a || !q->row_ptr || (q->nnz > 0 && (!q->col || !q->b)))
+            return fail(SBT_EINVAL, "%s: event %d is empty or malformed", who, e);
+        if (q->row_ptr[0] != 0 || q->row_ptr[q->n] != q->nnz)
+            return fail(SBT_EINVAL, "%s: event %d row_ptr does not span [0, nnz]", who, e);
+        for (int32_t i = 0; i < q->n; ++i) {
+            if (!std::isfinite(q->a[i])) return fail(SBT_EINVAL, "%s: event %d: a not finite", who, e);
+            for (int64_t k = q->row_ptr[i]; k < q->row_ptr[i + 1]; ++k) {
+                const int32_t j = q->col[k];
+                if (j < 0 || j >= q->n || j == i || (k > q->row_ptr[i] && q->col[k - 1] >= j) ||
+                    !std::isfinite(q->b[k]))
+                    return fail(SBT_EINVAL, "%s: event %d: malformed row %d", who, e, i);
+                const int32_t *c0 = q->col + q->row_ptr[j], *c1 = q->col + q->row_ptr[j + 1];
+                const int32_t *f = std::lower_bound(c0, c1, i);
+                if (f == c1 || *f != i || q->b[q->row_ptr[j] + (f - c0)] != q->b[k])
+                    return fail(SBT_EINVAL, "%s: event %d: b is not symmetric", who, e);
+            }
+        }
+        n[e] = q->n;
+        nnz[e] = q->nnz;
+        sum_n += q->n;
+        sum_nnz += q->nnz;
+    }
+    std::vector<double> a(sum_n), b(std::max<int64_t>(sum_nnz, 1));
+    std::vector<int32_t> rp(sum_n + E), col(std::max<int64_t>(sum_nnz, 1));
+    {
+        int64_t ro = 0, zo = 0;
+        for (int32_t e = 0; e < E; ++e) {
+            const sbt_qubo *q = qs[e];
+            std::copy(q->a, q->a + q->n, a.begin() + ro);
+            for (int32_t i = 0; i <= q->n; ++i) rp[ro + e + i] = static_cast<int32_t>(q->row_ptr[i]);
+            std::copy(q->col, q->col + q->nnz, col.begin() + zo);
+            std::copy(q->b, q->b + q->nnz, b.begin() + zo);
+            ro += q->n;
+            zo += q->nnz;
+        }
+    }
+    int rc0 = check_batch_params(p, who);
+    if (rc0) return rc0;
+    {
+        Schedule S;
+        rc0 = make_schedule(n.data(), nnz.data(), E, p, S, who);
+        if (rc0) return rc0;
+    }
+    const size_t ws_bytes = sbt_batch_workspace_bytes(n.data(), nnz.data(), E, &p);
+    if (ws_bytes == 0) return SBT_EINVAL;
+    const int n_ck = p.energy_every > 0 ? p.steps / p.energy_every : 0;
+    if (out->trace && n_ck == 0)
+        return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
+    DevBuf da, drp, dcol, db, dws, dbe, dba, dbt, dae, dtr;
+    const size_t M = static_cast<size_t>(p.agents);
+    if (hipMalloc(&da.p, sizeof(double) * sum_n) || hipMalloc(&drp.p, sizeof(int32_t) * rp.size()) ||
+        hipMalloc(&dcol.p, sizeof(int32_t) * col.size()) || hipMalloc(&db.p, sizeof(double) * b.size()) ||
+        hipMalloc(&dws.p, ws_bytes) || hipMalloc(&dbe.p, sizeof(double) * E) ||
+        hipMalloc(&dba.p, sizeof(int32_t) * E) || hipMalloc(&dbt.p, sum_n) ||
+        hipMalloc(&dae.p, sizeof(double) * E * M) ||
+        (out->trace && hipMalloc(&dtr.p, sizeof(double) * E * n_ck)))
+        return fail(SBT_ENOMEM, "%s: device allocation failed", who);
+    hipStream_t st = nullptr;
+    SBT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { (void)hipStreamDestroy(s); }
+    } guard{st};
+    SBT_HIP(hipMemcpyAsync(da.p, a.data(), sizeof(double) * sum_n, hipMemcpyHostToDevice, st));
+    SBT_HIP(hipMemcpyAsync(drp.p, rp.data(), sizeof(int32_t) * rp.size(), hipMemcpyHostToDevice, st));
+    SBT_HIP(hipMemcpyAsync(dcol.p, col.data(), sizeof(int32_t) * col.size(), hipMemcpyHostToDevice, st));
+    SBT_HIP(hipMemcpyAsync(db.p, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, st));
+    hipEvent_t e0, e1;
+    SBT_HIP(hipEventCreate(&e0));
+    SBT_HIP(hipEventCreate(&e1));
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } eg{e0, e1};
+    SBT_HIP(hipEventRecord(e0, st));
+    int rc = sbt_batch_plan(n.data(), nnz.data(), E, &p, dws.p, ws_bytes, st);
+    if (rc < 0) return rc;
+    sbt_dev_batch dbch{E, n.data(), nnz.data(), static_cast<const double *>(da.p),
+                       static_cast<const int32_t *>(drp.p), static_cast<const int32_t *>(dcol.p),
+                       static_cast<const double *>(db.p)};
+    sbt_dev_batch_result dr{};
+    dr.best_energy = static_cast<double *>(dbe.p);
+    dr.best_agent = static_cast<int32_t *>(dba.p);
+    dr.best_T = static_cast<int8_t *>(dbt.p);
+    dr.agent_energy = static_cast<double *>(dae.p);
+    dr.trace = static_cast<double *>(dtr.p);
+    rc = sbt_batch_run(&dbch, mode, prec, &p, dws.p, ws_bytes, &dr, st);
+    if (rc) return rc;
+    SBT_HIP(hipEventRecord(e1, st));
+    SBT_HIP(hipMemcpyAsync(out->energy, dbe.p, sizeof(double) * E, hipMemcpyDeviceToHost, st));
+    SBT_HIP(hipMemcpyAsync(out->best_agent, dba.p, sizeof(int32_t) * E, hipMemcpyDeviceToHost, st));
+    if (out->T) SBT_HIP(hipMemcpyAsync(out->T, dbt.p, sum_n, hipMemcpyDeviceToHost, st));
+    if (out->agent_energy)
+        SBT_HIP(hipMemcpyAsync(out->agent_energy, dae.p, sizeof(double) * E * M, hipMemcpyDeviceToHost, st));
+    if (out->trace)
+        SBT_HIP(hipMemcpyAsync(out->trace, dtr.p, sizeof(double) * E * n_ck, hipMemcpyDeviceToHost, st));
+    SBT_HIP(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    SBT_HIP(hipEventElapsedTime(&ms, e0, e1));
+    out->elapsed_s = 1e-3 * ms;
+    return SBT_OK;
+}

@@ -1,0 +1,172 @@
+"""GPU parity of the batched, reduced-precision solver (sbt_batch_* through
+the C ABI) against the FP64 oracle.
+
+The batch holds couplings in 16 bits (FP16 or BF16).  The oracle is run
+with the same rounded couplings (FP16: one rounding of the FP64 J; BF16:
+FP64 -> FP32 -> BF16 round-to-nearest-even), everything else in FP64, so
+the FP32 trajectories must stay within 1e-5 relative over 50 steps as for
+the FP32 path.  Energies of the returned spins are exact FP64 (1e-9); the
+quality against plain FP32 solves is compared at full length.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import trackgen as tg
+from oracle import energy as oenergy
+from oracle import ising as oising
+from oracle import sb as osb
+from oracle import tracks as otracks
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2402_14718_amd as sbt  # noqa: E402
+
+
+def q_fp16(J):
+    return J.astype(np.float16).astype(np.float64)
+
+
+def q_bf16(J):
+    u = J.astype(np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+QUANT = {"fp16": q_fp16, "bf16": q_bf16}
+
+
+def _events(specs_seeds):
+    evs, qs = [], []
+    for spec, seed in specs_seeds:
+        ev = tg.generate(spec, seed)
+        evs.append(ev)
+        qs.append(sbt.build_qubo(ev.hits_struct()))
+    return evs, qs
+
+
+def _oracle_run(q, prec, mode, M, K, seed, event):
+    b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
+    isg = oising.from_qubo(q.a, b)
+    Jq = isg.J.copy()
+    Jq.data = QUANT[prec](Jq.data)
+    return b, isg, osb.run(Jq, isg.h, isg.c0, mode, M, K, seed=seed, event=event,
+                           margin_steps=K)
+
+
+SMALL = [(tg.plain_spec(30), 1), (tg.tiny_spec(), 4), (tg.plain_spec(60), 2),
+         (tg.plain_spec(150), 3)]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+def test_batch_trajectories_match_oracle_with_rounded_couplings(prec, mode):
+    evs, qs = _events(SMALL)
+    M, K, seed = 64, 50, 21
+    ds = sbt.DeviceBatchSolver(qs, mode, prec, sbt.solve_params(agents=M, steps=K, seed=seed),
+                               want_agent_energy=True, want_agent_state=True)
+    ds.run()
+    r = ds.result()
+    for e, q in enumerate(qs):
+        b, isg, ref = _oracle_run(q, prec, mode, M, K, seed, e)
+        x = r["agent_x"][e]
+        err = np.linalg.norm(x - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
+        close = ref.wall_margin < 1e-6
+        if mode == "dsb":
+            close |= ref.sign_margin < 1e-6
+        assert np.all((err <= 1e-5) | close), (e, err.max())
+        T = r["agent_T"][e]
+        assert np.array_equal(T, (x >= 0).astype(np.int8))
+        e_or = oenergy.qubo_energy(q.a, b, T)
+        assert np.allclose(r["agent_energy"][e], e_or, rtol=1e-12, atol=1e-9)
+        best = oenergy.best_agent(e_or)
+        assert r["best_agent"][e] == best
+        assert np.array_equal(r["T"][e], T[:, best])
+        assert abs(r["offset"][e] - isg.C) <= 1e-9 * max(1.0, abs(isg.C))
+
+
+def test_batch_ragged_agents_and_event_sizes():
+    """100 agents (work items of 64 + 36), events from 1 to ~2000 variables."""
+    rng = np.random.default_rng(7)
+    qs = []
+    for n in (1, 3, 257, 1000, 2100):
+        rows, cols, vals = [], [], []
+        for i in range(n - 1):
+            w = 1.0 if rng.random() < 0.3 else -rng.uniform(0.2, 1.0)
+            rows += [i, i + 1]
+            cols += [i + 1, i]
+            vals += [w, w]
+        b = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+        b.sort_indices()
+        qs.append(sbt.Qubo(n, rng.uniform(0, 0.7, n), b.indptr.astype(np.int64),
+                           b.indices.astype(np.int32), b.data.copy(), np.zeros((n, 3), np.int64)))
+    M, K = 100, 9
+    ds = sbt.DeviceBatchSolver(qs, "dsb", "fp16", sbt.solve_params(agents=M, steps=K, seed=3),
+                               want_agent_energy=True, want_agent_state=True)
+    ds.run()
+    r = ds.result()
+    for e, q in enumerate(qs):
+        b, isg, ref = _oracle_run(q, "fp16", "dsb", M, K, 3, e)
+        assert np.allclose(r["agent_x"][e], ref.x, rtol=0, atol=1e-5)
+        e_or = oenergy.qubo_energy(q.a, b, r["agent_T"][e])
+        assert np.allclose(r["agent_energy"][e], e_or, rtol=1e-12, atol=1e-9)
+
+
+def test_batch_deterministic_and_host_entry_point():
+    evs, qs = _events(SMALL)
+    p = sbt.solve_params(agents=32, steps=300, seed=5, energy_every=50)
+    ds = sbt.DeviceBatchSolver(qs, "dsb", "fp16", p, want_agent_energy=True, want_trace=True,
+                               want_agent_state=True)
+    ds.run()
+    r1 = ds.result()
+    ds.run()
+    r2 = ds.result()
+    for e in range(len(qs)):
+        assert np.array_equal(r1["agent_x"][e], r2["agent_x"][e])
+    assert np.array_equal(r1["agent_energy"], r2["agent_energy"])
+    h = sbt.solve_batch(qs, "dsb", "fp16", agents=32, steps=300, seed=5, energy_every=50,
+                        want_agent_energy=True, want_trace=True)
+    assert np.array_equal(h["agent_energy"], r1["agent_energy"])
+    assert np.array_equal(h["energy"], r1["energy"])
+    for e in range(len(qs)):
+        assert np.array_equal(h["T"][e], r1["T"][e])
+        tr = r1["trace"][e]
+        assert np.all(np.diff(tr) <= 0)
+        assert abs(tr[-1] - r1["energy"][e]) <= 1e-9 * max(1.0, abs(tr[-1])) or tr[-1] < r1["energy"][e]
+
+
+def test_batch_rejects_unsupported():
+    rng = np.random.default_rng(1)
+    n = 9300
+    big = sbt.Qubo(n, rng.uniform(0, 0.7, n), np.zeros(n + 1, np.int64), np.zeros(0, np.int32),
+                   np.zeros(0), np.zeros((n, 3), np.int64))
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve_batch([big], "dsb", "fp16", agents=4, steps=2)
+    assert e.value.code == -4
+    evs, qs = _events(SMALL[:1])
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve_batch(qs, "dsb", "fp32", agents=4, steps=2)
+    assert e.value.code == -4
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_batch_quality_equals_plain_fp32(prec):
+    """Full-length dSB (128 agents, 3000 steps) on eight events of the
+    batching recipe: best energies within 0.5% of the plain FP32 solver and
+    efficiency / purity within 0.01."""
+    specs = tg.batching_specs()[:8]
+    evs, qs = _events(specs)
+    r = sbt.solve_batch(qs, "dsb", prec, agents=128, steps=3000, seed=0)
+    for e, (ev, q) in enumerate(zip(evs, qs)):
+        s = sbt.solve(q, "dsb", agents=128, steps=3000, seed=0, event=e)
+        assert r["energy"][e] <= s["energy"] + 0.005 * abs(s["energy"])
+        assert s["energy"] <= r["energy"][e] + 0.005 * abs(r["energy"][e])
+        b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
+        assert abs(oenergy.qubo_energy(q.a, b, r["T"][e]) - r["energy"][e]) <= 1e-9 * abs(r["energy"][e])
+        eff_b, pur_b, *_ = otracks.evaluate(ev, q.trip_hits, r["T"][e])
+        eff_s, pur_s, *_ = otracks.evaluate(ev, q.trip_hits, s["T"])
+        assert abs(eff_b - eff_s) <= 0.01 and abs(pur_b - pur_s) <= 0.01
