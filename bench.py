@@ -52,6 +52,109 @@ def step_bytes(n, nnz, agents, steps):
     return float(steps) * (16.0 * n * agents + 8.0 * nnz + 4.0 * (n + 1))
 
 
+TTT_DEFINITION = ("time of the cheapest complete solve (steps K from a ladder, same agents and "
+                  "seed, schedule a_k = a0 k / K) whose best FP64 O(T) reaches the target; "
+                  "targets relative to the FP64 oracle's best")
+TTT_TARGETS = (("within_0.5pct", 0.005), ("within_0.1pct", 0.001), ("exact", 1e-12))
+TTT_LADDER = (25, 50, 100, 200, 500, 1000, 2000, 5000)
+
+
+def load_golden(name):
+    with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+        return json.load(f)
+
+
+def timed_runs(run, torch, reps=3):
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def ttt_ladder(make, target, torch, best_of=lambda s: s.result()["energy"]):
+    """Smallest K in the ladder whose solve reaches `target`, and its time."""
+    for K in TTT_LADDER:
+        s = make(K)
+        t = timed_runs(s.run, torch)
+        e = best_of(s)
+        if e <= target:
+            return {"steps": K, "seconds": t, "energy": e}
+    return {"steps": None, "seconds": None, "energy": e}
+
+
+def precision_form(sbt, tg, torch, np):
+    """1000 particles (N ~ 8.5e3), dSB, 1024 agents x 5000 steps: plain FP32
+    against the 16-bit-coupling forms (one-event batch), with the energy gap
+    to the FP64 oracle (best of the first 32 agents)."""
+    ref = load_golden("oracle_best_precision.json")
+    ev = tg.generate(tg.precision_spec(), ref["event_seed"])
+    q = sbt.build_qubo(ev.hits_struct())
+    M, K = 1024, 5000
+    e_star = ref["modes"]["dsb"]["best"]
+    out = {"workload": "precision: 10-layer barrel, 1000 particles + 10% noise, event seed 200; "
+                       "dSB, 1024 agents x 5000 steps", "n": q.n, "nnz": q.nnz,
+           "oracle_best_32_agents": e_star}
+    ds = sbt.DeviceSolver(q, "dsb", sbt.solve_params(agents=M, steps=K, seed=0))
+    t = timed_runs(ds.run, torch, reps=2)
+    r = ds.result()
+    mk32 = lambda k: sbt.DeviceSolver(q, "dsb", sbt.solve_params(agents=M, steps=k, seed=0))
+    out["fp32"] = {"kernel": ds.kernel, "seconds": t, "spin_updates_per_s": q.n * M * K / t,
+                   "best": r["energy"], "gap_to_oracle": r["energy"] - e_star,
+                   "ttt_within_0.5pct": ttt_ladder(mk32, e_star + 0.005 * abs(e_star), torch),
+                   "ttt_exact": ttt_ladder(mk32, e_star + 1e-12 * abs(e_star), torch)}
+    for prec in ("fp16", "bf16"):
+        mk = lambda k, prec=prec: sbt.DeviceBatchSolver(
+            [q], "dsb", prec, sbt.solve_params(agents=M, steps=k, seed=0))
+        bs = mk(K)
+        t = timed_runs(bs.run, torch, reps=2)
+        e = float(bs.result()["energy"][0])
+        best = lambda s: float(s.result()["energy"][0])
+        out[prec] = {"kernel": "sb_batch", "seconds": t, "spin_updates_per_s": q.n * M * K / t,
+                     "best": e, "gap_to_oracle": e - e_star,
+                     "ttt_within_0.5pct": ttt_ladder(mk, e_star + 0.005 * abs(e_star), torch, best),
+                     "ttt_exact": ttt_ladder(mk, e_star + 1e-12 * abs(e_star), torch, best)}
+    return out
+
+
+def batched_form(sbt, tg, torch, np):
+    """512 events of 20-1000 particles, dSB, 128 agents x 3000 steps: one
+    persistent batched kernel (FP16 / BF16 couplings) against plain FP32
+    solving the events one at a time.  Per-event energies are compared with
+    the plain FP32 results (the FP64 oracle cannot run this batch)."""
+    specs = tg.batching_specs()
+    qs = [sbt.build_qubo(tg.generate(s, seed).hits_struct()) for s, seed in specs]
+    M, K = 128, 3000
+    sum_n = sum(q.n for q in qs)
+    out = {"workload": "batching: 512 events, 20 + floor(981 U) particles (U from seed 999), "
+                       "event seeds 1000-1511; dSB, 128 agents x 3000 steps",
+           "events": len(qs), "sum_n": sum_n, "max_n": max(q.n for q in qs)}
+    plain = [sbt.DeviceSolver(q, "dsb", sbt.solve_params(agents=M, steps=K, seed=0, event=e))
+             for e, q in enumerate(qs)]
+
+    def run_plain():
+        for s in plain:
+            s.run()
+
+    t = timed_runs(run_plain, torch, reps=1)
+    e32 = np.array([float(s.best_energy.item()) for s in plain])
+    out["fp32_one_event_at_a_time"] = {"seconds": t, "spin_updates_per_s": sum_n * M * K / t}
+    del plain
+    for prec in ("fp16", "bf16"):
+        bs = sbt.DeviceBatchSolver(qs, "dsb", prec, sbt.solve_params(agents=M, steps=K, seed=0))
+        tb = timed_runs(bs.run, torch, reps=2)
+        eb = bs.result()["energy"]
+        gap = (eb - e32) / np.abs(e32)
+        out[prec] = {"seconds": tb, "spin_updates_per_s": sum_n * M * K / tb,
+                     "speedup_vs_fp32": t / tb, "work_items": bs.n_items,
+                     "rel_energy_gap_vs_fp32": {"mean": float(gap.mean()), "max": float(gap.max()),
+                                                "min": float(gap.min())},
+                     "events_within_0.5pct_of_fp32": int(np.sum(gap <= 0.005))}
+    return out
+
+
 def measured_traffic(profile_name):
     """HBM bytes per launch from the committed rocprofv3 counter record, or
     None when the kernel's sources changed after the counters were taken."""
@@ -97,6 +200,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision (1000 particles) and batched (512 events) forms")
     ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
@@ -197,37 +302,24 @@ def main():
     }
 
     if not args.no_ttt:
-        gold = os.path.join(ROOT, "tests", "golden", "oracle_best_plain.json")
-        with open(gold) as f:
-            ref = json.load(f)
-        ttt = {"target": "oracle best O(T) + 0.5% |O|, checkpoints every 50 steps (timed)"}
+        ref = load_golden("oracle_best_plain.json")
+        ttt = {"definition": TTT_DEFINITION}
         for mode in ("bsb", "dsb"):
             e_star = ref["modes"][mode]["best"]
-            target = e_star + 0.005 * abs(e_star)
-            p = sbt.solve_params(agents=AGENTS, steps=SB_STEPS, seed=SOLVER_SEED,
-                                 kernel=args.kernel, energy_every=TTT_EVERY)
-            ds = sbt.DeviceSolver(q, mode, p, want_trace=True)
-            ds.run()
-            torch.cuda.synchronize()
-            reps = 3
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                ds.run()
-            torch.cuda.synchronize()
-            t_solve = (time.perf_counter() - t0) / reps
-            res = ds.result()
-            hit = np.nonzero(res["trace"] <= target)[0]
-            entry = {"oracle_best": e_star, "gpu_best": res["energy"],
-                     "gap_to_oracle": res["energy"] - e_star, "solve_s": t_solve}
-            if hit.size:
-                frac = (hit[0] + 1) * TTT_EVERY / SB_STEPS
-                entry["ttt_s"] = t_solve * frac
-                entry["ttt_step"] = int((hit[0] + 1) * TTT_EVERY)
-            else:
-                entry["ttt_s"] = None
-            ttt[mode] = entry
+            mk = lambda K, mode=mode: sbt.DeviceSolver(
+                q, mode, sbt.solve_params(agents=AGENTS, steps=K, seed=SOLVER_SEED,
+                                          kernel=args.kernel))
+            ttt[mode] = {"oracle_best": e_star,
+                         **{name: ttt_ladder(mk, e_star + f * abs(e_star), torch)
+                            for name, f in TTT_TARGETS}}
         result["time_to_target"] = ttt
         log("time-to-target done")
+
+    if not args.no_forms:
+        result["precision_form"] = precision_form(sbt, tg, torch, np)
+        log("precision form done")
+        result["batched_form"] = batched_form(sbt, tg, torch, np)
+        log("batched form done")
 
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")

@@ -122,13 +122,20 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;
 }
 
+// Records the largest dynamic-LDS size a kernel has been opened up to, so
+// the attribute is set once (on a kernel's first launch) rather than on
+// every launch -- launches may be captured into a HIP graph.
+bool lds_attribute_needed(const void *fn, size_t lds);
+
 // Launch with a dynamic-LDS request beyond the default limit.
 template <class F, class... Args>
 hipError_t launch_with_lds(F fn, dim3 grid, dim3 block, size_t lds, hipStream_t st, Args... args) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       static_cast<int>(lds));
-    if (e != hipSuccess) return e;
+    if (lds_attribute_needed(reinterpret_cast<const void *>(fn), lds)) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
     fn<<<grid, block, lds, st>>>(args...);
     return hipGetLastError();
 }

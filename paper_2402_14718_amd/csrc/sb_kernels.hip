@@ -23,11 +23,23 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
+#include <unordered_map>
 
 #include "sb_device.hpp"
 #include "sb_kernels.hpp"
 
 namespace sbt {
+
+bool lds_attribute_needed(const void *fn, size_t lds) {
+    static std::mutex mu;
+    static std::unordered_map<const void *, size_t> opened;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &have = opened[fn];
+    if (lds <= have) return false;
+    have = lds;
+    return true;
+}
 
 // ------------------------------------------------------------ Ising prep
 
