@@ -123,10 +123,20 @@ typedef enum {
                                 HBM, lanes are agents                       */
 } sbt_kernel;
 
+/* Storage precision of the couplings J (the reduced-precision forms of the
+ * paper's FP16 runs; accumulation is FP32 and energies FP64 throughout).
+ * FP8 is OCP e4m3 with one FP32 scale per row, max_j |J_ij| / 448. */
+typedef enum {
+    SBT_PREC_FP32 = 0,
+    SBT_PREC_FP16 = 1,
+    SBT_PREC_BF16 = 2,
+    SBT_PREC_FP8 = 3
+} sbt_precision;
+
 /* Solver parameters (section "Simulated Bifurcation" and Results: a0 = dt = 1,
  * fixed c0).  sbt_solve_params_default() fills a0 = dt = 1, c0 = auto,
  * agents = 32, steps = 2000, seed = 0, event = 0, kernel = AUTO,
- * energy_every = 0, tpb = 0. */
+ * energy_every = 0, tpb = 0, precision = FP32. */
 typedef struct {
     double a0;            /* a0 > 0                                          */
     double dt;            /* time step > 0                                   */
@@ -140,6 +150,10 @@ typedef struct {
     int32_t energy_every; /* > 0: record the best O(T) every that many steps */
     int32_t tpb;          /* resident kernel threads per workgroup (64, 256,  */
                           /* 512, 1024); 0 = chosen from the shape           */
+    int32_t precision;    /* sbt_precision of J for sbt_solve/sbt_solve_dev: */
+                          /* FP32 (any kernel) or FP8 (stream kernel only);  */
+                          /* the batch functions take theirs as an argument  */
+    int32_t reserved;     /* must be 0                                       */
 } sbt_solve_params;
 
 void sbt_solve_params_default(sbt_solve_params *p);
@@ -234,8 +248,6 @@ int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
  * held in 16 bits (the reduced-precision form); accumulation is FP32 and
  * energies are FP64 of the returned spins.
  * ---------------------------------------------------------------------- */
-
-typedef enum { SBT_PREC_FP32 = 0, SBT_PREC_FP16 = 1, SBT_PREC_BF16 = 2 } sbt_precision;
 
 /* Events concatenated in device memory. */
 typedef struct {

@@ -1,0 +1,84 @@
+"""Reduced-precision coupling forms, from their definitions.
+
+Test infrastructure: only the tests, the smoke check and the benchmark's
+CPU baseline use this package.
+
+The paper runs SB in reduced precision on its GPUs (Results); here J is
+stored in a narrow format while positions, momenta and accumulation stay
+FP32 and energies FP64.  This module writes out the FP8 form:
+
+* OCP 8-bit E4M3 ("e4m3fn"): sign bit, 4 exponent bits with bias 7, 3
+  mantissa bits; exponent field 0 holds subnormals m/8 * 2^-6; the pattern
+  S.1111.111 is NaN and there are no infinities, so the largest finite
+  magnitude is 1.75 * 2^8 = 448; rounding is to nearest, ties to even.
+* per-row scaling: s_i = fl32(fl32(max_j |J_ij|) / 448) (1 for an all-zero
+  row), code_ij = e4m3(min(max(fl32(J_ij / s_i), -448), 448)) and the
+  coupling used is J'_ij = fl32(s_i * e4m3_value(code_ij)).  J enters in
+  FP32 (the kernels' coupling type).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+E4M3_MAX = 448.0
+E4M3_MIN_NORMAL = 2.0 ** -6
+E4M3_MIN_SUBNORMAL = 2.0 ** -9
+
+
+def e4m3_value(code) -> np.ndarray:
+    """Value of E4M3 codes (uint8 array); NaN for the two NaN patterns."""
+    c = np.asarray(code, dtype=np.int64)
+    sign = np.where(c & 0x80, -1.0, 1.0)
+    e = (c >> 3) & 0xF
+    m = c & 0x7
+    mag = np.where(e == 0, m / 8.0 * E4M3_MIN_NORMAL, (1.0 + m / 8.0) * np.exp2(e - 7.0))
+    mag = np.where((e == 15) & (m == 7), np.nan, mag)
+    return sign * mag
+
+
+def e4m3_encode(v) -> np.ndarray:
+    """Round finite values with |v| <= 448 to the nearest E4M3 code (ties to
+    the even code).  Raises for larger or non-finite inputs."""
+    v = np.asarray(v, dtype=np.float64)
+    if not np.all(np.isfinite(v)) or np.any(np.abs(v) > E4M3_MAX):
+        raise ValueError("e4m3_encode takes finite values with |v| <= 448")
+    a = np.abs(v)
+    # spacing of representable magnitudes near a: 2^(E - 3) with E the
+    # binary exponent of a, floored at the subnormal exponent -6
+    with np.errstate(divide="ignore"):
+        E = np.where(a > 0, np.floor(np.log2(np.where(a > 0, a, 1.0))), -6.0)
+    E = np.maximum(E, -6.0)
+    quantum = np.exp2(E - 3.0)
+    r = np.rint(a / quantum) * quantum          # exact scaling; rint ties to even
+    # code of the rounded magnitude (it may have moved up one binade)
+    normal = r >= E4M3_MIN_NORMAL
+    with np.errstate(divide="ignore"):
+        e = np.where(normal, np.floor(np.log2(np.where(normal, r, 1.0))) + 7.0, 0.0)
+    m = np.where(normal, (r / np.exp2(e - 7.0) - 1.0) * 8.0, r / E4M3_MIN_SUBNORMAL)
+    code = (e.astype(np.int64) << 3) | np.rint(m).astype(np.int64)
+    code = np.where(np.signbit(v) & (r > 0), code | 0x80, code)
+    return code.astype(np.uint8)
+
+
+def fp8_rows(J: sp.csr_matrix):
+    """Per-row FP8 form of the couplings: (J' as CSR FP64 of FP32 values,
+    codes per stored entry, FP32 scale per row)."""
+    J = sp.csr_matrix(J)
+    J32 = J.data.astype(np.float32)
+    n = J.shape[0]
+    scale = np.ones(n, dtype=np.float32)
+    codes = np.zeros(J32.shape[0], dtype=np.uint8)
+    vals = np.zeros(J32.shape[0], dtype=np.float32)
+    for i in range(n):
+        lo, hi = J.indptr[i], J.indptr[i + 1]
+        if hi == lo:
+            continue
+        mx = np.float32(np.max(np.abs(J32[lo:hi])))
+        s = np.float32(mx / np.float32(E4M3_MAX)) if mx > 0 else np.float32(1.0)
+        scale[i] = s
+        q = np.clip((J32[lo:hi] / s).astype(np.float32), -E4M3_MAX, E4M3_MAX)
+        codes[lo:hi] = e4m3_encode(q)
+        vals[lo:hi] = (s * e4m3_value(codes[lo:hi]).astype(np.float32)).astype(np.float32)
+    Jq = sp.csr_matrix((vals.astype(np.float64), J.indices.copy(), J.indptr.copy()), shape=J.shape)
+    return Jq, codes, scale

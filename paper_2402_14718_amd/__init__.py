@@ -23,6 +23,8 @@ from ._lib import (SBT_BSB, SBT_DSB, SBT_KERNEL_AUTO, SBT_KERNEL_RESIDENT, SBT_K
 
 MODES = {"bsb": SBT_BSB, "dsb": SBT_DSB}
 KERNELS = {"auto": SBT_KERNEL_AUTO, "resident": SBT_KERNEL_RESIDENT, "stream": SBT_KERNEL_STREAM}
+PRECISIONS = {"fp32": _lib.SBT_PREC_FP32, "fp16": _lib.SBT_PREC_FP16, "bf16": _lib.SBT_PREC_BF16,
+              "fp8": _lib.SBT_PREC_FP8}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 
 HIT_DTYPE = np.dtype([("hit_id", "<i8"), ("layer", "<i4"), ("pad", "<i4"),
@@ -109,7 +111,8 @@ def energy(q: Qubo, T: np.ndarray) -> float:
 
 def solve_params(agents: int = 32, steps: int = 2000, dt: float = 1.0, a0: float = 1.0,
                  c0: float = 0.0, seed: int = 0, event: int = 0, kernel: str = "auto",
-                 energy_every: int = 0, tpb: int = 0) -> _lib.SbtSolveParams:
+                 energy_every: int = 0, tpb: int = 0,
+                 precision: str = "fp32") -> _lib.SbtSolveParams:
     p = _lib.SbtSolveParams()
     load().sbt_solve_params_default(C.byref(p))
     p.agents, p.steps, p.dt, p.a0, p.c0 = agents, steps, dt, a0, c0
@@ -118,16 +121,18 @@ def solve_params(agents: int = 32, steps: int = 2000, dt: float = 1.0, a0: float
     p.kernel = KERNELS[kernel]
     p.energy_every = energy_every
     p.tpb = tpb
+    p.precision = PRECISIONS[precision]
     return p
 
 
 def solve(q: Qubo, mode: str, agents: int = 32, steps: int = 2000, dt: float = 1.0,
           a0: float = 1.0, c0: float = 0.0, seed: int = 0, event: int = 0,
           kernel: str = "auto", energy_every: int = 0, want_state: bool = False,
-          want_trace: bool = False, tpb: int = 0) -> dict:
+          want_trace: bool = False, tpb: int = 0, precision: str = "fp32") -> dict:
     """sbt_solve: host QUBO in, host results out (the library uploads,
     solves on the GPU and downloads)."""
-    p = solve_params(agents, steps, dt, a0, c0, seed, event, kernel, energy_every, tpb)
+    p = solve_params(agents, steps, dt, a0, c0, seed, event, kernel, energy_every, tpb,
+                     precision)
     s = q.as_struct()
     T = np.zeros(q.n, dtype=np.int8)
     E = np.zeros(agents, dtype=np.float64)
@@ -226,7 +231,6 @@ class DeviceSolver:
                 "kernel": self.kernel}
 
 
-PRECISIONS = {"fp32": _lib.SBT_PREC_FP32, "fp16": _lib.SBT_PREC_FP16, "bf16": _lib.SBT_PREC_BF16}
 
 
 def _concat_batch(qubos):

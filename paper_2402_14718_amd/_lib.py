@@ -48,7 +48,7 @@ class SbtSolveParams(C.Structure):
     _fields_ = [("a0", C.c_double), ("dt", C.c_double), ("c0", C.c_double),
                 ("agents", C.c_int32), ("steps", C.c_int32), ("seed", C.c_uint64),
                 ("event", C.c_int32), ("kernel", C.c_int32), ("energy_every", C.c_int32),
-                ("tpb", C.c_int32)]
+                ("tpb", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SbtResult(C.Structure):
@@ -74,6 +74,7 @@ class SbtDevResult(C.Structure):
 SBT_PREC_FP32 = 0
 SBT_PREC_FP16 = 1
 SBT_PREC_BF16 = 2
+SBT_PREC_FP8 = 3
 
 
 class SbtDevBatch(C.Structure):

@@ -25,7 +25,7 @@ ARCH = "gfx950"
 
 HOST_SOURCES = ["status.cpp", "build_qubo.cpp"]
 RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
-HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_batch.hip"]
+HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_batch.hip", "sb_stream.hip"]
 
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
               "-Wall", "-Wextra", "-Wno-unused-parameter", f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -12,9 +12,7 @@
 //                                     workgroup per agent, positions in LDS
 //                                     (ping-pong), momenta in VGPRs, J in
 //                                     LDS when it fits
-//   sb_stream<MODE>                   one step per launch: one wave per
-//                                     (row, 64 agents), state in HBM with
-//                                     agents contiguous, J row wave-uniform
+//   (the streaming one-step kernel is in sb_stream.hip)
 //   energy_rows / energy_reduce       FP64 O(T) of every agent (Eq. 13)
 //   select_best                       argmin over agents (lowest index on
 //                                     ties) and the best T
@@ -237,36 +235,6 @@ __global__ __launch_bounds__(TPB) void sb_resident(ResidentArgs A) {
     }
 }
 
-// ------------------------------------------------------- stream kernel
-
-// One step.  Wave w of the workgroup handles row i = 4 blockIdx.x + w for
-// the 64 agents of blockIdx.y; row bounds, columns and J values are
-// wave-uniform (scalar loads), each gathered x_j row is one coalesced
-// 256-byte load.
-template <int MODE>
-__global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const float *__restrict__ xin,
-                                                 float *__restrict__ xout) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wave);
-    if (i >= A.n) return;
-    const int m = blockIdx.y * 64 + lane;
-    if (m >= A.M) return;
-    const int M = A.M;
-    const float c0 = static_cast<float>(A.scal[0]);
-    const float g = A.sched[k];
-    const int p0 = A.row_ptr[i], p1 = A.row_ptr[i + 1];
-    float acc = A.h[i];
-    for (int p = p0; p < p1; ++p) {
-        const int c = A.col[p];
-        acc = __builtin_fmaf(A.J[p], coupling_operand<MODE>(xin[static_cast<size_t>(c) * M + m]), acc);
-    }
-    const size_t o = static_cast<size_t>(i) * M + m;
-    float x = xin[o], y = A.y[o];
-    sb_update(x, y, acc, c0, g, A.dt, A.dta0);
-    xout[o] = x;
-    A.y[o] = y;
-}
-
 // -------------------------------------------------------------- energy
 
 // part[blockIdx.x * M + m] = sum over rows of this block of
@@ -425,16 +393,6 @@ static hipError_t launch_resident_m(const ResidentArgs &A, const ResidentShape &
 hipError_t launch_resident(int mode, const ResidentArgs &A, const ResidentShape &S, hipStream_t st) {
     if (S.rc > 0) return launch_resident_reg(mode, A, S, st);
     return mode == kDSB ? launch_resident_m<kDSB>(A, S, st) : launch_resident_m<kBSB>(A, S, st);
-}
-
-hipError_t launch_stream_step(int mode, const StreamArgs &A, int k, const float *xin, float *xout,
-                              hipStream_t st) {
-    dim3 grid((A.n + 3) / 4, (A.M + 63) / 64);
-    if (mode == kDSB)
-        sb_stream<kDSB><<<grid, 256, 0, st>>>(A, k, xin, xout);
-    else
-        sb_stream<kBSB><<<grid, 256, 0, st>>>(A, k, xin, xout);
-    return hipGetLastError();
 }
 
 hipError_t launch_energy(int n, int M, const double *a, const int *row_ptr, const int *col,

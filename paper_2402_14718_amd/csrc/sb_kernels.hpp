@@ -40,17 +40,24 @@ struct ResidentShape {
 
 constexpr int kRegMaxN = 8192;   // register-row variant: largest n (buffer stride)
 
+// Streaming kernel's couplings: CSR with every row padded to a multiple of
+// kStreamChunk entries by (own column, zero coupling), so each chunk of
+// columns and couplings is one aligned scalar load.
+constexpr int kStreamChunk = 8;
+
 struct StreamArgs {
     int n, M, K;
     double a0;
     float dt, dta0;
-    const int *row_ptr;
-    const int *col;
-    const float *J;
+    const int *row_ptr;          // [n+1] padded row pointers (multiples of kStreamChunk)
+    const int *col;              // [padded nnz]
+    const float *J;              // [padded nnz] FP32 couplings
     const float *h;
     const double *scal;
     float *y;
     const float *sched;          // [K] a0 - a_k
+    const uint8_t *J8;           // [padded nnz] FP8 e4m3 couplings (FP8 form)
+    const float *rowscale;       // [n] per-row FP32 scale of J8
 };
 
 // ---------------------------------------------------------------- batch
@@ -58,7 +65,7 @@ struct StreamArgs {
 constexpr int kBatchTPB = 1024;                     // threads per workgroup
 constexpr int kBatchSPT = 9;                        // slots per thread
 constexpr int kBatchSlots = kBatchTPB * kBatchSPT;  // largest n * agents per item
-enum : int { kJFp16 = 0, kJBf16 = 1 };              // 16-bit coupling formats
+enum : int { kJFp16 = 0, kJBf16 = 1, kJFp32 = 2, kJFp8 = 3 };  // coupling formats
 
 struct BatchEvent {
     int n, nnz;
@@ -113,8 +120,15 @@ hipError_t launch_resident(int mode, const ResidentArgs &A, const ResidentShape 
 hipError_t launch_resident_reg(int mode, const ResidentArgs &A, const ResidentShape &S,
                                hipStream_t st);
 hipError_t launch_row_order(int n, const int *row_ptr, int *perm, hipStream_t st);
-hipError_t launch_stream_step(int mode, const StreamArgs &A, int k, const float *xin, float *xout,
-                              hipStream_t st);
+hipError_t launch_stream2(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
+                          float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st);
+hipError_t launch_sign_planes(int n, int M, const float *x, uint64_t *S, hipStream_t st);
+hipError_t launch_quantize_fp8(int n, const int *row_ptr, const float *J, uint8_t *J8, float *scale,
+                               hipStream_t st);
+// Padded copy (col, J) -> (pcol, pJ) with row pointers prow; pcol and pJ hold
+// at most nnz + (kStreamChunk - 1) n entries.
+hipError_t launch_stream_pack(int n, const int *row_ptr, const int *col, const float *J, int *prow,
+                              int *pcol, float *pJ, hipStream_t st);
 hipError_t launch_energy(int n, int M, const double *a, const int *row_ptr, const int *col,
                          const double *b, const float *x, double *part, double *out,
                          hipStream_t st);

@@ -22,12 +22,18 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t J = 0, h = 0, scal = 0, prep = 0, perm = 0, sched = 0, xa = 0, xb = 0, y = 0, epart = 0, etrace = 0;
+    size_t J = 0, h = 0, scal = 0, prep = 0, perm = 0, sched = 0, xa = 0, xb = 0, y = 0, epart = 0,
+           etrace = 0, S0 = 0, S1 = 0, J8 = 0, rowscale = 0, prow = 0, pcol = 0, pJ = 0;
     size_t total = 0;
     int n_ckpt = 0;
 };
 
-Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every) {
+// x is updated in place under dSB (the streaming kernel's neighbours are
+// the sign planes S0/S1), so the second position buffer exists for bSB
+// only; FP8 couplings add one byte per padded nonzero and a scale per row.
+// prow/pcol/pJ: the streaming kernel's row-padded copy of the couplings.
+Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, sbt_mode mode,
+                   int32_t prec) {
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -46,10 +52,23 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every) 
     L.perm = take(sizeof(int32_t) * n);
     L.sched = take(sizeof(float) * static_cast<size_t>(K));
     L.xa = take(sizeof(float) * nm);
-    L.xb = take(sizeof(float) * nm);
+    L.xb = mode == SBT_BSB ? take(sizeof(float) * nm) : L.xa;
     L.y = take(sizeof(float) * nm);
     L.epart = take(sizeof(double) * nblk_e * M);
     L.etrace = take(sizeof(double) * static_cast<size_t>(L.n_ckpt) * M);
+    if (mode == SBT_DSB) {
+        const size_t words = static_cast<size_t>(n) * ((static_cast<size_t>(M) + 63) / 64);
+        L.S0 = take(sizeof(uint64_t) * words);
+        L.S1 = take(sizeof(uint64_t) * words);
+    }
+    const size_t pnnz = static_cast<size_t>(nnz) + (sbt::kStreamChunk - 1) * static_cast<size_t>(n);
+    L.prow = take(sizeof(int32_t) * (static_cast<size_t>(n) + 1));
+    L.pcol = take(sizeof(int32_t) * pnnz);
+    L.pJ = take(sizeof(float) * pnnz);
+    if (prec == SBT_PREC_FP8) {
+        L.J8 = take(pnnz);
+        L.rowscale = take(sizeof(float) * n);
+    }
     L.total = off;
     return L;
 }
@@ -68,12 +87,15 @@ int check_params(const sbt_solve_params &p, const char *who) {
         return fail(SBT_EINVAL, "%s: unknown kernel %d", who, p.kernel);
     if (p.tpb != 0 && p.tpb != 64 && p.tpb != 256 && p.tpb != 512 && p.tpb != 1024)
         return fail(SBT_EINVAL, "%s: tpb must be 0, 64, 256, 512 or 1024", who);
+    if (p.precision < SBT_PREC_FP32 || p.precision > SBT_PREC_FP8)
+        return fail(SBT_EINVAL, "%s: unknown precision %d", who, p.precision);
+    if (p.reserved != 0) return fail(SBT_EINVAL, "%s: reserved must be 0", who);
     return SBT_OK;
 }
 
 int check_shape(int32_t n, int64_t nnz, int32_t M, const char *who) {
     if (n < 1) return fail(SBT_EINVAL, "%s: n must be >= 1", who);
-    if (nnz < 0 || nnz > std::numeric_limits<int32_t>::max())
+    if (nnz < 0 || nnz + int64_t(sbt::kStreamChunk - 1) * n > std::numeric_limits<int32_t>::max())
         return fail(SBT_EINVAL, "%s: nnz %lld out of range", who, static_cast<long long>(nnz));
     if (static_cast<int64_t>(n) * M > (int64_t(1) << 31) - 1)
         return fail(SBT_EINVAL, "%s: n * agents exceeds 2^31 - 1", who);
@@ -146,6 +168,14 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, const sbt_solve_params 
                 sbt::ResidentShape *shape) {
     sbt::ResidentShape S = resident_shape(n, nnz, max_row, p.tpb, lds_limit);
     if (shape) *shape = S;
+    if (p.precision == SBT_PREC_FP16 || p.precision == SBT_PREC_BF16)
+        return fail(SBT_EUNSUPPORTED,
+                    "16-bit couplings are solved by the batch functions (sbt_solve_batch)");
+    if (p.precision == SBT_PREC_FP8) {
+        if (p.kernel == SBT_KERNEL_RESIDENT)
+            return fail(SBT_EUNSUPPORTED, "FP8 couplings run on the streaming kernel only");
+        return SBT_KERNEL_STREAM;
+    }
     if (p.kernel == SBT_KERNEL_STREAM) return SBT_KERNEL_STREAM;
     if (p.kernel == SBT_KERNEL_RESIDENT) {
         if (S.tpb == 0)
@@ -196,7 +226,7 @@ extern "C" size_t sbt_workspace_bytes(int32_t n, int64_t nnz, sbt_mode mode,
     }
     if (check_params(*p, "sbt_workspace_bytes") != SBT_OK) return 0;
     if (check_shape(n, nnz, p->agents, "sbt_workspace_bytes") != SBT_OK) return 0;
-    return make_layout(n, nnz, p->agents, p->steps, p->energy_every).total;
+    return make_layout(n, nnz, p->agents, p->steps, p->energy_every, mode, p->precision).total;
 }
 
 extern "C" int sbt_select_kernel(int32_t n, int64_t nnz, int32_t max_row_nnz, sbt_mode mode,
@@ -231,7 +261,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         return fail(SBT_EINVAL, "%s: result pointer is NULL", who);
     const int32_t n = q->n, M = p->agents, K = p->steps;
     const int nnz = static_cast<int>(q->nnz);
-    const Layout L = make_layout(n, q->nnz, M, K, p->energy_every);
+    const Layout L = make_layout(n, q->nnz, M, K, p->energy_every, mode, p->precision);
     if (!workspace || workspace_bytes < L.total)
         return fail(SBT_EINVAL, "%s: workspace of %zu bytes is smaller than the %zu needed", who,
                     workspace_bytes, L.total);
@@ -254,6 +284,13 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
     float *dy = reinterpret_cast<float *>(ws + L.y);
     double *epart = reinterpret_cast<double *>(ws + L.epart);
     double *etrace = reinterpret_cast<double *>(ws + L.etrace);
+    uint64_t *S0 = reinterpret_cast<uint64_t *>(ws + L.S0);
+    uint64_t *S1 = reinterpret_cast<uint64_t *>(ws + L.S1);
+    uint8_t *J8 = reinterpret_cast<uint8_t *>(ws + L.J8);
+    float *rowscale = reinterpret_cast<float *>(ws + L.rowscale);
+    int *prow = reinterpret_cast<int *>(ws + L.prow);
+    int *pcol = reinterpret_cast<int *>(ws + L.pcol);
+    float *pJ = reinterpret_cast<float *>(ws + L.pJ);
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     const double c0_fixed = (std::isnan(p->c0) || p->c0 <= 0.0) ? 0.0 : p->c0;
@@ -297,18 +334,31 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         A.a0 = p->a0;
         A.dt = dt;
         A.dta0 = dta0;
-        A.row_ptr = q->row_ptr;
-        A.col = q->col;
-        A.J = dJ;
+        SBT_HIP(sbt::launch_stream_pack(n, q->row_ptr, q->col, dJ, prow, pcol, pJ, st));
+        A.row_ptr = prow;
+        A.col = pcol;
+        A.J = pJ;
         A.h = dh;
         A.scal = scal;
         A.y = dy;
         A.sched = sched;
+        const bool fp8 = p->precision == SBT_PREC_FP8;
+        if (fp8) {
+            SBT_HIP(sbt::launch_quantize_fp8(n, prow, pJ, J8, rowscale, st));
+            A.J8 = J8;
+            A.rowscale = rowscale;
+        }
+        const int jprec = fp8 ? sbt::kJFp8 : sbt::kJFp32;
+        // dSB: x, y in place, signs ping-pong between S0 and S1;
+        // bSB: positions ping-pong between xa and xb
         float *xin = xa, *xout = xb;
+        uint64_t *Sin = S0, *Sout = S1;
+        if (mode == SBT_DSB) SBT_HIP(sbt::launch_sign_planes(n, M, xa, S0, st));
         int ck = 0;
         for (int k = 0; k < K; ++k) {
-            SBT_HIP(sbt::launch_stream_step(mode, A, k, xin, xout, st));
+            SBT_HIP(sbt::launch_stream2(static_cast<int>(mode), jprec, A, k, xin, xout, Sin, Sout, st));
             std::swap(xin, xout);
+            std::swap(Sin, Sout);
             if (p->energy_every > 0 && (k + 1) % p->energy_every == 0) {
                 SBT_HIP(sbt::launch_energy(n, M, q->a, q->row_ptr, q->col, q->b, xin, epart,
                                            etrace + static_cast<size_t>(ck) * M, st));
@@ -415,7 +465,7 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
 
     std::vector<int32_t> rp32(n + 1);
     for (int32_t i = 0; i <= n; ++i) rp32[i] = static_cast<int32_t>(q->row_ptr[i]);
-    const size_t ws_bytes = make_layout(n, nnz, M, p.steps, p.energy_every).total;
+    const size_t ws_bytes = make_layout(n, nnz, M, p.steps, p.energy_every, mode, p.precision).total;
     const size_t nm = static_cast<size_t>(n) * M;
 
     DevBuf da, drp, dcol, db, dws, dT, dE, dbe, dbm, dsc, dx, dy, dtr;

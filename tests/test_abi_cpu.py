@@ -35,7 +35,7 @@ def test_library_exports_every_declared_function():
 def test_struct_sizes_match_c_layout():
     assert C.sizeof(_lib.SbtHit) == 40
     assert C.sizeof(_lib.SbtBuildParams) == 6 * 8 + 2 * 4 + 4 * 8
-    assert C.sizeof(_lib.SbtSolveParams) == 3 * 8 + 2 * 4 + 8 + 4 * 4
+    assert C.sizeof(_lib.SbtSolveParams) == 3 * 8 + 2 * 4 + 8 + 6 * 4
     assert sbt.HIT_DTYPE.itemsize == C.sizeof(_lib.SbtHit)
 
 
@@ -123,6 +123,39 @@ def test_workspace_and_param_validation():
         sbt.workspace_bytes(0, 0, "dsb", sbt.solve_params())
     with pytest.raises(sbt.SbtError):
         sbt.workspace_bytes(1 << 20, 0, "dsb", sbt.solve_params(agents=4096))
+    # dSB updates x in place: one position buffer plus two sign planes
+    wd = sbt.workspace_bytes(1500, 3000, "dsb", p)
+    assert 2 * 1500 * 256 * 4 + 2 * 1500 * 4 * 8 <= wd < ws
+    # FP8 adds one byte per padded coupling and a scale per row
+    w8 = sbt.workspace_bytes(1500, 3000, "bsb", sbt.solve_params(agents=256, steps=5000,
+                                                                precision="fp8"))
+    assert w8 >= ws + 3000 + 1500 * 4
+
+
+def test_precision_selects_or_rejects_kernels():
+    n, nnz, row = 1480, 2722, 12
+    # FP32: either kernel, depending on the device's LDS size
+    assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256)) in ("resident",
+                                                                                 "stream")
+    assert sbt.select_kernel(n, nnz, row, "dsb",
+                             sbt.solve_params(agents=256, precision="fp8")) == "stream"
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.select_kernel(n, nnz, row, "dsb",
+                          sbt.solve_params(agents=256, precision="fp8", kernel="resident"))
+    assert e.value.code == _lib.SBT_EUNSUPPORTED
+    for prec in ("fp16", "bf16"):
+        with pytest.raises(sbt.SbtError) as e:
+            sbt.select_kernel(n, nnz, row, "bsb", sbt.solve_params(precision=prec))
+        assert e.value.code == _lib.SBT_EUNSUPPORTED
+    p = sbt.solve_params()
+    p.precision = 9
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.select_kernel(n, nnz, row, "bsb", p)
+    assert e.value.code == _lib.SBT_EINVAL
+    p = sbt.solve_params()
+    p.reserved = 1
+    with pytest.raises(sbt.SbtError):
+        sbt.select_kernel(n, nnz, row, "bsb", p)
 
 
 def test_solve_rejects_malformed_qubo_before_touching_a_device():

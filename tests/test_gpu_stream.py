@@ -1,0 +1,108 @@
+"""GPU parity of the streaming step kernel (one launch per step, state in
+HBM) and of its FP8 coupling form, through the C ABI, against the oracle.
+
+FP8: the oracle runs with the same per-row E4M3 couplings
+(``oracle.quant.fp8_rows``), everything else in FP64, so the FP32
+trajectories must stay within 1e-5 relative over 50 steps, with the same
+close-call allowance as the FP32 path.  Energies are of the true QUBO, FP64.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import trackgen as tg
+from oracle import energy as oenergy
+from oracle import ising as oising
+from oracle import quant as oquant
+from oracle import sb as osb
+from oracle import tracks as otracks
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+import paper_2402_14718_amd as sbt  # noqa: E402
+from paper_2402_14718_amd import _lib  # noqa: E402
+
+
+def _event(spec, seed):
+    ev = tg.generate(spec, seed)
+    q = sbt.build_qubo(ev.hits_struct())
+    b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
+    return ev, q, b, oising.from_qubo(q.a, b)
+
+
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+@pytest.mark.parametrize("dt,K", [(1.0, 50), (0.1, 10), (0.1, 20)])
+def test_fp8_trajectory_within_1e5(mode, dt, K):
+    """dt = 1 puts every position of this event on the wall within ten steps;
+    dt = 0.1 keeps the state inside (all of it at K = 10, about a quarter at
+    K = 20), where the arithmetic of every coupling shows."""
+    ev, q, b, isg = _event(tg.plain_spec(), 100)
+    Jq, codes, scale = oquant.fp8_rows(isg.J)
+    M, seed = 70, 11                          # 70 agents: a ragged second 64-agent word
+    r = sbt.solve(q, mode, agents=M, steps=K, dt=dt, seed=seed, precision="fp8", want_state=True)
+    assert r["kernel"] == "stream"
+    ref = osb.run(Jq, isg.h, isg.c0, mode, M, K, dt=dt, seed=seed, margin_steps=K)
+    err = np.linalg.norm(r["x"] - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
+    close_call = ref.wall_margin < 1e-6
+    if mode == "dsb":
+        close_call |= ref.sign_margin < 1e-6
+    ok = err <= 1e-5
+    assert np.all(ok | close_call), (err.max(), np.nonzero(~ok & ~close_call))
+    assert np.mean(ok) >= 0.9
+    if dt < 1.0:
+        # inside the walls the FP8 couplings move the state measurably away
+        # from the FP32 ones (about 3e-4 relative at K = 10)
+        r32 = sbt.solve(q, mode, agents=M, steps=K, dt=dt, seed=seed, kernel="stream",
+                        want_state=True)
+        assert np.linalg.norm(r32["x"] - r["x"]) > 1e-5 * np.linalg.norm(r["x"])
+
+
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+def test_fp8_energies_are_exact_fp64_of_the_true_qubo(mode):
+    ev, q, b, isg = _event(tg.plain_spec(), 101)
+    r = sbt.solve(q, mode, agents=96, steps=800, seed=2, precision="fp8", want_state=True)
+    T = (r["x"] >= 0).astype(np.int8)
+    e_or = oenergy.qubo_energy(q.a, b, T)
+    assert np.all(np.abs(r["agent_energy"] - e_or) <= 1e-9 * np.maximum(1.0, np.abs(e_or)))
+    best = oenergy.best_agent(e_or)
+    assert r["best_agent"] == best and np.array_equal(r["T"], T[:, best])
+
+
+def test_fp8_rejected_on_resident_kernel_and_16_bit_single_event():
+    ev, q, b, isg = _event(tg.tiny_spec(), 1)
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve(q, "dsb", agents=8, steps=10, precision="fp8", kernel="resident")
+    assert e.value.code == _lib.SBT_EUNSUPPORTED
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve(q, "dsb", agents=8, steps=10, precision="fp16")
+    assert e.value.code == _lib.SBT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+def test_fp8_full_size_quality(mode):
+    """Plain workload at full length: the FP8 form's best energy within 0.5%
+    of the FP32 solver's best over the same agents, efficiency and purity
+    within 0.02."""
+    ev, q, b, isg = _event(tg.plain_spec(), 100)
+    r8 = sbt.solve(q, mode, agents=256, steps=5000, seed=0, precision="fp8")
+    r32 = sbt.solve(q, mode, agents=256, steps=5000, seed=0)
+    assert r8["energy"] <= r32["energy"] + 0.005 * abs(r32["energy"])
+    eff8, pur8, *_ = otracks.evaluate(ev, q.trip_hits, r8["T"])
+    eff32, pur32, *_ = otracks.evaluate(ev, q.trip_hits, r32["T"])
+    assert abs(eff8 - eff32) <= 0.02 and abs(pur8 - pur32) <= 0.02
+
+
+@pytest.mark.parametrize("M", [1, 63, 64, 65, 130])
+def test_stream_agent_words_ragged(M):
+    """Agent counts around the 64-agent word of the sign planes: the
+    streaming kernel against the resident one, bit for bit."""
+    ev, q, b, isg = _event(tg.plain_spec(60), 7)
+    for mode in ("bsb", "dsb"):
+        rr = sbt.solve(q, mode, agents=M, steps=120, seed=9, kernel="resident", want_state=True)
+        rs = sbt.solve(q, mode, agents=M, steps=120, seed=9, kernel="stream", want_state=True)
+        assert np.array_equal(rr["x"], rs["x"]), mode
+        assert np.array_equal(rr["y"], rs["y"]), mode

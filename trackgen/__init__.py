@@ -14,7 +14,7 @@ reproduced; every event is drawn from a seeded NumPy PCG64 generator.
 from .helix import (EventSpec, Event, generate, RADII_4, RADII_10,
                     SPEED_OF_LIGHT_GEV_PER_T_M)
 from .workloads import (WORKLOADS, workload_spec, tiny_spec, plain_spec,
-                        precision_spec, stress_spec, batching_specs)
+                        precision_spec, stress_spec, batching_specs, STRESS_Z0_MAX)
 from .random_qubo import random_qubo
 
 __all__ = [
