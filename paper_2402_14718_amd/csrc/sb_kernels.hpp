@@ -45,6 +45,23 @@ constexpr int kRegMaxN = 8192;   // register-row variant: largest n (buffer stri
 // columns and couplings is one aligned scalar load.
 constexpr int kStreamChunk = 8;
 
+// Agents per lane of the streaming kernel: one wave covers one row for
+// 64 * APL agents, lane l holding agents base + 64 k + l (k < APL), so the
+// row's dSB sign words for those agents are APL consecutive 64-bit words.
+// Largest APL per form (bSB: gathers in flight vs VGPRs; dSB: sign
+// records in flight vs SGPRs).
+constexpr int kStreamAplMaxBsb = 4;
+constexpr int kStreamAplMaxDsb = 8;
+__host__ __device__ constexpr int stream_apl(int M, int mode) {
+    const int cap = mode == 1 ? kStreamAplMaxDsb : kStreamAplMaxBsb;
+    const int apl = M > 256 ? 8 : (M > 128 ? 4 : (M > 64 ? 2 : 1));
+    return apl < cap ? apl : cap;
+}
+// 64-bit dSB sign words per spin: ceil(M / 64) rounded up to a multiple of APL.
+__host__ __device__ constexpr int stream_sign_stride(int M) {
+    return ((M + 63) / 64 + stream_apl(M, 1) - 1) / stream_apl(M, 1) * stream_apl(M, 1);
+}
+
 struct StreamArgs {
     int n, M, K;
     double a0;
@@ -58,6 +75,7 @@ struct StreamArgs {
     const float *sched;          // [K] a0 - a_k
     const uint8_t *J8;           // [padded nnz] FP8 e4m3 couplings (FP8 form)
     const float *rowscale;       // [n] per-row FP32 scale of J8
+    int sign_stride;             // stream_sign_stride(M)
 };
 
 // ---------------------------------------------------------------- batch

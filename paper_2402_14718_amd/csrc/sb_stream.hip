@@ -2,18 +2,18 @@
 //
 // Paper section "Simulated Bifurcation": one symplectic-Euler step of bSB
 // (Eq. 5-8) or dSB (Eq. 9-12) per launch, all spins and agents at once.
-// State x, y is FP32 in HBM, spin-major with agents contiguous; one wave
-// handles one row i for 64 agents, so every x_j gather is one coalesced
-// 256-byte line and a row's columns and couplings are wave-uniform scalar
-// loads.  Rows are padded to multiples of eight couplings (own column, zero
-// coupling); each chunk of eight is one scalar load of columns, one of
-// couplings, then eight gathers in flight, summed in CSR order (the padding
-// adds exact zeros).
+// State x, y is FP32 in HBM, spin-major with agents contiguous.  One wave
+// handles one row i for 64 * APL agents (lane l: agents base + 64 k + l), so
+// a row's columns and couplings are wave-uniform scalar loads shared by
+// all its agents, and every x_j gather is APL coalesced 256-byte lines.
+// Rows are padded to multiples of eight couplings (own column, zero
+// coupling); each chunk of eight is one scalar load of columns and one of
+// couplings, summed in CSR order (the padding adds exact zeros).
 //
-// dSB reads only the neighbours' signs, kept as one 64-bit word per
-// (spin, 64-agent block) -- a ballot of x >= 0 -- in two alternating
-// planes; x and y are then updated in place.  bSB gathers x itself from the
-// previous step's buffer.
+// dSB reads only the neighbours' signs, kept as 64-bit words -- ballots of
+// x >= 0 over 64 agents -- in two alternating planes, so x and y update in
+// place and the coupling sum needs no gather of x at all: a sign word is
+// itself the lane mask that picks +J_ij or -J_ij for every lane at once.
 //
 // Workgroups are numbered so that each XCD (workgroups are dealt to the 8
 // XCDs round robin) sweeps one contiguous range of rows: neighbouring rows
@@ -75,14 +75,14 @@ __device__ __forceinline__ bool map_block(int nrb, int nab, int &rb, int &ab) {
 
 }  // namespace
 
-// Sign planes from the current positions: S[i * MW + w] bit l = x[i, 64 w + l] >= 0.
-__global__ __launch_bounds__(256) void sign_planes(int n, int M, const float *__restrict__ x,
+// Sign planes from the current positions: S[i * SW + w] bit l =
+// x[i, 64 w + l] >= 0 (0 for agents >= M).
+__global__ __launch_bounds__(256) void sign_planes(int n, int M, int SW, const float *__restrict__ x,
                                                    uint64_t *__restrict__ S) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int MW = (M + 63) / 64;
     const int64_t idx = static_cast<int64_t>(blockIdx.x) * 4 + wave;  // (row, word)
-    if (idx >= static_cast<int64_t>(n) * MW) return;
-    const int i = static_cast<int>(idx / MW), w = static_cast<int>(idx % MW);
+    if (idx >= static_cast<int64_t>(n) * SW) return;
+    const int i = static_cast<int>(idx / SW), w = static_cast<int>(idx % SW);
     const int m = w * 64 + lane;
     const bool pos = m < M && x[static_cast<size_t>(i) * M + m] >= 0.0f;
     const uint64_t bal = __ballot(pos);
@@ -151,25 +151,34 @@ __global__ __launch_bounds__(256) void quantize_fp8_rows(int n, const int *__res
     }
 }
 
-template <int MODE, int JP>
-__global__ __launch_bounds__(256) void sb_stream2(StreamArgs A, int k, const float *xin, float *xout,
-                                                  const uint64_t *__restrict__ Sin,
-                                                  uint64_t *__restrict__ Sout) {
+template <int MODE, int JP, int APL>
+__global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const float *xin, float *xout,
+                                                 const uint64_t *__restrict__ Sin,
+                                                 uint64_t *__restrict__ Sout) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int M = A.M, MW = (M + 63) / 64;
+    const int M = A.M, SW = A.sign_stride;
     const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
+    const int nab = (M + 64 * APL - 1) / (64 * APL);
     int rb, ab;
-    if (!map_block(nrb, MW, rb, ab)) return;
+    if (!map_block(nrb, nab, rb, ab)) return;
     const int i = __builtin_amdgcn_readfirstlane(rb * kRowsPerWG + wave);
     if (i >= A.n) return;
-    const int m = ab * 64 + lane;
-    const bool live = m < M;
+    const int base = ab * 64 * APL;
+    bool live[APL];
+    int mcol[APL];  // agent column; dead lanes read column 0 (in bounds, one line)
+#pragma unroll
+    for (int a = 0; a < APL; ++a) {
+        const int m = base + 64 * a + lane;
+        live[a] = m < M;
+        mcol[a] = live[a] ? m : 0;
+    }
     const float c0 = static_cast<float>(A.scal[0]);
     const float g = A.sched[k];
     const float scale = JP == kJFp8 ? A.rowscale[i] : 1.0f;
     const int p0 = A.row_ptr[i], p1 = A.row_ptr[i + 1];
-    float acc = A.h[i];
-    const size_t mcol = static_cast<size_t>(live ? m : 0);
+    float acc[APL];
+#pragma unroll
+    for (int a = 0; a < APL; ++a) acc[a] = A.h[i];
     for (int p = p0; p < p1; p += kChunk) {
         const int4 ca = *reinterpret_cast<const int4 *>(A.col + p);
         const int4 cb = *reinterpret_cast<const int4 *>(A.col + p + 4);
@@ -177,39 +186,102 @@ __global__ __launch_bounds__(256) void sb_stream2(StreamArgs A, int k, const flo
         float w[kChunk];
         load_chunk<JP>(A, p, scale, w);
         if constexpr (MODE == kDSB) {
-            // neighbours' signs: one scalar 64-bit word per coupling
-            uint64_t sw[kChunk];
-#pragma unroll
-            for (int u = 0; u < kChunk; ++u) sw[u] = Sin[static_cast<size_t>(c[u]) * MW + ab];
 #pragma unroll
             for (int u = 0; u < kChunk; ++u) {
-                const float sg = ((sw[u] >> lane) & 1ull) ? 1.0f : -1.0f;
-                acc = __builtin_fmaf(w[u], sg, acc);
+                const uint64_t *rec = Sin + static_cast<size_t>(c[u]) * SW + ab * APL;
+#pragma unroll
+                for (int a = 0; a < APL; ++a) {
+                    // J sgn(x_j) = +-J exactly: same value as fma(J, +-1, acc)
+                    const bool pos = __builtin_amdgcn_inverse_ballot_w64(rec[a]);
+                    acc[a] += pos ? w[u] : -w[u];
+                }
             }
         } else {
-            float v[kChunk];
+            float v[kChunk][APL];
 #pragma unroll
-            for (int u = 0; u < kChunk; ++u) v[u] = xin[static_cast<size_t>(c[u]) * M + mcol];
+            for (int u = 0; u < kChunk; ++u) {
+                const float *row = xin + static_cast<size_t>(c[u]) * M;
 #pragma unroll
-            for (int u = 0; u < kChunk; ++u) acc = __builtin_fmaf(w[u], v[u], acc);
+                for (int a = 0; a < APL; ++a) v[u][a] = row[mcol[a]];
+            }
+#pragma unroll
+            for (int u = 0; u < kChunk; ++u)
+#pragma unroll
+                for (int a = 0; a < APL; ++a) acc[a] = __builtin_fmaf(w[u], v[u][a], acc[a]);
         }
     }
-    const size_t o = static_cast<size_t>(i) * M + mcol;
-    float x = live ? xin[o] : 0.0f, y = live ? A.y[o] : 0.0f;
-    sb_update(x, y, acc, c0, g, A.dt, A.dta0);
-    if (live) {
-        xout[o] = x;
-        A.y[o] = y;
-    }
-    if constexpr (MODE == kDSB) {
-        const uint64_t bal = __ballot(live && x >= 0.0f);
-        if (lane == 0) Sout[static_cast<size_t>(i) * MW + ab] = bal;
+    const size_t o = static_cast<size_t>(i) * M;
+#pragma unroll
+    for (int a = 0; a < APL; ++a) {
+        float x = live[a] ? xin[o + mcol[a]] : 0.0f;
+        float y = live[a] ? A.y[o + mcol[a]] : 0.0f;
+        sb_update(x, y, acc[a], c0, g, A.dt, A.dta0);
+        if (live[a]) {
+            xout[o + mcol[a]] = x;
+            A.y[o + mcol[a]] = y;
+        }
+        if constexpr (MODE == kDSB) {
+            const uint64_t bal = __ballot(live[a] && x >= 0.0f);
+            if (lane == 0) Sout[static_cast<size_t>(i) * SW + ab * APL + a] = bal;
+        }
     }
 }
 
+// bSB with four consecutive agents per lane (M a multiple of 4): one
+// 16-byte gather per coupling and lane, 256 agents per wave.
+template <int JP>
+__global__ __launch_bounds__(256) void sb_stream_v4(StreamArgs A, int k, const float *xin,
+                                                    float *xout) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int M = A.M;
+    const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
+    const int nab = (M + 255) / 256;
+    int rb, ab;
+    if (!map_block(nrb, nab, rb, ab)) return;
+    const int i = __builtin_amdgcn_readfirstlane(rb * kRowsPerWG + wave);
+    if (i >= A.n) return;
+    const int m = ab * 256 + 4 * lane;
+    const bool live = m < M;
+    const int mcol = live ? m : 0;  // dead lanes read agents 0..3 (in bounds)
+    const float c0 = static_cast<float>(A.scal[0]);
+    const float g = A.sched[k];
+    const float scale = JP == kJFp8 ? A.rowscale[i] : 1.0f;
+    const int p0 = A.row_ptr[i], p1 = A.row_ptr[i + 1];
+    float4 acc = make_float4(A.h[i], A.h[i], A.h[i], A.h[i]);
+    for (int p = p0; p < p1; p += kChunk) {
+        const int4 ca = *reinterpret_cast<const int4 *>(A.col + p);
+        const int4 cb = *reinterpret_cast<const int4 *>(A.col + p + 4);
+        const int c[kChunk] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y, cb.z, cb.w};
+        float w[kChunk];
+        load_chunk<JP>(A, p, scale, w);
+        float4 v[kChunk];
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u)
+            v[u] = *reinterpret_cast<const float4 *>(xin + static_cast<size_t>(c[u]) * M + mcol);
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) {
+            acc.x = __builtin_fmaf(w[u], v[u].x, acc.x);
+            acc.y = __builtin_fmaf(w[u], v[u].y, acc.y);
+            acc.z = __builtin_fmaf(w[u], v[u].z, acc.z);
+            acc.w = __builtin_fmaf(w[u], v[u].w, acc.w);
+        }
+    }
+    if (!live) return;
+    const size_t o = static_cast<size_t>(i) * M + mcol;
+    float4 x = *reinterpret_cast<const float4 *>(xin + o);
+    float4 y = *reinterpret_cast<const float4 *>(A.y + o);
+    sb_update(x.x, y.x, acc.x, c0, g, A.dt, A.dta0);
+    sb_update(x.y, y.y, acc.y, c0, g, A.dt, A.dta0);
+    sb_update(x.z, y.z, acc.z, c0, g, A.dt, A.dta0);
+    sb_update(x.w, y.w, acc.w, c0, g, A.dt, A.dta0);
+    *reinterpret_cast<float4 *>(xout + o) = x;
+    *reinterpret_cast<float4 *>(A.y + o) = y;
+}
+
 hipError_t launch_sign_planes(int n, int M, const float *x, uint64_t *S, hipStream_t st) {
-    const int64_t words = static_cast<int64_t>(n) * ((M + 63) / 64);
-    sign_planes<<<static_cast<unsigned>((words + 3) / 4), 256, 0, st>>>(n, M, x, S);
+    const int SW = stream_sign_stride(M);
+    const int64_t words = static_cast<int64_t>(n) * SW;
+    sign_planes<<<static_cast<unsigned>((words + 3) / 4), 256, 0, st>>>(n, M, SW, x, S);
     return hipGetLastError();
 }
 
@@ -226,23 +298,43 @@ hipError_t launch_quantize_fp8(int n, const int *row_ptr, const float *J, uint8_
     return hipGetLastError();
 }
 
-hipError_t launch_stream2(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
-                          float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st) {
+namespace {
+
+template <int MODE, int JP>
+hipError_t launch_stream_apl(const StreamArgs &A, int k, const float *xin, float *xout,
+                             const uint64_t *Sin, uint64_t *Sout, hipStream_t st) {
+    const int apl = stream_apl(A.M, MODE);
     const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
-    const int total = nrb * ((A.M + 63) / 64);
+    const int total = nrb * ((A.M + 64 * apl - 1) / (64 * apl));
     const int grid = (total + 7) / 8 * 8;
-    if (mode == kDSB) {
-        if (jprec == kJFp8)
-            sb_stream2<kDSB, kJFp8><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout);
-        else
-            sb_stream2<kDSB, kJFp32><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout);
-    } else {
-        if (jprec == kJFp8)
-            sb_stream2<kBSB, kJFp8><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout);
-        else
-            sb_stream2<kBSB, kJFp32><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout);
+    switch (apl) {
+        case 8: sb_stream<MODE, JP, 8><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
+        case 4: sb_stream<MODE, JP, 4><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
+        case 2: sb_stream<MODE, JP, 2><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
+        default: sb_stream<MODE, JP, 1><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stream2(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
+                          float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st) {
+    if (mode == kDSB)
+        return jprec == kJFp8 ? launch_stream_apl<kDSB, kJFp8>(A, k, xin, xout, Sin, Sout, st)
+                              : launch_stream_apl<kDSB, kJFp32>(A, k, xin, xout, Sin, Sout, st);
+    if (A.M % 4 == 0 && A.M > 64) {
+        const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
+        const int total = nrb * ((A.M + 255) / 256);
+        const int grid = (total + 7) / 8 * 8;
+        if (jprec == kJFp8)
+            sb_stream_v4<kJFp8><<<grid, 256, 0, st>>>(A, k, xin, xout);
+        else
+            sb_stream_v4<kJFp32><<<grid, 256, 0, st>>>(A, k, xin, xout);
+        return hipGetLastError();
+    }
+    return jprec == kJFp8 ? launch_stream_apl<kBSB, kJFp8>(A, k, xin, xout, Sin, Sout, st)
+                          : launch_stream_apl<kBSB, kJFp32>(A, k, xin, xout, Sin, Sout, st);
 }
 
 }  // namespace sbt

@@ -57,7 +57,7 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
     L.epart = take(sizeof(double) * nblk_e * M);
     L.etrace = take(sizeof(double) * static_cast<size_t>(L.n_ckpt) * M);
     if (mode == SBT_DSB) {
-        const size_t words = static_cast<size_t>(n) * ((static_cast<size_t>(M) + 63) / 64);
+        const size_t words = static_cast<size_t>(n) * sbt::stream_sign_stride(M);
         L.S0 = take(sizeof(uint64_t) * words);
         L.S1 = take(sizeof(uint64_t) * words);
     }
@@ -342,6 +342,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         A.scal = scal;
         A.y = dy;
         A.sched = sched;
+        A.sign_stride = sbt::stream_sign_stride(M);
         const bool fp8 = p->precision == SBT_PREC_FP8;
         if (fp8) {
             SBT_HIP(sbt::launch_quantize_fp8(n, prow, pJ, J8, rowscale, st));
