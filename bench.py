@@ -155,6 +155,64 @@ def batched_form(sbt, tg, torch, np):
     return out
 
 
+def stream_bytes(n, nnz, agents, jbytes):
+    """Algorithmic HBM bytes of one streaming-kernel launch (one SB step):
+    x, y read and written per spin update, each coupling's column and value
+    once, h, row pointers and the per-row scale once."""
+    return 16.0 * n * agents + (4.0 + jbytes) * nnz + 12.0 * n
+
+
+def stress_form(sbt, tg, torch, np, K=10000):
+    """5000 particles (N ~ 2.1e5), bSB, 512 agents x 10000 steps on the
+    streaming kernel: FP8 couplings (the workload's storage) and FP32, spins
+    in azimuth order, FP64 energies of every agent on the GPU."""
+    ev = tg.generate(tg.stress_spec(), 300)
+    hits = ev.hits_struct()
+    bp = sbt.build_params_default()
+    bp.z0_max = tg.STRESS_Z0_MAX
+    t0 = time.perf_counter()
+    q0 = sbt.build_qubo(hits, bp)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    q = sbt.permute_qubo(q0, sbt.phi_order(q0, hits))
+    t_order = time.perf_counter() - t0
+    del q0
+    M = 512
+    out = {"workload": "stress: 10-layer barrel, 5000 particles + 20% noise, |eta| < 2, event "
+                       f"seed 300, doublet |z0| <= 300 mm; bSB, 512 agents x {K} steps, "
+                       "spins in azimuth order",
+           "n": q.n, "nnz": q.nnz, "host_build_s": t_build, "host_order_s": t_order}
+    for prec in ("fp8", "fp32"):
+        s = sbt.DeviceSolver(q, "bsb", sbt.solve_params(agents=M, steps=K, seed=0,
+                                                         kernel="stream", precision=prec))
+        b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.record()
+        e.record()
+        torch.cuda.synchronize()
+        s._dr.step_begin, s._dr.step_end = b.cuda_event, e.cuda_event
+        t0 = time.perf_counter()
+        s.run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s._dr.step_begin = s._dr.step_end = None
+        launch_s = b.elapsed_time(e) * 1e-3 / K
+        r = s.result()
+        E = np.sort(r["agent_energy"])
+        byts = stream_bytes(q.n, q.nnz, M, 1 if prec == "fp8" else 4)
+        achieved = byts / launch_s / 1e9
+        out[prec] = {"seconds": wall, "spin_updates_per_s": q.n * M * K / wall,
+                     "best": r["energy"], "mean_best_32": float(E[:32].mean()),
+                     "roofline": {"bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_GBS,
+                                  "unit": "GB/s", "frac": achieved / MI355X_HBM_GBS,
+                                  "traffic": measured_traffic(f"sb_stream_stress_{prec}.md"),
+                                  "kernel": "sb_stream_v4", "launch_ms": launch_s * 1e3,
+                                  "bytes_per_launch": byts}}
+        del s
+        torch.cuda.empty_cache()
+    out["fp8_rel_gap_vs_fp32"] = (out["fp8"]["best"] - out["fp32"]["best"]) / abs(out["fp32"]["best"])
+    return out
+
+
 def measured_traffic(profile_name):
     """HBM bytes per launch from the committed rocprofv3 counter record, or
     None when the kernel's sources changed after the counters were taken."""
@@ -178,10 +236,14 @@ def cpu_baseline(q, n_target_s=12.0):
     b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
     isg = oising.from_qubo(q.a, b)
     with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for mode in ("bsb", "dsb"):
-            osb.run(isg.J, isg.h, isg.c0, mode, AGENTS, 20, seed=SOLVER_SEED)
-        per_step = (time.perf_counter() - t0) / 40.0
+        # per-step cost from the difference of two run lengths (the start-up
+        # draw and set-up cancel out)
+        t = []
+        for k in (20, 120):
+            t0 = time.perf_counter()
+            osb.run(isg.J, isg.h, isg.c0, "bsb", AGENTS, k, seed=SOLVER_SEED)
+            t.append(time.perf_counter() - t0)
+        per_step = max(1e-6, (t[1] - t[0]) / 100.0)
         k = max(20, int(n_target_s / (2.0 * per_step)))
         t0 = time.perf_counter()
         for mode in ("bsb", "dsb"):
@@ -201,7 +263,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttt", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the precision (1000 particles) and batched (512 events) forms")
+                    help="skip the precision (1000 particles), batched (512 events) and stress "
+                         "(5000 particles) forms")
+    ap.add_argument("--only-stress", action="store_true",
+                    help="run only the stress form (for profiling the streaming kernel)")
+    ap.add_argument("--stress-steps", type=int, default=10000,
+                    help="SB steps of the stress form (10000 is the workload's)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
@@ -229,6 +296,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.only_stress:
+        print(json.dumps({"stress_form": stress_form(sbt, tg, torch, np, args.stress_steps)}),
+              flush=True)
+        return
     log("building the event QUBO on the host")
     ev = tg.generate(tg.plain_spec(), EVENT_SEED)
     q = sbt.build_qubo(ev.hits_struct())
@@ -320,6 +391,8 @@ def main():
         log("precision form done")
         result["batched_form"] = batched_form(sbt, tg, torch, np)
         log("batched form done")
+        result["stress_form"] = stress_form(sbt, tg, torch, np, args.stress_steps)
+        log("stress form done")
 
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")

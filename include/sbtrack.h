@@ -104,6 +104,24 @@ int sbt_build_qubo(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *
                    sbt_qubo **out);
 void sbt_qubo_free(sbt_qubo *q);
 
+/* Spin order for the solver's caches (a relabelling only; the section
+ * "QUBO formulation" fixes the problem, not its index order): triplets
+ * sorted by the azimuth of their middle hit, then its z, then index.  The
+ * azimuth is compared through the exact monotone key 1 - x/(|x|+|y|) for
+ * y >= 0 and 3 + x/(|x|+|y|) for y < 0 (0 for x = y = 0).
+ *   q     QUBO from sbt_build_qubo (its trip_hits name hit ids)
+ *   hits  the hits it was built from, any order
+ *   perm  caller [n]: perm[k] = original index of the triplet placed at k
+ * Errors: SBT_EINVAL for NULL arrays or a triplet naming an absent hit. */
+int sbt_phi_order(const sbt_qubo *q, const sbt_hit *hits, int64_t n_hits, int32_t *perm);
+
+/* The same QUBO with spins relabelled: row/column k of the result is
+ * row/column perm[k] of q (columns ascending again), a and trip_hits
+ * follow.  O(T') of the result equals O(T) of q for T'[k] = T[perm[k]].
+ * Library-owned result; free with sbt_qubo_free.
+ * Errors: SBT_EINVAL if perm is not a permutation of 0..n-1. */
+int sbt_qubo_permute(const sbt_qubo *q, const int32_t *perm, sbt_qubo **out);
+
 /* Exact FP64 value of Eq. 13 for a binary assignment (host, compensated
  * summation, rows in order, pairs j > i).  T host [n] of 0/1. */
 int sbt_energy(const sbt_qubo *q, const int8_t *T, double *energy);

@@ -81,6 +81,12 @@ def build_qubo(hits: np.ndarray, params: Optional[_lib.SbtBuildParams] = None) -
     out = C.POINTER(_lib.SbtQubo)()
     check(lib.sbt_build_qubo(hits.ctypes.data_as(C.POINTER(_lib.SbtHit)), hits.shape[0],
                              C.byref(params) if params is not None else None, C.byref(out)))
+    return _take_qubo(out)
+
+
+def _take_qubo(out) -> Qubo:
+    """Copy a library-owned sbt_qubo into a Qubo and free it."""
+    lib = load()
     try:
         q = out.contents
         n, nnz = int(q.n), int(q.nnz)
@@ -96,6 +102,29 @@ def build_qubo(hits: np.ndarray, params: Optional[_lib.SbtBuildParams] = None) -
     finally:
         lib.sbt_qubo_free(out)
     return res
+
+
+def phi_order(q: Qubo, hits: np.ndarray) -> np.ndarray:
+    """sbt_phi_order: triplets sorted by the azimuth (then z) of their
+    middle hit; perm[k] = original index of the triplet placed at k."""
+    hits = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    perm = np.zeros(max(q.n, 1), dtype=np.int32)
+    s = q.as_struct()
+    check(load().sbt_phi_order(C.byref(s), hits.ctypes.data_as(C.POINTER(_lib.SbtHit)),
+                               hits.shape[0], perm.ctypes.data_as(C.POINTER(C.c_int32))))
+    return perm[:q.n]
+
+
+def permute_qubo(q: Qubo, perm: np.ndarray) -> Qubo:
+    """sbt_qubo_permute: spin k of the result is spin perm[k] of q."""
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    if perm.shape != (q.n,):
+        raise ValueError("perm must have shape (n,)")
+    s = q.as_struct()
+    out = C.POINTER(_lib.SbtQubo)()
+    check(load().sbt_qubo_permute(C.byref(s), perm.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  C.byref(out)))
+    return _take_qubo(out)
 
 
 def energy(q: Qubo, T: np.ndarray) -> float:
@@ -362,6 +391,7 @@ class DeviceBatchSolver:
 
 
 __all__ = ["Qubo", "DeviceSolver", "DeviceBatchSolver", "build_qubo", "energy", "solve",
+           "phi_order", "permute_qubo",
            "solve_batch", "solve_params", "workspace_bytes", "select_kernel",
            "build_params_default", "version", "load", "SbtError", "HIT_DTYPE", "MODES",
            "KERNELS", "PRECISIONS"]

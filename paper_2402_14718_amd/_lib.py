@@ -104,6 +104,10 @@ EXPORTS = [
                                  C.POINTER(C.POINTER(SbtQubo))]),
     ("sbt_qubo_free", None, [C.POINTER(SbtQubo)]),
     ("sbt_energy", C.c_int, [C.POINTER(SbtQubo), C.POINTER(C.c_int8), C.POINTER(C.c_double)]),
+    ("sbt_phi_order", C.c_int, [C.POINTER(SbtQubo), C.POINTER(SbtHit), C.c_int64,
+                                C.POINTER(C.c_int32)]),
+    ("sbt_qubo_permute", C.c_int, [C.POINTER(SbtQubo), C.POINTER(C.c_int32),
+                                   C.POINTER(C.POINTER(SbtQubo))]),
     ("sbt_solve_params_default", None, [C.POINTER(SbtSolveParams)]),
     ("sbt_solve", C.c_int, [C.POINTER(SbtQubo), C.c_int, C.POINTER(SbtSolveParams),
                             C.POINTER(SbtResult)]),

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["status.cpp", "build_qubo.cpp"]
+HOST_SOURCES = ["status.cpp", "build_qubo.cpp", "order.cpp"]
 RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
 HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_batch.hip", "sb_stream.hip"]
 

@@ -33,6 +33,29 @@ namespace sbt {
 namespace {
 
 constexpr int kRowsPerWG = 4;  // one row per wave, 256 threads
+// Own-row x, y are touched once per step: stream them past L2 so the
+// gathered x_j lines of neighbouring rows stay resident.
+constexpr bool kStreamNT = true;
+// bSB with M % 4 == 0: four consecutive agents per lane (16-byte gathers).
+constexpr bool kStreamVec4 = true;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+    if constexpr (kStreamNT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <class T>
+__device__ __forceinline__ void st_stream(T v, T *p) {
+    if constexpr (kStreamNT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
 constexpr int kChunk = kStreamChunk;
 constexpr int kPackThreads = 1024;
 
@@ -213,12 +236,12 @@ __global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const floa
     const size_t o = static_cast<size_t>(i) * M;
 #pragma unroll
     for (int a = 0; a < APL; ++a) {
-        float x = live[a] ? xin[o + mcol[a]] : 0.0f;
-        float y = live[a] ? A.y[o + mcol[a]] : 0.0f;
+        float x = live[a] ? ld_stream(xin + o + mcol[a]) : 0.0f;
+        float y = live[a] ? ld_stream(A.y + o + mcol[a]) : 0.0f;
         sb_update(x, y, acc[a], c0, g, A.dt, A.dta0);
         if (live[a]) {
-            xout[o + mcol[a]] = x;
-            A.y[o + mcol[a]] = y;
+            st_stream(x, xout + o + mcol[a]);
+            st_stream(y, A.y + o + mcol[a]);
         }
         if constexpr (MODE == kDSB) {
             const uint64_t bal = __ballot(live[a] && x >= 0.0f);
@@ -268,14 +291,14 @@ __global__ __launch_bounds__(256) void sb_stream_v4(StreamArgs A, int k, const f
     }
     if (!live) return;
     const size_t o = static_cast<size_t>(i) * M + mcol;
-    float4 x = *reinterpret_cast<const float4 *>(xin + o);
-    float4 y = *reinterpret_cast<const float4 *>(A.y + o);
-    sb_update(x.x, y.x, acc.x, c0, g, A.dt, A.dta0);
-    sb_update(x.y, y.y, acc.y, c0, g, A.dt, A.dta0);
-    sb_update(x.z, y.z, acc.z, c0, g, A.dt, A.dta0);
-    sb_update(x.w, y.w, acc.w, c0, g, A.dt, A.dta0);
-    *reinterpret_cast<float4 *>(xout + o) = x;
-    *reinterpret_cast<float4 *>(A.y + o) = y;
+    const f32x4 xv = ld_stream(reinterpret_cast<const f32x4 *>(xin + o));
+    const f32x4 yv = ld_stream(reinterpret_cast<const f32x4 *>(A.y + o));
+    float x[4] = {xv.x, xv.y, xv.z, xv.w}, y[4] = {yv.x, yv.y, yv.z, yv.w};
+    const float f[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) sb_update(x[a], y[a], f[a], c0, g, A.dt, A.dta0);
+    st_stream(f32x4{x[0], x[1], x[2], x[3]}, reinterpret_cast<f32x4 *>(xout + o));
+    st_stream(f32x4{y[0], y[1], y[2], y[3]}, reinterpret_cast<f32x4 *>(A.y + o));
 }
 
 hipError_t launch_sign_planes(int n, int M, const float *x, uint64_t *S, hipStream_t st) {
@@ -323,7 +346,7 @@ hipError_t launch_stream2(int mode, int jprec, const StreamArgs &A, int k, const
     if (mode == kDSB)
         return jprec == kJFp8 ? launch_stream_apl<kDSB, kJFp8>(A, k, xin, xout, Sin, Sout, st)
                               : launch_stream_apl<kDSB, kJFp32>(A, k, xin, xout, Sin, Sout, st);
-    if (A.M % 4 == 0 && A.M > 64) {
+    if (kStreamVec4 && A.M % 4 == 0 && A.M > 64) {
         const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
         const int total = nrb * ((A.M + 255) / 256);
         const int grid = (total + 7) / 8 * 8;

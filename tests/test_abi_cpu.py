@@ -174,3 +174,38 @@ def test_solve_rejects_malformed_qubo_before_touching_a_device():
     nanq.a[0] = np.inf
     with pytest.raises(sbt.SbtError):
         sbt.solve(nanq, "bsb", agents=4, steps=5)
+
+
+@pytest.mark.parametrize("spec,seed", [(tg.plain_spec(), 100), (tg.plain_spec(300), 3),
+                                       (tg.tiny_spec(), 2)])
+def test_phi_order_and_permutation_bit_exact_with_oracle(spec, seed):
+    from oracle import order as oorder
+    ev = tg.generate(spec, seed)
+    hits = ev.hits_struct()
+    q = sbt.build_qubo(hits)
+    perm = sbt.phi_order(q, hits[::-1])           # hit order must not matter
+    o = oorder.phi_order(q.trip_hits, ev.hit_id, ev.x, ev.y, ev.z)
+    assert np.array_equal(perm, o)
+    qp = sbt.permute_qubo(q, perm)
+    import scipy.sparse as sp
+    a2, b2, th2 = oorder.permute(q.a, sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n)),
+                                 q.trip_hits, o)
+    assert np.array_equal(qp.a, a2) and np.array_equal(qp.trip_hits, th2)
+    assert np.array_equal(qp.row_ptr, b2.indptr) and np.array_equal(qp.col, b2.indices)
+    assert np.array_equal(qp.b, b2.data)
+    T = (np.random.default_rng(seed).random(q.n) < 0.4).astype(np.int8)
+    assert abs(sbt.energy(qp, T[perm]) - sbt.energy(q, T)) <= 1e-12 * max(1.0, abs(sbt.energy(q, T)))
+
+
+def test_permutation_rejects_bad_input():
+    ev = tg.generate(tg.tiny_spec(), 1)
+    hits = ev.hits_struct()
+    q = sbt.build_qubo(hits)
+    bad = np.arange(q.n, dtype=np.int32)
+    bad[0] = bad[1]
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.permute_qubo(q, bad)
+    assert e.value.code == _lib.SBT_EINVAL
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.phi_order(q, hits[:3])                # triplets name hits not given
+    assert e.value.code == _lib.SBT_EINVAL
