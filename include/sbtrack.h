@@ -141,8 +141,10 @@ typedef enum {
                                 HBM, lanes are agents                       */
 } sbt_kernel;
 
-/* Storage precision of the couplings J (the reduced-precision forms of the
- * paper's FP16 runs; accumulation is FP32 and energies FP64 throughout).
+/* Storage precision of the couplings J.  The paper fixes no number format
+ * (section "Simulated Bifurcation" states the dynamics only); the narrow
+ * forms are this library's: only J is stored narrower, accumulation is FP32
+ * and energies are FP64 of the exact QUBO throughout.
  * FP8 is OCP e4m3 with one FP32 scale per row, max_j |J_ij| / 448. */
 typedef enum {
     SBT_PREC_FP32 = 0,

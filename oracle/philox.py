@@ -64,9 +64,11 @@ def word_to_uniform(r) -> np.ndarray:
     return ((r >> 8) - (1 << 23)).astype(np.float64) * 2.0 ** -26
 
 
-def initial_state(n: int, agents: int, seed: int, event: int = 0):
-    """x0, y0 of shape [n, agents] (spin-major, agents contiguous), FP64."""
-    i = np.arange(n, dtype=np.uint64)[:, None]
+def initial_state(n: int, agents: int, seed: int, event: int = 0, spins=None):
+    """x0, y0 of shape [n, agents] (spin-major, agents contiguous), FP64.
+    With `spins` (an index array) only those spins' rows are drawn."""
+    i = (np.arange(n, dtype=np.uint64) if spins is None
+         else np.asarray(spins, dtype=np.uint64))[:, None]
     m = np.arange(agents, dtype=np.uint64)[None, :]
     seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     r0, r1, _, _ = philox4x32_10(i, m, np.uint64(event), np.uint64(0),

@@ -3,8 +3,8 @@
 Test infrastructure: only the tests, the smoke check and the benchmark's
 CPU baseline use this package.
 
-The paper runs SB in reduced precision on its GPUs (Results); here J is
-stored in a narrow format while positions, momenta and accumulation stay
+The paper fixes no number format for SB; the library offers forms that
+store J in a narrow format while positions, momenta and accumulation stay
 FP32 and energies FP64.  This module writes out the FP8 form:
 
 * OCP 8-bit E4M3 ("e4m3fn"): sign bit, 4 exponent bits with bias 7, 3
