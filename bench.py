@@ -154,7 +154,7 @@ def precision_form(sbt, tg, torch, np):
     return out
 
 
-def batched_form(sbt, tg, torch, np):
+def batched_form(sbt, tg, torch, np, with_fp32=True):
     """512 events of 20-1000 particles, dSB, 128 agents x 3000 steps: one
     persistent batched kernel (FP16 / BF16 couplings) against plain FP32
     solving the events one at a time.  Per-event energies are compared with
@@ -163,30 +163,53 @@ def batched_form(sbt, tg, torch, np):
     qs = [sbt.build_qubo(tg.generate(s, seed).hits_struct()) for s, seed in specs]
     M, K = 128, 3000
     sum_n = sum(q.n for q in qs)
+    sum_nnz = sum(q.nnz for q in qs)
     out = {"workload": "batching: 512 events, 20 + floor(981 U) particles (U from seed 999), "
                        "event seeds 1000-1511; dSB, 128 agents x 3000 steps",
            "events": len(qs), "sum_n": sum_n, "max_n": max(q.n for q in qs)}
-    plain = [sbt.DeviceSolver(q, "dsb", sbt.solve_params(agents=M, steps=K, seed=0, event=e))
-             for e, q in enumerate(qs)]
+    if with_fp32:
+        plain = [sbt.DeviceSolver(q, "dsb", sbt.solve_params(agents=M, steps=K, seed=0, event=e))
+                 for e, q in enumerate(qs)]
 
-    def run_plain():
-        for s in plain:
-            s.run()
+        def run_plain():
+            for s in plain:
+                s.run()
 
-    t = timed_runs(run_plain, torch, reps=1)
-    e32 = np.array([float(s.best_energy.item()) for s in plain])
-    out["fp32_one_event_at_a_time"] = {"seconds": t, "spin_updates_per_s": sum_n * M * K / t}
-    del plain
+        t = timed_runs(run_plain, torch, reps=1)
+        e32 = np.array([float(s.best_energy.item()) for s in plain])
+        out["fp32_one_event_at_a_time"] = {"seconds": t, "spin_updates_per_s": sum_n * M * K / t}
+        del plain
+        log("batched form: FP32 one event at a time done")
     for prec in ("fp16", "bf16"):
         bs = sbt.DeviceBatchSolver(qs, "dsb", prec, sbt.solve_params(agents=M, steps=K, seed=0))
         tb = timed_runs(bs.run, torch, reps=2)
-        eb = bs.result()["energy"]
-        gap = (eb - e32) / np.abs(e32)
+        # the batch kernel's own duration, on its stream, from the library's step events
+        b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.record()
+        e.record()
+        torch.cuda.synchronize()
+        bs._dr.step_begin, bs._dr.step_end = b.cuda_event, e.cuda_event
+        bs.run()
+        torch.cuda.synchronize()
+        bs._dr.step_begin = bs._dr.step_end = None
+        launch_s = b.elapsed_time(e) * 1e-3
+        flops = float(K) * M * (2.0 * sum_nnz + 8.0 * sum_n)
+        achieved = flops / launch_s / 1e12
         out[prec] = {"seconds": tb, "spin_updates_per_s": sum_n * M * K / tb,
-                     "speedup_vs_fp32": t / tb, "work_items": bs.n_items,
-                     "rel_energy_gap_vs_fp32": {"mean": float(gap.mean()), "max": float(gap.max()),
-                                                "min": float(gap.min())},
-                     "events_within_0.5pct_of_fp32": int(np.sum(gap <= 0.005))}
+                     "work_items": bs.n_items,
+                     "roofline": {"bound": "alu", "achieved": achieved,
+                                  "peak": MI355X_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": achieved / MI355X_FP32_VECTOR_TFLOPS,
+                                  "traffic": measured_traffic(f"sb_batch_batching_{prec}.md"),
+                                  "kernel": "sb_batch", "launch_ms": launch_s * 1e3}}
+        if with_fp32:
+            gap = (bs.result()["energy"] - e32) / np.abs(e32)
+            out[prec].update({"speedup_vs_fp32": t / tb,
+                              "rel_energy_gap_vs_fp32": {"mean": float(gap.mean()),
+                                                         "max": float(gap.max()),
+                                                         "min": float(gap.min())},
+                              "events_within_0.5pct_of_fp32": int(np.sum(gap <= 0.005))})
+        log(f"batched form: {prec} batch done")
     return out
 
 
@@ -302,8 +325,11 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision (1000 particles), batched (512 events) and stress "
                          "(5000 particles) forms")
-    ap.add_argument("--only-stress", action="store_true",
-                    help="run only the stress form (for profiling the streaming kernel)")
+    ap.add_argument("--only", choices=["precision", "batched", "stress"],
+                    help="run only this form and print it (for profiling one kernel)")
+    ap.add_argument("--batch-skip-fp32", action="store_true",
+                    help="batched form without the FP32 one-event-at-a-time comparison "
+                         "(for counter collection)")
     ap.add_argument("--stress-steps", type=int, default=10000,
                     help="SB steps of the stress form (10000 is the workload's)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
@@ -333,9 +359,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
-    if args.only_stress:
-        print(json.dumps({"stress_form": stress_form(sbt, tg, torch, np, args.stress_steps)}),
-              flush=True)
+    if args.only:
+        form = {"precision": lambda: precision_form(sbt, tg, torch, np),
+                "batched": lambda: batched_form(sbt, tg, torch, np, not args.batch_skip_fp32),
+                "stress": lambda: stress_form(sbt, tg, torch, np, args.stress_steps)}[args.only]
+        print(json.dumps({f"{args.only}_form": form()}), flush=True)
         return
     log("building the event QUBO on the host")
     ev = tg.generate(tg.plain_spec(), EVENT_SEED)

@@ -33,25 +33,27 @@ namespace sbt {
 namespace {
 
 constexpr int kRowsPerWG = 4;  // one row per wave, 256 threads
-// Own-row x, y are touched once per step: stream them past L2 so the
-// gathered x_j lines of neighbouring rows stay resident.
-constexpr bool kStreamNT = true;
+// Own-row x, y are touched once per step.  When the state is larger than
+// the 256 MB Infinity Cache they are streamed past the caches (non-temporal)
+// so the gathered x_j lines of neighbouring rows stay in L2; smaller states
+// stay cached from one step to the next.
+constexpr size_t kStreamNTBytes = size_t(256) << 20;
 // bSB with M % 4 == 0: four consecutive agents per lane (16-byte gathers).
 constexpr bool kStreamVec4 = true;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <class T>
+template <bool NT, class T>
 __device__ __forceinline__ T ld_stream(const T *p) {
-    if constexpr (kStreamNT)
+    if constexpr (NT)
         return __builtin_nontemporal_load(p);
     else
         return *p;
 }
 
-template <class T>
+template <bool NT, class T>
 __device__ __forceinline__ void st_stream(T v, T *p) {
-    if constexpr (kStreamNT)
+    if constexpr (NT)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(256) void quantize_fp8_rows(int n, const int *__res
     }
 }
 
-template <int MODE, int JP, int APL>
+template <int MODE, int JP, int APL, bool NT>
 __global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const float *xin, float *xout,
                                                  const uint64_t *__restrict__ Sin,
                                                  uint64_t *__restrict__ Sout) {
@@ -236,12 +238,12 @@ __global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const floa
     const size_t o = static_cast<size_t>(i) * M;
 #pragma unroll
     for (int a = 0; a < APL; ++a) {
-        float x = live[a] ? ld_stream(xin + o + mcol[a]) : 0.0f;
-        float y = live[a] ? ld_stream(A.y + o + mcol[a]) : 0.0f;
+        float x = live[a] ? ld_stream<NT>(xin + o + mcol[a]) : 0.0f;
+        float y = live[a] ? ld_stream<NT>(A.y + o + mcol[a]) : 0.0f;
         sb_update(x, y, acc[a], c0, g, A.dt, A.dta0);
         if (live[a]) {
-            st_stream(x, xout + o + mcol[a]);
-            st_stream(y, A.y + o + mcol[a]);
+            st_stream<NT>(x, xout + o + mcol[a]);
+            st_stream<NT>(y, A.y + o + mcol[a]);
         }
         if constexpr (MODE == kDSB) {
             const uint64_t bal = __ballot(live[a] && x >= 0.0f);
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const floa
 
 // bSB with four consecutive agents per lane (M a multiple of 4): one
 // 16-byte gather per coupling and lane, 256 agents per wave.
-template <int JP>
+template <int JP, bool NT>
 __global__ __launch_bounds__(256) void sb_stream_v4(StreamArgs A, int k, const float *xin,
                                                     float *xout) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -291,14 +293,14 @@ __global__ __launch_bounds__(256) void sb_stream_v4(StreamArgs A, int k, const f
     }
     if (!live) return;
     const size_t o = static_cast<size_t>(i) * M + mcol;
-    const f32x4 xv = ld_stream(reinterpret_cast<const f32x4 *>(xin + o));
-    const f32x4 yv = ld_stream(reinterpret_cast<const f32x4 *>(A.y + o));
+    const f32x4 xv = ld_stream<NT>(reinterpret_cast<const f32x4 *>(xin + o));
+    const f32x4 yv = ld_stream<NT>(reinterpret_cast<const f32x4 *>(A.y + o));
     float x[4] = {xv.x, xv.y, xv.z, xv.w}, y[4] = {yv.x, yv.y, yv.z, yv.w};
     const float f[4] = {acc.x, acc.y, acc.z, acc.w};
 #pragma unroll
     for (int a = 0; a < 4; ++a) sb_update(x[a], y[a], f[a], c0, g, A.dt, A.dta0);
-    st_stream(f32x4{x[0], x[1], x[2], x[3]}, reinterpret_cast<f32x4 *>(xout + o));
-    st_stream(f32x4{y[0], y[1], y[2], y[3]}, reinterpret_cast<f32x4 *>(A.y + o));
+    st_stream<NT>(f32x4{x[0], x[1], x[2], x[3]}, reinterpret_cast<f32x4 *>(xout + o));
+    st_stream<NT>(f32x4{y[0], y[1], y[2], y[3]}, reinterpret_cast<f32x4 *>(A.y + o));
 }
 
 hipError_t launch_sign_planes(int n, int M, const float *x, uint64_t *S, hipStream_t st) {
@@ -323,7 +325,7 @@ hipError_t launch_quantize_fp8(int n, const int *row_ptr, const float *J, uint8_
 
 namespace {
 
-template <int MODE, int JP>
+template <int MODE, int JP, bool NT>
 hipError_t launch_stream_apl(const StreamArgs &A, int k, const float *xin, float *xout,
                              const uint64_t *Sin, uint64_t *Sout, hipStream_t st) {
     const int apl = stream_apl(A.M, MODE);
@@ -331,33 +333,43 @@ hipError_t launch_stream_apl(const StreamArgs &A, int k, const float *xin, float
     const int total = nrb * ((A.M + 64 * apl - 1) / (64 * apl));
     const int grid = (total + 7) / 8 * 8;
     switch (apl) {
-        case 8: sb_stream<MODE, JP, 8><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
-        case 4: sb_stream<MODE, JP, 4><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
-        case 2: sb_stream<MODE, JP, 2><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
-        default: sb_stream<MODE, JP, 1><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
+        case 8: sb_stream<MODE, JP, 8, NT><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
+        case 4: sb_stream<MODE, JP, 4, NT><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
+        case 2: sb_stream<MODE, JP, 2, NT><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
+        default: sb_stream<MODE, JP, 1, NT><<<grid, 256, 0, st>>>(A, k, xin, xout, Sin, Sout); break;
     }
     return hipGetLastError();
+}
+
+template <bool NT>
+hipError_t launch_stream_nt(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
+                            float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st) {
+    if (mode == kDSB)
+        return jprec == kJFp8
+                   ? launch_stream_apl<kDSB, kJFp8, NT>(A, k, xin, xout, Sin, Sout, st)
+                   : launch_stream_apl<kDSB, kJFp32, NT>(A, k, xin, xout, Sin, Sout, st);
+    if (kStreamVec4 && A.M % 4 == 0 && A.M > 64) {
+        const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
+        const int total = nrb * ((A.M + 255) / 256);
+        const int grid = (total + 7) / 8 * 8;
+        if (jprec == kJFp8)
+            sb_stream_v4<kJFp8, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
+        else
+            sb_stream_v4<kJFp32, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
+        return hipGetLastError();
+    }
+    return jprec == kJFp8 ? launch_stream_apl<kBSB, kJFp8, NT>(A, k, xin, xout, Sin, Sout, st)
+                          : launch_stream_apl<kBSB, kJFp32, NT>(A, k, xin, xout, Sin, Sout, st);
 }
 
 }  // namespace
 
 hipError_t launch_stream2(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
                           float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st) {
-    if (mode == kDSB)
-        return jprec == kJFp8 ? launch_stream_apl<kDSB, kJFp8>(A, k, xin, xout, Sin, Sout, st)
-                              : launch_stream_apl<kDSB, kJFp32>(A, k, xin, xout, Sin, Sout, st);
-    if (kStreamVec4 && A.M % 4 == 0 && A.M > 64) {
-        const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
-        const int total = nrb * ((A.M + 255) / 256);
-        const int grid = (total + 7) / 8 * 8;
-        if (jprec == kJFp8)
-            sb_stream_v4<kJFp8><<<grid, 256, 0, st>>>(A, k, xin, xout);
-        else
-            sb_stream_v4<kJFp32><<<grid, 256, 0, st>>>(A, k, xin, xout);
-        return hipGetLastError();
-    }
-    return jprec == kJFp8 ? launch_stream_apl<kBSB, kJFp8>(A, k, xin, xout, Sin, Sout, st)
-                          : launch_stream_apl<kBSB, kJFp32>(A, k, xin, xout, Sin, Sout, st);
+    // x (once or twice) and y, FP32
+    const size_t state = static_cast<size_t>(A.n) * A.M * sizeof(float) * (mode == kDSB ? 2 : 3);
+    return state > kStreamNTBytes ? launch_stream_nt<true>(mode, jprec, A, k, xin, xout, Sin, Sout, st)
+                                  : launch_stream_nt<false>(mode, jprec, A, k, xin, xout, Sin, Sout, st);
 }
 
 }  // namespace sbt
