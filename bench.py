@@ -265,6 +265,12 @@ def stress_form(sbt, tg, torch, np, K=10000):
     q0 = sbt.build_qubo(hits, bp)
     t_build = time.perf_counter() - t0
     t0 = time.perf_counter()
+    qg, t_gpu_dev = sbt.build_qubo_gpu(hits, bp)
+    t_gpu = time.perf_counter() - t0
+    same = bool(qg.n == q0.n and np.array_equal(qg.col, q0.col) and
+                np.array_equal(qg.row_ptr, q0.row_ptr))
+    del qg
+    t0 = time.perf_counter()
     q = sbt.permute_qubo(q0, sbt.phi_order(q0, hits))
     t_order = time.perf_counter() - t0
     del q0
@@ -272,7 +278,9 @@ def stress_form(sbt, tg, torch, np, K=10000):
     out = {"workload": "stress: 10-layer barrel, 5000 particles + 20% noise, |eta| < 2, event "
                        f"seed 300, doublet |z0| <= 300 mm; bSB, 512 agents x {K} steps, "
                        "spins in azimuth order",
-           "n": q.n, "nnz": q.nnz, "host_build_s": t_build, "host_order_s": t_order}
+           "n": q.n, "nnz": q.nnz, "host_build_s": t_build, "host_order_s": t_order,
+           "gpu_build_s": t_gpu, "gpu_build_device_s": t_gpu_dev,
+           "gpu_build_same_structure": same}
     for prec in ("fp8", "fp32"):
         s = sbt.DeviceSolver(q, "bsb", sbt.solve_params(agents=M, steps=K, seed=0,
                                                          kernel="stream", precision=prec))

@@ -104,6 +104,19 @@ int sbt_build_qubo(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *
                    sbt_qubo **out);
 void sbt_qubo_free(sbt_qubo *q);
 
+/* The same construction as sbt_build_qubo computed on the GPU (host hits
+ * in, library-owned host QUBO out).  The host sorts the hits and lists each
+ * layer by azimuth; doublets, triplets, quadruplets, the five-hit rule,
+ * biases, conflicts and the CSR assembly run on the device with the host
+ * builder's fixed-order FP64 expressions, so n, row_ptr, col and trip_hits
+ * equal sbt_build_qubo's; a and b can differ in the last place where exp
+ * (Eq. 15) or atan2 (Eq. 14) enter.
+ *   elapsed_s  out or NULL: device time of the construction (HIP events)
+ * Errors: as sbt_build_qubo, plus SBT_EDEVICE for HIP failures and
+ * SBT_EUNSUPPORTED beyond 32-bit counts. */
+int sbt_build_qubo_gpu(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *p,
+                       sbt_qubo **out, double *elapsed_s);
+
 /* Spin order for the solver's caches (a relabelling only; the section
  * "QUBO formulation" fixes the problem, not its index order): triplets
  * sorted by the azimuth of their middle hit, then its z, then index.  The

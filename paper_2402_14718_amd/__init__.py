@@ -84,6 +84,19 @@ def build_qubo(hits: np.ndarray, params: Optional[_lib.SbtBuildParams] = None) -
     return _take_qubo(out)
 
 
+def build_qubo_gpu(hits: np.ndarray, params: Optional[_lib.SbtBuildParams] = None):
+    """sbt_build_qubo_gpu: the same QUBO built on the GPU.  Returns
+    (Qubo, device seconds of the construction)."""
+    lib = load()
+    hits = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    out = C.POINTER(_lib.SbtQubo)()
+    t = C.c_double()
+    check(lib.sbt_build_qubo_gpu(hits.ctypes.data_as(C.POINTER(_lib.SbtHit)), hits.shape[0],
+                                 C.byref(params) if params is not None else None, C.byref(out),
+                                 C.byref(t)))
+    return _take_qubo(out), float(t.value)
+
+
 def _take_qubo(out) -> Qubo:
     """Copy a library-owned sbt_qubo into a Qubo and free it."""
     lib = load()
@@ -391,7 +404,7 @@ class DeviceBatchSolver:
 
 
 __all__ = ["Qubo", "DeviceSolver", "DeviceBatchSolver", "build_qubo", "energy", "solve",
-           "phi_order", "permute_qubo",
+           "phi_order", "permute_qubo", "build_qubo_gpu",
            "solve_batch", "solve_params", "workspace_bytes", "select_kernel",
            "build_params_default", "version", "load", "SbtError", "HIT_DTYPE", "MODES",
            "KERNELS", "PRECISIONS"]

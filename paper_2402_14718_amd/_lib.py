@@ -104,6 +104,8 @@ EXPORTS = [
                                  C.POINTER(C.POINTER(SbtQubo))]),
     ("sbt_qubo_free", None, [C.POINTER(SbtQubo)]),
     ("sbt_energy", C.c_int, [C.POINTER(SbtQubo), C.POINTER(C.c_int8), C.POINTER(C.c_double)]),
+    ("sbt_build_qubo_gpu", C.c_int, [C.POINTER(SbtHit), C.c_int64, C.POINTER(SbtBuildParams),
+                                     C.POINTER(C.POINTER(SbtQubo)), C.POINTER(C.c_double)]),
     ("sbt_phi_order", C.c_int, [C.POINTER(SbtQubo), C.POINTER(SbtHit), C.c_int64,
                                 C.POINTER(C.c_int32)]),
     ("sbt_qubo_permute", C.c_int, [C.POINTER(SbtQubo), C.POINTER(C.c_int32),

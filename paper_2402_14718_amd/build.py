@@ -25,7 +25,11 @@ ARCH = "gfx950"
 
 HOST_SOURCES = ["status.cpp", "build_qubo.cpp", "order.cpp"]
 RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
-HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_batch.hip", "sb_stream.hip"]
+HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_batch.hip", "sb_stream.hip",
+               "build_qubo_gpu.hip"]
+# the GPU QUBO builder evaluates the host builder's cut expressions: no
+# floating-point contraction, like the host file
+HIP_EXTRA_FLAGS = {"build_qubo_gpu.hip": ["-ffp-contract=off"]}
 
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
               "-Wall", "-Wextra", "-Wno-unused-parameter", f"-I{INCLUDE}", f"-I{CSRC}"]
@@ -57,7 +61,8 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        _run([hipcc, *HIP_FLAGS, *HIP_EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o",
+              obj], verbose)
         objs.append(obj)
     tmp = LIB_PATH + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,

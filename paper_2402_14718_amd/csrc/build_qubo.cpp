@@ -380,32 +380,40 @@ extern "C" void sbt_build_params_default(sbt_build_params *p) {
     p->lambda_ = 0.5;
 }
 
-extern "C" int sbt_build_qubo(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *pp,
-                              sbt_qubo **out) {
-    sbt::clear_error();
-    if (!out) return sbt::fail(SBT_EINVAL, "sbt_build_qubo: out is NULL");
+int sbt::check_build_inputs(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *pp,
+                            sbt_qubo **out, sbt_build_params *p, const char *who) {
+    if (!out) return sbt::fail(SBT_EINVAL, "%s: out is NULL", who);
     *out = nullptr;
     if (n_hits < 0 || n_hits > INT32_MAX / 2)
-        return sbt::fail(SBT_EINVAL, "sbt_build_qubo: n_hits %lld out of range",
+        return sbt::fail(SBT_EINVAL, "%s: n_hits %lld out of range", who,
                          static_cast<long long>(n_hits));
-    if (n_hits > 0 && !hits) return sbt::fail(SBT_EINVAL, "sbt_build_qubo: hits is NULL");
-    sbt_build_params p;
+    if (n_hits > 0 && !hits) return sbt::fail(SBT_EINVAL, "%s: hits is NULL", who);
     if (pp)
-        p = *pp;
+        *p = *pp;
     else
-        sbt_build_params_default(&p);
-    if (!(p.dphi_tan > 0.0) || !(p.dtheta_tan > 0.0) || !(p.gamma_ > 0.0) || !(p.lambda_ > 0.0) ||
-        !std::isfinite(p.curv_max) || !std::isfinite(p.dcurv_max) || !std::isfinite(p.s_min))
-        return sbt::fail(SBT_EINVAL, "sbt_build_qubo: invalid parameters");
+        sbt_build_params_default(p);
+    if (!(p->dphi_tan > 0.0) || !(p->dtheta_tan > 0.0) || !(p->gamma_ > 0.0) ||
+        !(p->lambda_ > 0.0) || !std::isfinite(p->curv_max) || !std::isfinite(p->dcurv_max) ||
+        !std::isfinite(p->s_min))
+        return sbt::fail(SBT_EINVAL, "%s: invalid parameters", who);
     for (int64_t k = 0; k < n_hits; ++k) {
         const sbt_hit &h = hits[k];
         if (!std::isfinite(h.x) || !std::isfinite(h.y) || !std::isfinite(h.z))
-            return sbt::fail(SBT_EINVAL, "sbt_build_qubo: hit %lld has a non-finite coordinate",
+            return sbt::fail(SBT_EINVAL, "%s: hit %lld has a non-finite coordinate", who,
                              static_cast<long long>(k));
         if (h.layer < 0 || h.layer > 4096)
-            return sbt::fail(SBT_EINVAL, "sbt_build_qubo: hit %lld has layer %d",
+            return sbt::fail(SBT_EINVAL, "%s: hit %lld has layer %d", who,
                              static_cast<long long>(k), h.layer);
     }
+    return SBT_OK;
+}
+
+extern "C" int sbt_build_qubo(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *pp,
+                              sbt_qubo **out) {
+    sbt::clear_error();
+    sbt_build_params p;
+    const int rc = sbt::check_build_inputs(hits, n_hits, pp, out, &p, "sbt_build_qubo");
+    if (rc) return rc;
     try {
         return build_impl(hits, n_hits, p, out);
     } catch (const std::bad_alloc &) {

@@ -2,8 +2,11 @@
 #pragma once
 
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <string>
+
+#include "sbtrack.h"
 
 namespace sbt {
 
@@ -12,5 +15,11 @@ int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
 // Clears the thread-local message.
 void clear_error();
+
+
+// Argument checks shared by the host and GPU QUBO builders: fills *p (the
+// defaults when pp is NULL), clears *out; SBT_OK or an error status.
+int check_build_inputs(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *pp,
+                       sbt_qubo **out, sbt_build_params *p, const char *who);
 
 }  // namespace sbt
