@@ -312,6 +312,22 @@ def stress_form(sbt, tg, torch, np, K=10000):
     return out
 
 
+def c0_scan_form(sbt, q, torch):
+    """Automatic c0 scan on the plain event (Results: fixed c0 or a scan):
+    c0 * 2^k for k = -3..3, dSB and bSB, FP16 batch, 256 agents x 5000
+    steps, every copy from the same start."""
+    ref = load_golden("oracle_best_plain.json")
+    factors = [2.0 ** k for k in range(-3, 4)]
+    out = {"factors": factors}
+    for mode in ("dsb", "bsb"):
+        t0 = time.perf_counter()
+        s = sbt.c0_scan(q, mode, factors, "fp16", agents=AGENTS, steps=SB_STEPS, seed=SOLVER_SEED)
+        out[mode] = {"energy": s["energy"].tolist(), "best_factor": s["factor"],
+                     "seconds": time.perf_counter() - t0,
+                     "oracle_best_fixed_c0": ref["modes"][mode]["best"]}
+    return out
+
+
 def measured_traffic(profile_name):
     """HBM bytes per launch from the committed rocprofv3 counter record, or
     None when the kernel's sources changed after the counters were taken."""
@@ -502,6 +518,8 @@ def main():
         log("batched form done")
         result["stress_form"] = stress_form(sbt, tg, torch, np, args.stress_steps)
         log("stress form done")
+        result["c0_scan"] = c0_scan_form(sbt, q, torch)
+        log("c0 scan done")
 
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")

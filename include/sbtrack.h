@@ -318,11 +318,16 @@ size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz, int32_t n
 /* Upload the batch's schedule (event descriptors and the ordered work
  * items) into `workspace` on `stream`.  Call once per (batch shape,
  * parameters); sbt_batch_run then only launches kernels and may be captured
- * in a HIP graph.  Returns the number of work items, or a negative status;
- * SBT_EUNSUPPORTED for an event with more than 9216 variables. */
+ * in a HIP graph.
+ *   c0_scale    host [E] or NULL: event e runs with c0 * c0_scale[e] (c0 the
+ *               fixed or automatic value of that event); each > 0
+ *   same_start  nonzero: every event draws its start with counter word
+ *               p->event (a scan of one QUBO); zero: event e uses p->event + e
+ * Returns the number of work items, or a negative status; SBT_EUNSUPPORTED
+ * for an event with more than 9216 variables. */
 int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
-                   const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
-                   void *stream);
+                   const double *c0_scale, int32_t same_start, const sbt_solve_params *p,
+                   void *workspace, size_t workspace_bytes, void *stream);
 
 /* Solve every event of a planned batch: per-event Ising preparation and
  * spin ordering, all steps of all agents of all events in one persistent
@@ -345,6 +350,19 @@ typedef struct {
 /* Host convenience: validate and upload the QUBOs, plan, run, download. */
 int sbt_solve_batch(const sbt_qubo *const *qs, int32_t n_events, sbt_mode mode,
                     sbt_precision prec, const sbt_solve_params *p, sbt_batch_result *out);
+
+/* Automatic c0 scan (Results: c0 fixed or found by a scan).  Solves the one
+ * QUBO q once per factor in a single batch, copy k with c0 * factors[k]
+ * (c0 = p->c0 if > 0, else the automatic value), every copy from the same
+ * Philox start (counter word p->event).
+ *   energy       caller [n_factors]: best FP64 O(T) per factor
+ *   best_agent   caller [n_factors]
+ *   best_factor  out: index of the lowest energy (lowest index on ties)
+ * Errors: as sbt_solve_batch; SBT_EINVAL for a factor that is not finite
+ * and > 0. */
+int sbt_c0_scan(const sbt_qubo *q, sbt_mode mode, sbt_precision prec, const sbt_solve_params *p,
+                const double *factors, int32_t n_factors, double *energy, int32_t *best_agent,
+                int32_t *best_factor);
 
 #ifdef __cplusplus
 }

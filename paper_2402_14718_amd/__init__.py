@@ -323,13 +323,31 @@ def solve_batch(qubos, mode: str, precision: str = "fp16", agents: int = 128,
             "trace": None if tr is None else tr.reshape(E, n_ck), "elapsed_s": r.elapsed_s}
 
 
+def c0_scan(q: Qubo, mode: str, factors, precision: str = "fp16", agents: int = 128,
+            steps: int = 3000, dt: float = 1.0, a0: float = 1.0, c0: float = 0.0,
+            seed: int = 0, event: int = 0) -> dict:
+    """sbt_c0_scan: one batch solving q once per c0 factor from one start."""
+    p = solve_params(agents, steps, dt, a0, c0, seed, event)
+    f = np.ascontiguousarray(factors, dtype=np.float64)
+    e = np.zeros(f.shape[0])
+    ba = np.zeros(f.shape[0], dtype=np.int32)
+    best = C.c_int32()
+    s = q.as_struct()
+    check(load().sbt_c0_scan(C.byref(s), MODES[mode], PRECISIONS[precision], C.byref(p),
+                             f.ctypes.data_as(C.POINTER(C.c_double)), f.shape[0],
+                             e.ctypes.data_as(C.POINTER(C.c_double)),
+                             ba.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(best)))
+    return {"energy": e, "best_agent": ba, "best_factor": int(best.value),
+            "factor": float(f[best.value])}
+
+
 class DeviceBatchSolver:
     """sbt_batch_plan once, then sbt_batch_run per call, every buffer held by
     torch on a HIP device (events concatenated)."""
 
     def __init__(self, qubos, mode: str, precision: str, params: _lib.SbtSolveParams,
                  device="cuda", want_agent_energy: bool = False, want_trace: bool = False,
-                 want_agent_state: bool = False):
+                 want_agent_state: bool = False, c0_scale=None, same_start: bool = False):
         import torch
         self.torch = torch
         self.mode, self.precision, self.params = mode, precision, params
@@ -360,7 +378,13 @@ class DeviceBatchSolver:
         self.trace = (torch.empty(E * n_ck, dtype=torch.float64, device=dev)
                       if want_trace and n_ck > 0 else None)
         st = torch.cuda.current_stream()
-        rc = lib.sbt_batch_plan(np_, nz_, E, C.byref(params),
+        self._c0_scale = (None if c0_scale is None
+                          else np.ascontiguousarray(c0_scale, dtype=np.float64))
+        if self._c0_scale is not None and self._c0_scale.shape != (E,):
+            raise ValueError("c0_scale must have one entry per event")
+        cs = (None if self._c0_scale is None
+              else self._c0_scale.ctypes.data_as(C.POINTER(C.c_double)))
+        rc = lib.sbt_batch_plan(np_, nz_, E, cs, 1 if same_start else 0, C.byref(params),
                                 C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
                                 C.c_void_p(st.cuda_stream))
         if rc < 0:
@@ -404,7 +428,7 @@ class DeviceBatchSolver:
 
 
 __all__ = ["Qubo", "DeviceSolver", "DeviceBatchSolver", "build_qubo", "energy", "solve",
-           "phi_order", "permute_qubo", "build_qubo_gpu",
+           "phi_order", "permute_qubo", "build_qubo_gpu", "c0_scan",
            "solve_batch", "solve_params", "workspace_bytes", "select_kernel",
            "build_params_default", "version", "load", "SbtError", "HIT_DTYPE", "MODES",
            "KERNELS", "PRECISIONS"]

@@ -123,12 +123,16 @@ EXPORTS = [
     ("sbt_batch_workspace_bytes", C.c_size_t, [C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                                C.c_int32, C.POINTER(SbtSolveParams)]),
     ("sbt_batch_plan", C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int32,
-                                 C.POINTER(SbtSolveParams), C.c_void_p, C.c_size_t, C.c_void_p]),
+                                 C.POINTER(C.c_double), C.c_int32, C.POINTER(SbtSolveParams),
+                                 C.c_void_p, C.c_size_t, C.c_void_p]),
     ("sbt_batch_run", C.c_int, [C.POINTER(SbtDevBatch), C.c_int, C.c_int,
                                 C.POINTER(SbtSolveParams), C.c_void_p, C.c_size_t,
                                 C.POINTER(SbtDevBatchResult), C.c_void_p]),
     ("sbt_solve_batch", C.c_int, [C.POINTER(C.POINTER(SbtQubo)), C.c_int32, C.c_int, C.c_int,
                                   C.POINTER(SbtSolveParams), C.POINTER(SbtBatchResult)]),
+    ("sbt_c0_scan", C.c_int, [C.POINTER(SbtQubo), C.c_int, C.c_int, C.POINTER(SbtSolveParams),
+                              C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_double),
+                              C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
 ]
 
 _LIB = None

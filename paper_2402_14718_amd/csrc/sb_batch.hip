@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void batch_prep(BatchArgs B, int jprec) {
         double c0 = B.c0_fixed > 0.0 ? B.c0_fixed
                                      : (sd == 0.0 ? 0.5 / sqrt(static_cast<double>(E.n))
                                                   : 0.5 / (sqrt(static_cast<double>(E.n)) * sd));
-        B.c0[e] = static_cast<float>(c0);
+        B.c0[e] = static_cast<float>(c0 * static_cast<double>(E.c0_scale));
         B.offset[e] = 0.5 * t3 + 0.25 * t2;
     }
     // spin order: decreasing min(row length, 63), ascending id within a length

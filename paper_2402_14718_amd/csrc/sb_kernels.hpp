@@ -92,7 +92,7 @@ struct BatchEvent {
     int nz_off;                  // offset into col, b, J16
     int lg_agents;               // log2 of the agents one work item holds
     int event_id;                // Philox counter word 2
-    int pad;
+    float c0_scale;              // c0 of the event = (fixed or auto c0) * c0_scale
 };
 
 struct BatchArgs {

@@ -36,10 +36,14 @@ int lg_agents_for(int32_t n, int32_t M) {
     return lg;
 }
 
-int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const sbt_solve_params &p,
-                  Schedule &S, const char *who) {
+int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const double *c0_scale,
+                  int32_t same_start, const sbt_solve_params &p, Schedule &S, const char *who) {
     if (E < 1) return fail(SBT_EINVAL, "%s: n_events must be >= 1", who);
     if (!n || !nnz) return fail(SBT_EINVAL, "%s: n or nnz is NULL", who);
+    if (c0_scale)
+        for (int32_t e = 0; e < E; ++e)
+            if (!(c0_scale[e] > 0.0) || !std::isfinite(c0_scale[e]))
+                return fail(SBT_EINVAL, "%s: c0_scale[%d] must be finite and > 0", who, e);
     S.ev.resize(E);
     struct Item {
         int64_t cost;
@@ -60,8 +64,8 @@ int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const sbt_sol
         d.rp_off = static_cast<int>(row_off + e);
         d.nz_off = static_cast<int>(nz_off);
         d.lg_agents = lg_agents_for(n[e], p.agents);
-        d.event_id = p.event + e;
-        d.pad = 0;
+        d.event_id = same_start ? p.event : p.event + e;
+        d.c0_scale = c0_scale ? static_cast<float>(c0_scale[e]) : 1.0f;
         const int A = 1 << d.lg_agents;
         for (int a0 = 0; a0 < p.agents; a0 += A) {
             const int used = std::min(A, p.agents - a0);
@@ -154,11 +158,12 @@ extern "C" size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz
     }
     if (check_batch_params(*p, who)) return 0;
     Schedule S;
-    if (make_schedule(n, nnz, n_events, *p, S, who)) return 0;
+    if (make_schedule(n, nnz, n_events, nullptr, 0, *p, S, who)) return 0;
     return make_layout(S, *p).total;
 }
 
 extern "C" int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                              const double *c0_scale, int32_t same_start,
                               const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
                               void *stream) {
     const char *who = "sbt_batch_plan";
@@ -167,7 +172,7 @@ extern "C" int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_ev
     int rc = check_batch_params(*p, who);
     if (rc) return rc;
     Schedule S;
-    rc = make_schedule(n, nnz, n_events, *p, S, who);
+    rc = make_schedule(n, nnz, n_events, c0_scale, same_start, *p, S, who);
     if (rc) return rc;
     const BatchLayout L = make_layout(S, *p);
     if (!workspace || workspace_bytes < L.total)
@@ -197,7 +202,7 @@ extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_prec
     int rc = check_batch_params(*p, who);
     if (rc) return rc;
     Schedule S;
-    rc = make_schedule(batch->n, batch->nnz, batch->n_events, *p, S, who);
+    rc = make_schedule(batch->n, batch->nnz, batch->n_events, nullptr, 0, *p, S, who);
     if (rc) return rc;
     const BatchLayout L = make_layout(S, *p);
     if (!workspace || workspace_bytes < L.total)
@@ -277,11 +282,9 @@ struct DevBuf {
 
 }  // namespace
 
-extern "C" int sbt_solve_batch(const sbt_qubo *const *qs, int32_t E, sbt_mode mode,
-                               sbt_precision prec, const sbt_solve_params *pp,
-                               sbt_batch_result *out) {
-    const char *who = "sbt_solve_batch";
-    sbt::clear_error();
+static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *c0_scale,
+                     int32_t same_start, sbt_mode mode, sbt_precision prec,
+                     const sbt_solve_params *pp, sbt_batch_result *out, const char *who) {
     if (!qs || !out || !out->energy || !out->best_agent)
         return fail(SBT_EINVAL, "%s: NULL argument", who);
     if (E < 1) return fail(SBT_EINVAL, "%s: n_events must be >= 1", who);
@@ -338,7 +341,7 @@ extern "C" int sbt_solve_batch(const sbt_qubo *const *qs, int32_t E, sbt_mode mo
     if (rc0) return rc0;
     {
         Schedule S;
-        rc0 = make_schedule(n.data(), nnz.data(), E, p, S, who);
+        rc0 = make_schedule(n.data(), nnz.data(), E, c0_scale, same_start, p, S, who);
         if (rc0) return rc0;
     }
     const size_t ws_bytes = sbt_batch_workspace_bytes(n.data(), nnz.data(), E, &p);
@@ -376,7 +379,7 @@ extern "C" int sbt_solve_batch(const sbt_qubo *const *qs, int32_t E, sbt_mode mo
         }
     } eg{e0, e1};
     SBT_HIP(hipEventRecord(e0, st));
-    int rc = sbt_batch_plan(n.data(), nnz.data(), E, &p, dws.p, ws_bytes, st);
+    int rc = sbt_batch_plan(n.data(), nnz.data(), E, c0_scale, same_start, &p, dws.p, ws_bytes, st);
     if (rc < 0) return rc;
     sbt_dev_batch dbch{E, n.data(), nnz.data(), static_cast<const double *>(da.p),
                        static_cast<const int32_t *>(drp.p), static_cast<const int32_t *>(dcol.p),
@@ -401,5 +404,33 @@ extern "C" int sbt_solve_batch(const sbt_qubo *const *qs, int32_t E, sbt_mode mo
     float ms = 0.0f;
     SBT_HIP(hipEventElapsedTime(&ms, e0, e1));
     out->elapsed_s = 1e-3 * ms;
+    return SBT_OK;
+}
+
+extern "C" int sbt_solve_batch(const sbt_qubo *const *qs, int32_t E, sbt_mode mode,
+                               sbt_precision prec, const sbt_solve_params *p,
+                               sbt_batch_result *out) {
+    sbt::clear_error();
+    return solve_batch_impl(qs, E, nullptr, 0, mode, prec, p, out, "sbt_solve_batch");
+}
+
+extern "C" int sbt_c0_scan(const sbt_qubo *q, sbt_mode mode, sbt_precision prec,
+                           const sbt_solve_params *p, const double *factors, int32_t n_factors,
+                           double *energy, int32_t *best_agent, int32_t *best_factor) {
+    const char *who = "sbt_c0_scan";
+    sbt::clear_error();
+    if (!q || !factors || !energy || !best_agent || !best_factor)
+        return fail(SBT_EINVAL, "%s: NULL argument", who);
+    if (n_factors < 1) return fail(SBT_EINVAL, "%s: n_factors must be >= 1", who);
+    std::vector<const sbt_qubo *> qs(static_cast<size_t>(n_factors), q);
+    sbt_batch_result r{};
+    r.energy = energy;
+    r.best_agent = best_agent;
+    const int rc = solve_batch_impl(qs.data(), n_factors, factors, 1, mode, prec, p, &r, who);
+    if (rc) return rc;
+    int32_t best = 0;
+    for (int32_t k = 1; k < n_factors; ++k)
+        if (energy[k] < energy[best]) best = k;
+    *best_factor = best;
     return SBT_OK;
 }

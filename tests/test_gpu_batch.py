@@ -170,3 +170,52 @@ def test_batch_quality_equals_plain_fp32(prec):
         eff_b, pur_b, *_ = otracks.evaluate(ev, q.trip_hits, r["T"][e])
         eff_s, pur_s, *_ = otracks.evaluate(ev, q.trip_hits, s["T"])
         assert abs(eff_b - eff_s) <= 0.01 and abs(pur_b - pur_s) <= 0.01
+
+
+@pytest.mark.parametrize("dt,K", [(1.0, 50), (0.1, 10)])
+def test_c0_scan_copies_match_oracle_with_scaled_c0(dt, K):
+    """A c0 scan (one QUBO, c0 * f per copy, one start) against the oracle
+    run with the same rounded couplings and c0 * f."""
+    evs, qs = _events([(tg.plain_spec(150), 3)])
+    q = qs[0]
+    factors = [0.5, 1.0, 2.0]
+    M, seed = 64, 21
+    ds = sbt.DeviceBatchSolver([q] * 3, "dsb", "fp16",
+                               sbt.solve_params(agents=M, steps=K, dt=dt, seed=seed),
+                               want_agent_state=True, c0_scale=factors, same_start=True)
+    ds.run()
+    r = ds.result()
+    b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
+    isg = oising.from_qubo(q.a, b)
+    Jq = isg.J.copy()
+    Jq.data = q_fp16(Jq.data)
+    for k, f in enumerate(factors):
+        ref = osb.run(Jq, isg.h, isg.c0 * f, "dsb", M, K, dt=dt, seed=seed, event=0,
+                      margin_steps=K)
+        x = r["agent_x"][k]
+        err = np.linalg.norm(x - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
+        close = (ref.wall_margin < 1e-6) | (ref.sign_margin < 1e-6)
+        assert np.all((err <= 1e-5) | close), (k, err.max())
+        assert np.mean(err <= 1e-5) >= 0.9
+    if dt < 1.0:
+        # the copies really differ
+        assert not np.array_equal(r["agent_x"][0], r["agent_x"][2])
+
+
+def test_c0_scan_host_entry_point():
+    evs, qs = _events([(tg.plain_spec(120), 5)])
+    q = qs[0]
+    factors = np.array([0.25, 0.5, 1.0, 2.0, 4.0])
+    s = sbt.c0_scan(q, "dsb", factors, "fp16", agents=64, steps=400, seed=2)
+    ds = sbt.DeviceBatchSolver([q] * 5, "dsb", "fp16", sbt.solve_params(agents=64, steps=400,
+                                                                         seed=2),
+                               c0_scale=factors, same_start=True)
+    ds.run()
+    e = ds.result()["energy"]
+    assert np.array_equal(s["energy"], e)
+    assert s["best_factor"] == int(np.argmin(e)) and s["factor"] == factors[s["best_factor"]]
+    # factor 1 is the plain single-event batch solve
+    one = sbt.solve_batch([q], "dsb", "fp16", agents=64, steps=400, seed=2)
+    assert s["energy"][2] == one["energy"][0]
+    with pytest.raises(sbt.SbtError):
+        sbt.c0_scan(q, "dsb", [1.0, 0.0], "fp16", agents=8, steps=10)
