@@ -6,6 +6,8 @@ Section "Simulated Bifurcation" of the paper:
                  dy_i/dt = -(a0 - a(t)) x_i + c0 sum_j J_ij x_j,
   with perfectly inelastic walls at |x_i| > 1: x_i <- sgn(x_i), y_i <- 0.
 * dSB, Eq. 9-12: the same, with x_j replaced by sgn(x_j) in the coupling.
+* aSB, Eq. 1-4: dy_i/dt = -(x_i^2 + a0 - a(t)) x_i + c0 sum_j J_ij x_j, no
+  walls (the quartic term of V_aSB bounds the motion).
 * a(t) rises monotonically from zero; a0, dt = 1 and c0 fixed (Results).
 * integration by the symplectic Euler method; all spins update at once.
 
@@ -31,6 +33,7 @@ from .philox import initial_state
 
 BSB = "bsb"
 DSB = "dsb"
+ASB = "asb"
 
 
 def sgn(x: np.ndarray) -> np.ndarray:
@@ -54,7 +57,7 @@ def run(J: sp.csr_matrix, h: np.ndarray, c0: float, mode: str, agents: int,
 
     `margin_steps` > 0 records decision margins over the first that many
     steps (used to tell a legitimate FP32 divergence from a wrong result)."""
-    if mode not in (BSB, DSB):
+    if mode not in (BSB, DSB, ASB):
         raise ValueError(mode)
     n = int(h.shape[0])
     J = sp.csr_matrix(J, dtype=np.float64)
@@ -69,12 +72,16 @@ def run(J: sp.csr_matrix, h: np.ndarray, c0: float, mode: str, agents: int,
     hcol = h[:, None]
     for k in range(steps):
         a_k = a0 * k / steps
-        if mode == BSB:
-            F = J @ x + hcol
-        else:
+        if mode == DSB:
             F = J @ sgn(x) + hcol
             if k < margin_steps:
                 sign_margin = np.minimum(sign_margin, np.abs(x).min(axis=0))
+        else:
+            F = J @ x + hcol
+        if mode == ASB:
+            y = y + dt * (c0 * F - (x * x + (a0 - a_k)) * x)
+            x = x + dt * a0 * y
+            continue
         y = y + dt * (c0 * F - (a0 - a_k) * x)
         x = x + dt * a0 * y
         if k < margin_steps:

@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import (SBT_BSB, SBT_DSB, SBT_KERNEL_AUTO, SBT_KERNEL_RESIDENT, SBT_KERNEL_STREAM,
                    SbtError, check, load)
 
-MODES = {"bsb": SBT_BSB, "dsb": SBT_DSB}
+MODES = {"bsb": SBT_BSB, "dsb": SBT_DSB, "asb": _lib.SBT_ASB}
 KERNELS = {"auto": SBT_KERNEL_AUTO, "resident": SBT_KERNEL_RESIDENT, "stream": SBT_KERNEL_STREAM}
 PRECISIONS = {"fp32": _lib.SBT_PREC_FP32, "fp16": _lib.SBT_PREC_FP16, "bf16": _lib.SBT_PREC_BF16,
               "fp8": _lib.SBT_PREC_FP8}

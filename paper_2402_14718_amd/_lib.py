@@ -19,6 +19,7 @@ SBT_EUNSUPPORTED = -4
 
 SBT_BSB = 0
 SBT_DSB = 1
+SBT_ASB = 2
 
 SBT_KERNEL_AUTO = 0
 SBT_KERNEL_RESIDENT = 1

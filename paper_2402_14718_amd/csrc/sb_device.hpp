@@ -10,7 +10,7 @@
 
 namespace sbt {
 
-enum : int { kBSB = 0, kDSB = 1 };
+enum : int { kBSB = 0, kDSB = 1, kASB = 2 };
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of
 // (hi0, lo0) = M0 c0, (hi1, lo1) = M1 c2, c = (hi1^c1^k0, lo1, hi0^c3^k1, lo0),
@@ -82,7 +82,17 @@ __device__ __forceinline__ void sb_update(float &x, float &y, float F, float c0,
     y = wall ? 0.0f : yn;
 }
 
-// What the coupling reads of a neighbour: its position (bSB) or sign (dSB).
+// One symplectic-Euler step of aSB (Eq. 1-2), no wall:
+//   y += dt (c0 F - (x^2 + g) x),  x += dt a0 y.
+__device__ __forceinline__ void sb_update_asb(float &x, float &y, float F, float c0, float g,
+                                              float dt, float dta0) {
+    const float q = __builtin_fmaf(x, x, g);
+    const float force = __builtin_fmaf(c0, F, -(q * x));
+    y = __builtin_fmaf(dt, force, y);
+    x = __builtin_fmaf(dta0, y, x);
+}
+
+// What the coupling reads of a neighbour: its position (bSB, aSB) or sign (dSB).
 template <int MODE>
 __device__ __forceinline__ float shared_value(float x) {
     if constexpr (MODE == kDSB)

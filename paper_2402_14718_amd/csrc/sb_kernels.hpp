@@ -53,7 +53,7 @@ constexpr int kStreamChunk = 8;
 constexpr int kStreamAplMaxBsb = 4;
 constexpr int kStreamAplMaxDsb = 8;
 __host__ __device__ constexpr int stream_apl(int M, int mode) {
-    const int cap = mode == 1 ? kStreamAplMaxDsb : kStreamAplMaxBsb;
+    const int cap = mode == 1 ? kStreamAplMaxDsb : kStreamAplMaxBsb;  // dSB : bSB, aSB
     const int apl = M > 256 ? 8 : (M > 128 ? 4 : (M > 64 ? 2 : 1));
     return apl < cap ? apl : cap;
 }

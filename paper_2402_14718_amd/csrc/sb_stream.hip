@@ -240,7 +240,10 @@ __global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const floa
     for (int a = 0; a < APL; ++a) {
         float x = live[a] ? ld_stream<NT>(xin + o + mcol[a]) : 0.0f;
         float y = live[a] ? ld_stream<NT>(A.y + o + mcol[a]) : 0.0f;
-        sb_update(x, y, acc[a], c0, g, A.dt, A.dta0);
+        if constexpr (MODE == kASB)
+            sb_update_asb(x, y, acc[a], c0, g, A.dt, A.dta0);
+        else
+            sb_update(x, y, acc[a], c0, g, A.dt, A.dta0);
         if (live[a]) {
             st_stream<NT>(x, xout + o + mcol[a]);
             st_stream<NT>(y, A.y + o + mcol[a]);
@@ -252,9 +255,9 @@ __global__ __launch_bounds__(256) void sb_stream(StreamArgs A, int k, const floa
     }
 }
 
-// bSB with four consecutive agents per lane (M a multiple of 4): one
+// bSB / aSB with four consecutive agents per lane (M a multiple of 4): one
 // 16-byte gather per coupling and lane, 256 agents per wave.
-template <int JP, bool NT>
+template <int MODE, int JP, bool NT>
 __global__ __launch_bounds__(256) void sb_stream_v4(StreamArgs A, int k, const float *xin,
                                                     float *xout) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -298,7 +301,12 @@ __global__ __launch_bounds__(256) void sb_stream_v4(StreamArgs A, int k, const f
     float x[4] = {xv.x, xv.y, xv.z, xv.w}, y[4] = {yv.x, yv.y, yv.z, yv.w};
     const float f[4] = {acc.x, acc.y, acc.z, acc.w};
 #pragma unroll
-    for (int a = 0; a < 4; ++a) sb_update(x[a], y[a], f[a], c0, g, A.dt, A.dta0);
+    for (int a = 0; a < 4; ++a) {
+        if constexpr (MODE == kASB)
+            sb_update_asb(x[a], y[a], f[a], c0, g, A.dt, A.dta0);
+        else
+            sb_update(x[a], y[a], f[a], c0, g, A.dt, A.dta0);
+    }
     st_stream<NT>(f32x4{x[0], x[1], x[2], x[3]}, reinterpret_cast<f32x4 *>(xout + o));
     st_stream<NT>(f32x4{y[0], y[1], y[2], y[3]}, reinterpret_cast<f32x4 *>(A.y + o));
 }
@@ -341,6 +349,24 @@ hipError_t launch_stream_apl(const StreamArgs &A, int k, const float *xin, float
     return hipGetLastError();
 }
 
+// bSB / aSB: neighbours' positions gathered
+template <int MODE, bool NT>
+hipError_t launch_stream_gather(int jprec, const StreamArgs &A, int k, const float *xin, float *xout,
+                                hipStream_t st) {
+    if (kStreamVec4 && A.M % 4 == 0 && A.M > 64) {
+        const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
+        const int total = nrb * ((A.M + 255) / 256);
+        const int grid = (total + 7) / 8 * 8;
+        if (jprec == kJFp8)
+            sb_stream_v4<MODE, kJFp8, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
+        else
+            sb_stream_v4<MODE, kJFp32, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
+        return hipGetLastError();
+    }
+    return jprec == kJFp8 ? launch_stream_apl<MODE, kJFp8, NT>(A, k, xin, xout, nullptr, nullptr, st)
+                          : launch_stream_apl<MODE, kJFp32, NT>(A, k, xin, xout, nullptr, nullptr, st);
+}
+
 template <bool NT>
 hipError_t launch_stream_nt(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
                             float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st) {
@@ -348,18 +374,8 @@ hipError_t launch_stream_nt(int mode, int jprec, const StreamArgs &A, int k, con
         return jprec == kJFp8
                    ? launch_stream_apl<kDSB, kJFp8, NT>(A, k, xin, xout, Sin, Sout, st)
                    : launch_stream_apl<kDSB, kJFp32, NT>(A, k, xin, xout, Sin, Sout, st);
-    if (kStreamVec4 && A.M % 4 == 0 && A.M > 64) {
-        const int nrb = (A.n + kRowsPerWG - 1) / kRowsPerWG;
-        const int total = nrb * ((A.M + 255) / 256);
-        const int grid = (total + 7) / 8 * 8;
-        if (jprec == kJFp8)
-            sb_stream_v4<kJFp8, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
-        else
-            sb_stream_v4<kJFp32, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
-        return hipGetLastError();
-    }
-    return jprec == kJFp8 ? launch_stream_apl<kBSB, kJFp8, NT>(A, k, xin, xout, Sin, Sout, st)
-                          : launch_stream_apl<kBSB, kJFp32, NT>(A, k, xin, xout, Sin, Sout, st);
+    return mode == kASB ? launch_stream_gather<kASB, NT>(jprec, A, k, xin, xout, st)
+                        : launch_stream_gather<kBSB, NT>(jprec, A, k, xin, xout, st);
 }
 
 }  // namespace

@@ -52,7 +52,7 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
     L.perm = take(sizeof(int32_t) * n);
     L.sched = take(sizeof(float) * static_cast<size_t>(K));
     L.xa = take(sizeof(float) * nm);
-    L.xb = mode == SBT_BSB ? take(sizeof(float) * nm) : L.xa;
+    L.xb = mode != SBT_DSB ? take(sizeof(float) * nm) : L.xa;
     L.y = take(sizeof(float) * nm);
     L.epart = take(sizeof(double) * nblk_e * M);
     L.etrace = take(sizeof(double) * static_cast<size_t>(L.n_ckpt) * M);
@@ -164,16 +164,18 @@ sbt::ResidentShape resident_shape(int32_t n, int64_t nnz, int32_t max_row, int t
     return S;
 }
 
-int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, const sbt_solve_params &p, int lds_limit,
+int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sbt_solve_params &p,
+                int lds_limit,
                 sbt::ResidentShape *shape) {
     sbt::ResidentShape S = resident_shape(n, nnz, max_row, p.tpb, lds_limit);
     if (shape) *shape = S;
     if (p.precision == SBT_PREC_FP16 || p.precision == SBT_PREC_BF16)
         return fail(SBT_EUNSUPPORTED,
                     "16-bit couplings are solved by the batch functions (sbt_solve_batch)");
-    if (p.precision == SBT_PREC_FP8) {
+    if (p.precision == SBT_PREC_FP8 || mode == SBT_ASB) {
         if (p.kernel == SBT_KERNEL_RESIDENT)
-            return fail(SBT_EUNSUPPORTED, "FP8 couplings run on the streaming kernel only");
+            return fail(SBT_EUNSUPPORTED, "%s runs on the streaming kernel only",
+                        mode == SBT_ASB ? "aSB" : "FP8 coupling storage");
         return SBT_KERNEL_STREAM;
     }
     if (p.kernel == SBT_KERNEL_STREAM) return SBT_KERNEL_STREAM;
@@ -220,7 +222,7 @@ extern "C" size_t sbt_workspace_bytes(int32_t n, int64_t nnz, sbt_mode mode,
         fail(SBT_EINVAL, "sbt_workspace_bytes: params is NULL");
         return 0;
     }
-    if (mode != SBT_BSB && mode != SBT_DSB) {
+    if (mode != SBT_BSB && mode != SBT_DSB && mode != SBT_ASB) {
         fail(SBT_EINVAL, "sbt_workspace_bytes: unknown mode");
         return 0;
     }
@@ -233,13 +235,13 @@ extern "C" int sbt_select_kernel(int32_t n, int64_t nnz, int32_t max_row_nnz, sb
                                  const sbt_solve_params *p) {
     sbt::clear_error();
     if (!p) return fail(SBT_EINVAL, "sbt_select_kernel: params is NULL");
-    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "sbt_select_kernel: mode");
+    if (mode != SBT_BSB && mode != SBT_DSB && mode != SBT_ASB) return fail(SBT_EINVAL, "sbt_select_kernel: mode");
     int rc = check_params(*p, "sbt_select_kernel");
     if (rc) return rc;
     rc = check_shape(n, nnz, p->agents, "sbt_select_kernel");
     if (rc) return rc;
     if (max_row_nnz < 0) return fail(SBT_EINVAL, "sbt_select_kernel: max_row_nnz < 0");
-    return pick_kernel(n, nnz, max_row_nnz, *p, device_lds_limit(), nullptr);
+    return pick_kernel(n, nnz, max_row_nnz, mode, *p, device_lds_limit(), nullptr);
 }
 
 extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
@@ -248,7 +250,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
     const char *who = "sbt_solve_dev";
     sbt::clear_error();
     if (!q || !p || !out) return fail(SBT_EINVAL, "%s: NULL argument", who);
-    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "%s: unknown mode", who);
+    if (mode != SBT_BSB && mode != SBT_DSB && mode != SBT_ASB) return fail(SBT_EINVAL, "%s: unknown mode", who);
     int rc = check_params(*p, who);
     if (rc) return rc;
     rc = check_shape(q->n, q->nnz, p->agents, who);
@@ -269,7 +271,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
 
     sbt::ResidentShape shape;
-    const int kernel = pick_kernel(n, q->nnz, max_row_nnz, *p, device_lds_limit(), &shape);
+    const int kernel = pick_kernel(n, q->nnz, max_row_nnz, mode, *p, device_lds_limit(), &shape);
     if (kernel < 0) return kernel;
 
     char *ws = static_cast<char *>(workspace);
@@ -450,7 +452,7 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
         p = *pp;
     else
         sbt_solve_params_default(&p);
-    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "%s: unknown mode", who);
+    if (mode != SBT_BSB && mode != SBT_DSB && mode != SBT_ASB) return fail(SBT_EINVAL, "%s: unknown mode", who);
     int rc = check_params(p, who);
     if (rc) return rc;
     int32_t max_row = 0;
@@ -502,7 +504,7 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
     dr.x_final = static_cast<float *>(dx.p);
     dr.y_final = static_cast<float *>(dy.p);
     dr.trace = static_cast<double *>(dtr.p);
-    const int kernel = pick_kernel(n, nnz, max_row, p, device_lds_limit(), nullptr);
+    const int kernel = pick_kernel(n, nnz, max_row, mode, p, device_lds_limit(), nullptr);
     if (kernel < 0) return kernel;
     SBT_HIP(hipEventRecord(hs.e0, hs.s));
     rc = sbt_solve_dev(&dq, max_row, mode, &p, dws.p, ws_bytes, &dr, hs.s);

@@ -106,3 +106,36 @@ def test_stream_agent_words_ragged(M):
         rs = sbt.solve(q, mode, agents=M, steps=120, seed=9, kernel="stream", want_state=True)
         assert np.array_equal(rr["x"], rs["x"]), mode
         assert np.array_equal(rr["y"], rs["y"]), mode
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp8"])
+@pytest.mark.parametrize("M", [70, 96])
+def test_asb_trajectory_matches_oracle(prec, M):
+    """aSB (Eq. 1-2, no walls) on the streaming kernel; dt = 0.1 (its
+    explicit steps diverge on this event at dt >= 0.5).  M = 96 runs the
+    four-agents-per-lane variant, M = 70 the lane-strided one."""
+    ev, q, b, isg = _event(tg.plain_spec(), 100)
+    J = oquant.fp8_rows(isg.J)[0] if prec == "fp8" else isg.J
+    K, dt, seed = 20, 0.1, 11
+    r = sbt.solve(q, "asb", agents=M, steps=K, dt=dt, seed=seed, precision=prec, want_state=True)
+    assert r["kernel"] == "stream"
+    ref = osb.run(J, isg.h, isg.c0, "asb", M, K, dt=dt, seed=seed)
+    err = np.linalg.norm(r["x"] - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
+    assert np.all(err <= 1e-5), err.max()
+    assert np.abs(ref.x).max() > 1.0            # no wall: positions leave [-1, 1]
+    yerr = np.linalg.norm(r["y"] - ref.y, axis=0) / np.linalg.norm(ref.y, axis=0)
+    assert np.all(yerr <= 1e-5), yerr.max()
+
+
+def test_asb_energies_and_unsupported_paths():
+    ev, q, b, isg = _event(tg.plain_spec(), 101)
+    r = sbt.solve(q, "asb", agents=64, steps=300, dt=0.1, seed=2, want_state=True)
+    T = (r["x"] >= 0).astype(np.int8)
+    e_or = oenergy.qubo_energy(q.a, b, T)
+    assert np.all(np.abs(r["agent_energy"] - e_or) <= 1e-9 * np.maximum(1.0, np.abs(e_or)))
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve(q, "asb", agents=8, steps=10, kernel="resident")
+    assert e.value.code == _lib.SBT_EUNSUPPORTED
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve_batch([q], "asb", agents=8, steps=10)
+    assert e.value.code == _lib.SBT_EUNSUPPORTED

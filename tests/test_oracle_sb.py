@@ -205,3 +205,43 @@ def test_tiny_event_solution_reconstructs_every_track():
     assert np.array_equal(T, tracks.true_triplet_mask(ev, q.trip_hits))
     eff, pur, *_ = tracks.evaluate(ev, q.trip_hits, T)
     assert eff == 1.0 and pur == 1.0
+
+
+def test_asb_single_oscillator_converges_to_the_ode():
+    """aSB with J = 0, h = 0 is dx/dt = a0 y, dy/dt = -(x^2 + a0 - a(t)) x
+    (Eq. 1-2) with a(t) = a0 t / T.  Symplectic Euler converges to the exact
+    trajectory at first order in dt: halving dt halves the error."""
+    from scipy.integrate import solve_ivp
+    a0, T = 1.0, 3.0
+    x0, y0 = np.array([[0.3]]), np.array([[-0.2]])
+
+    def rhs(t, u):
+        return [a0 * u[1], -(u[0] ** 2 + a0 - a0 * t / T) * u[0]]
+
+    exact = solve_ivp(rhs, (0.0, T), [0.3, -0.2], rtol=1e-12, atol=1e-12).y[:, -1]
+    errs = []
+    for K in (3000, 6000):
+        r = sb.run(sp.csr_matrix((1, 1)), np.zeros(1), 0.5, "asb", 1, K, dt=T / K, a0=a0,
+                   x0=x0, y0=y0)
+        errs.append(abs(r.x[0, 0] - exact[0]) + abs(r.y[0, 0] - exact[1]))
+    assert errs[0] < 3e-3
+    assert 1.6 < errs[0] / errs[1] < 2.4
+
+
+def test_asb_has_no_walls_and_odd_symmetry():
+    rng = np.random.default_rng(3)
+    n = 12
+    A = sp.random(n, n, density=0.4, random_state=5, data_rvs=lambda k: rng.normal(0, 1, k))
+    J = sp.csr_matrix(A + A.T)
+    x0 = rng.uniform(-0.1, 0.1, (n, 4))
+    y0 = rng.uniform(-0.1, 0.1, (n, 4))
+    # (explicit steps of the cubic force need a small dt: at c0 = 2, dt = 0.2
+    # this system diverges)
+    r1 = sb.run(J, np.zeros(n), 1.0, "asb", 4, 200, dt=0.1, x0=x0, y0=y0)
+    r2 = sb.run(J, np.zeros(n), 1.0, "asb", 4, 200, dt=0.1, x0=-x0, y0=-y0)
+    assert np.all(np.isfinite(r1.x))
+    assert np.array_equal(r1.x, -r2.x) and np.array_equal(r1.y, -r2.y)
+    # the coupling carries positions past 1, which bSB's wall forbids
+    assert np.abs(r1.x).max() > 1.0
+    rb = sb.run(J, np.zeros(n), 1.0, "bsb", 4, 200, dt=0.1, x0=x0, y0=y0)
+    assert np.abs(rb.x).max() <= 1.0
