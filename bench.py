@@ -508,6 +508,23 @@ def main():
             e_low = min(e_star, ck["final"])
             ttt[mode] = {"oracle_best": e_star, "checkpoint": ck, "ttt99_target": 0.999 * e_low,
                          "ttt99": ttt99(mk, 0.999 * e_low, AGENTS, torch)}
+        # CPU comparator (the paper's SA baseline role): TTT99 over sweeps
+        e_low = min(ref["modes"][m]["best"] for m in ("bsb", "dsb"))
+        target = 0.999 * e_low
+        best = None
+        for sweeps in (10, 30, 100, 300, 1000):
+            r = sbt.anneal_cpu(q, shots=50, sweeps=sweeps, seed=SOLVER_SEED)
+            p_s = float(np.mean(r["shot_energy"] <= target))
+            if p_s == 0.0:
+                continue
+            P = 1.0 - (1.0 - p_s) ** 50
+            tt = r["elapsed_s"] if P >= 0.99 else r["elapsed_s"] * np.log(0.01) / np.log1p(-P)
+            if best is None or tt < best["seconds"]:
+                best = {"sweeps": sweeps, "seconds": float(tt), "p_shot": p_s,
+                        "run_seconds": r["elapsed_s"]}
+        ttt["sa_cpu"] = {"target": target, "shots": 50, "cores": os.cpu_count(),
+                         "ttt99": best,
+                         "note": "single-flip Metropolis annealing on the host, all cores"}
         result["time_to_target"] = ttt
         log("time-to-target done")
 

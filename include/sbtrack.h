@@ -117,6 +117,35 @@ void sbt_qubo_free(sbt_qubo *q);
 int sbt_build_qubo_gpu(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *p,
                        sbt_qubo **out, double *elapsed_s);
 
+/* ------------------------------------------------------------------------
+ * Simulated annealing on the CPU (the comparator of section "Simulated
+ * Annealing": single-spin moves accepted by the Metropolis rule while the
+ * temperature falls)
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t shots;      /* independent runs >= 1 (each from T = 0)           */
+    int32_t sweeps;     /* passes over the spins in index order >= 1         */
+    double beta_hot;    /* first inverse temperature; <= 0: ln 2 / the       */
+                        /* largest possible energy change                    */
+    double beta_cold;   /* last one (geometric in between); <= 0: ln 100 /   */
+                        /* the smallest nonzero |a_i| or |b_ij|              */
+    uint64_t seed;      /* shot s uses its own stream from (seed, s)         */
+    int32_t threads;    /* host threads; 0 = all hardware threads            */
+    int32_t reserved;   /* 0                                                 */
+} sbt_anneal_params;
+
+/* shots = 50, sweeps = 1000, automatic temperatures, seed 0, all threads. */
+void sbt_anneal_params_default(sbt_anneal_params *p);
+
+/* Anneal the QUBO in host memory; O(T) (Eq. 13, FP64) of every shot's
+ * final T, the best (lowest shot index on ties) returned.
+ *   T_best       caller [n]      energy  out: O(T_best)
+ *   shot_energy  caller [shots] or NULL   elapsed_s  out or NULL: wall time
+ * Errors: SBT_EINVAL for a malformed QUBO or parameters. */
+int sbt_anneal_cpu(const sbt_qubo *q, const sbt_anneal_params *p, int8_t *T_best,
+                   double *energy, double *shot_energy, double *elapsed_s);
+
 /* Spin order for the solver's caches (a relabelling only; the section
  * "QUBO formulation" fixes the problem, not its index order): triplets
  * sorted by the azimuth of their middle hit, then its z, then index.  The

@@ -117,6 +117,22 @@ def _take_qubo(out) -> Qubo:
     return res
 
 
+def anneal_cpu(q: Qubo, shots: int = 50, sweeps: int = 1000, beta_hot: float = 0.0,
+               beta_cold: float = 0.0, seed: int = 0, threads: int = 0) -> dict:
+    """sbt_anneal_cpu: single-flip Metropolis annealing on the host."""
+    p = _lib.SbtAnnealParams()
+    load().sbt_anneal_params_default(C.byref(p))
+    p.shots, p.sweeps, p.beta_hot, p.beta_cold = shots, sweeps, beta_hot, beta_cold
+    p.seed, p.threads = seed & 0xFFFFFFFFFFFFFFFF, threads
+    T = np.zeros(q.n, dtype=np.int8)
+    se = np.zeros(shots)
+    e, t = C.c_double(), C.c_double()
+    s = q.as_struct()
+    check(load().sbt_anneal_cpu(C.byref(s), C.byref(p), T.ctypes.data_as(C.POINTER(C.c_int8)),
+                                C.byref(e), se.ctypes.data_as(C.POINTER(C.c_double)), C.byref(t)))
+    return {"T": T, "energy": float(e.value), "shot_energy": se, "elapsed_s": float(t.value)}
+
+
 def phi_order(q: Qubo, hits: np.ndarray) -> np.ndarray:
     """sbt_phi_order: triplets sorted by the azimuth (then z) of their
     middle hit; perm[k] = original index of the triplet placed at k."""
@@ -428,7 +444,7 @@ class DeviceBatchSolver:
 
 
 __all__ = ["Qubo", "DeviceSolver", "DeviceBatchSolver", "build_qubo", "energy", "solve",
-           "phi_order", "permute_qubo", "build_qubo_gpu", "c0_scan",
+           "phi_order", "permute_qubo", "build_qubo_gpu", "c0_scan", "anneal_cpu",
            "solve_batch", "solve_params", "workspace_bytes", "select_kernel",
            "build_params_default", "version", "load", "SbtError", "HIT_DTYPE", "MODES",
            "KERNELS", "PRECISIONS"]

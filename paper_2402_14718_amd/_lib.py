@@ -52,6 +52,12 @@ class SbtSolveParams(C.Structure):
                 ("tpb", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32)]
 
 
+class SbtAnnealParams(C.Structure):
+    _fields_ = [("shots", C.c_int32), ("sweeps", C.c_int32), ("beta_hot", C.c_double),
+                ("beta_cold", C.c_double), ("seed", C.c_uint64), ("threads", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
 class SbtResult(C.Structure):
     _fields_ = [("T", C.POINTER(C.c_int8)), ("agent_energy", C.POINTER(C.c_double)),
                 ("trace", C.POINTER(C.c_double)), ("x_final", C.POINTER(C.c_float)),
@@ -107,6 +113,10 @@ EXPORTS = [
     ("sbt_energy", C.c_int, [C.POINTER(SbtQubo), C.POINTER(C.c_int8), C.POINTER(C.c_double)]),
     ("sbt_build_qubo_gpu", C.c_int, [C.POINTER(SbtHit), C.c_int64, C.POINTER(SbtBuildParams),
                                      C.POINTER(C.POINTER(SbtQubo)), C.POINTER(C.c_double)]),
+    ("sbt_anneal_params_default", None, [C.POINTER(SbtAnnealParams)]),
+    ("sbt_anneal_cpu", C.c_int, [C.POINTER(SbtQubo), C.POINTER(SbtAnnealParams),
+                                 C.POINTER(C.c_int8), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("sbt_phi_order", C.c_int, [C.POINTER(SbtQubo), C.POINTER(SbtHit), C.c_int64,
                                 C.POINTER(C.c_int32)]),
     ("sbt_qubo_permute", C.c_int, [C.POINTER(SbtQubo), C.POINTER(C.c_int32),

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["status.cpp", "build_qubo.cpp", "order.cpp"]
+HOST_SOURCES = ["status.cpp", "build_qubo.cpp", "order.cpp", "anneal.cpp"]
 RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
 HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_batch.hip", "sb_stream.hip",
                "build_qubo_gpu.hip"]
@@ -66,7 +66,7 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     tmp = LIB_PATH + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
-          f"-L{ROCM}/lib", "-lamdhip64", f"-Wl,-rpath,{ROCM}/lib"], verbose)
+          f"-L{ROCM}/lib", "-lamdhip64", "-pthread", f"-Wl,-rpath,{ROCM}/lib"], verbose)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
