@@ -96,10 +96,13 @@ def test_fp8_full_size_quality(mode):
     assert abs(eff8 - eff32) <= 0.02 and abs(pur8 - pur32) <= 0.02
 
 
-@pytest.mark.parametrize("M", [1, 63, 64, 65, 130])
+@pytest.mark.parametrize("M", [1, 63, 64, 65, 130, 600, 1100, 1101])
 def test_stream_agent_words_ragged(M):
-    """Agent counts around the 64-agent word of the sign planes: the
-    streaming kernel against the resident one, bit for bit."""
+    """Agent counts around the 64-agent word of the sign planes and past one
+    wave's 512 (dSB) / 256 (bSB) agents -- several agent blocks per row, a
+    ragged last block, the four-agents-per-lane bSB variant (M % 4 = 0) and
+    the lane-strided one: the streaming kernel against the resident one, bit
+    for bit."""
     ev, q, b, isg = _event(tg.plain_spec(60), 7)
     for mode in ("bsb", "dsb"):
         rr = sbt.solve(q, mode, agents=M, steps=120, seed=9, kernel="resident", want_state=True)
