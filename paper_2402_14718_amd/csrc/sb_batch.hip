@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             for_slots([&](auto sc) __attribute__((always_inline)) {
                 constexpr int S = decltype(sc)::value;
                 if (spin[S] >= 0) {
-                    sb_update(xr[S], yr[S], acc[S], c0, g, dt, dta0);
+                    sb_step<MODE>(xr[S], yr[S], acc[S], c0, g, dt, dta0);
                     const uint32_t w = opaque(static_cast<uint32_t>(spin[S]));
                     xn[static_cast<int>(w) * A + a] = shared_value<MODE>(xr[S]);
                 }
@@ -455,6 +455,9 @@ hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream
     if (mode == kDSB)
         return jprec == kJFp16 ? launch_with_lds(sb_batch<kDSB, kJFp16>, grid, block, lds, st, B)
                                : launch_with_lds(sb_batch<kDSB, kJBf16>, grid, block, lds, st, B);
+    if (mode == kASB)
+        return jprec == kJFp16 ? launch_with_lds(sb_batch<kASB, kJFp16>, grid, block, lds, st, B)
+                               : launch_with_lds(sb_batch<kASB, kJBf16>, grid, block, lds, st, B);
     return jprec == kJFp16 ? launch_with_lds(sb_batch<kBSB, kJFp16>, grid, block, lds, st, B)
                            : launch_with_lds(sb_batch<kBSB, kJBf16>, grid, block, lds, st, B);
 }

@@ -92,6 +92,16 @@ __device__ __forceinline__ void sb_update_asb(float &x, float &y, float F, float
     x = __builtin_fmaf(dta0, y, x);
 }
 
+// The step of the mode: aSB (no wall) or bSB / dSB (wall).
+template <int MODE>
+__device__ __forceinline__ void sb_step(float &x, float &y, float F, float c0, float g, float dt,
+                                        float dta0) {
+    if constexpr (MODE == kASB)
+        sb_update_asb(x, y, F, c0, g, dt, dta0);
+    else
+        sb_update(x, y, F, c0, g, dt, dta0);
+}
+
 // What the coupling reads of a neighbour: its position (bSB, aSB) or sign (dSB).
 template <int MODE>
 __device__ __forceinline__ float shared_value(float x) {

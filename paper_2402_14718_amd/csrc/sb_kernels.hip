@@ -187,8 +187,10 @@ __global__ __launch_bounds__(TPB) void sb_resident(ResidentArgs A) {
     const float c0 = static_cast<float>(A.scal[0]);
     const float dt = A.dt, dta0 = A.dta0;
     int cur = 0, ck = 0;
+    float g_next = A.sched[0];  // loaded one step ahead
     for (int k = 0; k < A.K; ++k) {
-        const float g = A.sched[k];
+        const float g = g_next;
+        g_next = A.sched[min(k + 1, A.K - 1)];
         const float *xc = xs + cur * n;
         float *xn = xs + (cur ^ 1) * n;
 #pragma unroll
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(TPB) void sb_resident(ResidentArgs A) {
             if (i < n) {
                 float acc = hr[s];
                 for (int p = p0[s]; p < p1[s]; ++p) acc = __builtin_fmaf(jv[p], xc[cl[p]], acc);
-                sb_update(xr[s], yr[s], acc, c0, g, dt, dta0);
+                sb_step<MODE>(xr[s], yr[s], acc, c0, g, dt, dta0);
                 xn[i] = shared_value<MODE>(xr[s]);
             }
         }
@@ -392,6 +394,7 @@ static hipError_t launch_resident_m(const ResidentArgs &A, const ResidentShape &
 
 hipError_t launch_resident(int mode, const ResidentArgs &A, const ResidentShape &S, hipStream_t st) {
     if (S.rc > 0) return launch_resident_reg(mode, A, S, st);
+    if (mode == kASB) return launch_resident_m<kASB>(A, S, st);
     return mode == kDSB ? launch_resident_m<kDSB>(A, S, st) : launch_resident_m<kBSB>(A, S, st);
 }
 

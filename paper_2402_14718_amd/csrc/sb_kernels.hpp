@@ -38,7 +38,19 @@ struct ResidentShape {
     size_t lds_bytes;
 };
 
-constexpr int kRegMaxN = 8192;   // register-row variant: largest n (buffer stride)
+// Register-row variant: VGPR estimate of a thread holding spt spins with rc
+// couplings each (fit to the compiler's counts), the budget at a
+// workgroup size, and which (workgroup size, spt, rc) exist -- the host
+// picks a shape only among these.
+constexpr int reg_vgpr_estimate(int spt, int rc) { return 4 * spt * rc + 12 * spt + 40; }
+constexpr int reg_vgpr_budget(int maxtpb) { return maxtpb >= 1024 ? 128 : (maxtpb >= 512 ? 256 : 512); }
+constexpr bool reg_variant_fits(int maxtpb, int spt, int rc) {
+    return !(spt > 4 && rc > 4) && reg_vgpr_estimate(spt, rc) <= reg_vgpr_budget(maxtpb);
+}
+
+constexpr int kRegMaxN = 8192;   // register-row variant: largest n
+constexpr int kRegStride = kRegMaxN + 64;  // LDS position buffer: n words, then one pad
+                                           //   word per lane of a wave
 
 // Streaming kernel's couplings: CSR with every row padded to a multiple of
 // kStreamChunk entries by (own column, zero coupling), so each chunk of

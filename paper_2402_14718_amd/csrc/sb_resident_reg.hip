@@ -2,17 +2,21 @@
 //
 // Paper section "Simulated Bifurcation": all K symplectic-Euler steps of
 // bSB (Eq. 5-8) or dSB (Eq. 9-12) for one agent run inside one workgroup.
-// Positions live in LDS (two buffers, kRegMaxN floats apart), momenta and
+// Positions live in LDS (two buffers, kRegStride floats apart), momenta and
 // each spin's couplings (column, J) live in VGPRs, so a step is: gather
 // x_j for every held coupling, FMAs in CSR order, the update, one LDS
 // store, one barrier.  Nothing touches HBM between the first and the last
 // step.
 //
-// Spins are handed to threads in order of decreasing row length (thread t
-// takes sorted positions t*SPT .. t*SPT+SPT-1), so the number of gathers a
-// wave issues -- the longest row among its spins -- is small for almost
-// every wave.  A spin's arithmetic does not depend on which thread runs
-// it, so results are bit-identical to the streaming kernel.
+// Spins are handed out slot-major in order of decreasing row length (slot s
+// of thread t takes sorted position s*T + t, T threads), so the few long
+// rows sit in slot 0 of the first waves.  Each wave picks, once, a step
+// loop with a fixed gather count for slot 0 and one for its other slots
+// (the longest row it holds there), so a step has no branches.  Entries
+// past a row's length hold J = 0 and column 0: adding them changes at most
+// the sign of a zero sum, which never grows into a nonzero difference.  A
+// spin's arithmetic does not depend on which thread runs it, so results are
+// bit-identical to the streaming kernel.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -56,49 +60,51 @@ __global__ __launch_bounds__(1024) void row_order(int n, const int *__restrict__
     }
 }
 
-// Gather-and-sum over the first C held couplings of every slot: all LDS
-// loads first, then the FMAs in CSR order onto acc (which enters holding
-// h_i).  LDS holds what the coupling reads (x for bSB, sgn x for dSB).
-// Entries past a row's length hold J = 0 and column 0: an exact zero
-// contribution, since the running sum is never -0.
-template <int SPT, int RC, int C>
-__device__ __forceinline__ void reg_dots(const float *__restrict__ xc, const int (&cols)[SPT][RC],
-                                         const float (&js)[SPT][RC], float (&acc)[SPT]) {
-    float v[SPT][C];
-#pragma unroll
-    for (int s = 0; s < SPT; ++s)
-#pragma unroll
-        for (int e = 0; e < C; ++e) v[s][e] = xc[cols[s][e]];
-#pragma unroll
-    for (int s = 0; s < SPT; ++s) {
-        float a = acc[s];
-#pragma unroll
-        for (int e = 0; e < C; ++e) a = __builtin_fmaf(js[s][e], v[s][e], a);
-        acc[s] = a;
+// Calls f(integral_constant<int, C>) with C the smallest of 2, 4, RC that
+// covers cap (cap is wave-uniform).
+template <int RC, class F>
+__device__ __forceinline__ void by_cap(int cap, F &&f) {
+    if constexpr (RC <= 2) {
+        f(std::integral_constant<int, RC>{});
+    } else if constexpr (RC <= 4) {
+        if (cap <= 2)
+            f(std::integral_constant<int, 2>{});
+        else
+            f(std::integral_constant<int, RC>{});
+    } else {
+        if (cap <= 2)
+            f(std::integral_constant<int, 2>{});
+        else if (cap <= 4)
+            f(std::integral_constant<int, 4>{});
+        else
+            f(std::integral_constant<int, RC>{});
     }
 }
 
 template <int MODE, int MAXTPB, int SPT, int RC>
 __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
-    float *xs = reinterpret_cast<float *>(smem);  // [2][kRegMaxN]
-    double *red = reinterpret_cast<double *>(xs + 2 * kRegMaxN);
+    float *xs = reinterpret_cast<float *>(smem);  // [2][kRegStride]
+    double *red = reinterpret_cast<double *>(xs + 2 * kRegStride);
     const int n = A.n;
     const int t = threadIdx.x;
     const int m = blockIdx.x;
     const int M = A.M;
 
     float xr[SPT], yr[SPT], hr[SPT];
-    int spin[SPT];
+    int spin[SPT], wr[SPT];
     int cols[SPT][RC];
     float js[SPT][RC];
     int tail0[SPT], tail1[SPT];
-    int need = 0, tail = 0;
+    int need0 = 0, need_rest = 0, rest = 0, tail = 0;
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
-        const int j = t * SPT + s;
+        const int j = s * static_cast<int>(blockDim.x) + t;
         const int i = j < n ? A.perm[j] : -1;
         spin[s] = i;
+        // a lane without a spin in this slot updates a zero oscillator and
+        // stores it to its own pad word, so the step has no branches
+        wr[s] = i >= 0 ? i : kRegMaxN + (t & 63);
         xr[s] = yr[s] = hr[s] = 0.0f;
         tail0[s] = tail1[s] = 0;
 #pragma unroll
@@ -121,81 +127,114 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
             }
             tail0[s] = p0 + RC;
             tail1[s] = p1;
-            need = max(need, p1 - p0);
+            if (s == 0) {
+                need0 = p1 - p0;
+            } else {
+                need_rest = max(need_rest, p1 - p0);
+                rest = 1;
+            }
             tail |= (p1 - p0 > RC) ? 1 : 0;
             xs[i] = shared_value<MODE>(xr[s]);
         }
     }
-    const int cap = wave_max_int(need);
+    const int cap0 = wave_max_int(need0);
+    const int cap_rest = wave_max_int(need_rest);
+    const int any_rest = wave_max_int(rest);
     const int any_tail = wave_max_int(tail);
     __syncthreads();
 
     const float c0 = static_cast<float>(A.scal[0]);
     const float dt = A.dt, dta0 = A.dta0;
-    int ck = 0;
-    auto step = [&](auto bufc, int k) {
-        constexpr int B = decltype(bufc)::value;
-        const float *xc = xs + B * kRegMaxN;
-        float *xn = xs + (B ^ 1) * kRegMaxN;
-        const float g = A.sched[k];
-        float acc[SPT];
+
+    // The whole step loop, specialised per wave: C0 gathers for slot 0, CR
+    // for every other slot (0: this wave holds no spin past slot 0).  The
+    // choice is made once, so a step runs straight through: gathers, FMAs
+    // in CSR order, update, LDS store, barrier (rows longer than RC, rare,
+    // continue from global memory out of line).  Every variant meets the
+    // same barriers.
+    auto run = [&](auto c0c, auto crc) __attribute__((always_inline)) {
+        constexpr int C0 = decltype(c0c)::value;
+        constexpr int CR = decltype(crc)::value;
+        constexpr int NS = CR > 0 ? SPT : 1;  // slots this wave updates
+        auto step = [&](auto bufc, int k) __attribute__((always_inline)) {
+            constexpr int B = decltype(bufc)::value;
+            const float *xc = xs + B * kRegStride;
+            float *xn = xs + (B ^ 1) * kRegStride;
+            const float g = A.sched[k];
+            float acc[SPT];
+            float v[SPT][RC];
 #pragma unroll
-        for (int s = 0; s < SPT; ++s) acc[s] = hr[s];
-        if constexpr (RC <= 2) {
-            reg_dots<SPT, RC, RC>(xc, cols, js, acc);
-        } else if constexpr (RC <= 4) {
-            if (cap <= 2)
-                reg_dots<SPT, RC, 2>(xc, cols, js, acc);
-            else
-                reg_dots<SPT, RC, RC>(xc, cols, js, acc);
-        } else {
-            if (cap <= 2)
-                reg_dots<SPT, RC, 2>(xc, cols, js, acc);
-            else if (cap <= 4)
-                reg_dots<SPT, RC, 4>(xc, cols, js, acc);
-            else
-                reg_dots<SPT, RC, RC>(xc, cols, js, acc);
-        }
-        if (any_tail) {
+            for (int s = 0; s < NS; ++s) {
+                acc[s] = hr[s];
+                const int C = s == 0 ? C0 : CR;
 #pragma unroll
-            for (int s = 0; s < SPT; ++s)
-                for (int p = tail0[s]; p < tail1[s]; ++p)
-                    acc[s] = __builtin_fmaf(A.J[p], xc[A.col[p]], acc[s]);
-        }
-#pragma unroll
-        for (int s = 0; s < SPT; ++s) {
-            if (spin[s] >= 0) {
-                sb_update(xr[s], yr[s], acc[s], c0, g, dt, dta0);
-                xn[spin[s]] = shared_value<MODE>(xr[s]);
+                for (int e = 0; e < C; ++e) v[s][e] = xc[cols[s][e]];
             }
-        }
-        __syncthreads();
-        if (A.ckpt_every > 0 && (k + 1) % A.ckpt_every == 0) {
-            // FP64 O(T) of this agent's current state (Eq. 13)
-            double e = 0.0;
 #pragma unroll
-            for (int s = 0; s < SPT; ++s) {
-                const int i = spin[s];
-                if (i >= 0 && xr[s] >= 0.0f) {
-                    double er = A.a[i];
-                    for (int p = A.row_ptr[i]; p < A.row_ptr[i + 1]; ++p) {
-                        const int c = A.col[p];
-                        if (c > i && xn[c] >= 0.0f) er += A.b[p];
+            for (int s = 0; s < NS; ++s) {
+                const int C = s == 0 ? C0 : CR;
+#pragma unroll
+                for (int e = 0; e < C; ++e) acc[s] = __builtin_fmaf(js[s][e], v[s][e], acc[s]);
+            }
+            if (__builtin_expect(any_tail, 0)) {
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    for (int p = tail0[s]; p < tail1[s]; ++p)
+                        acc[s] = __builtin_fmaf(A.J[p], xc[A.col[p]], acc[s]);
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                sb_step<MODE>(xr[s], yr[s], acc[s], c0, g, dt, dta0);
+                xn[wr[s]] = shared_value<MODE>(xr[s]);
+            }
+            __syncthreads();
+        };
+        // steps in runs between checkpoints; the buffer read at step k is k & 1
+        int k = 0, ck = 0;
+        while (k < A.K) {
+            const int kend =
+                A.ckpt_every > 0 ? min(A.K, k - k % A.ckpt_every + A.ckpt_every) : A.K;
+            if (k & 1) step(std::integral_constant<int, 1>{}, k++);
+            for (; k + 1 < kend; k += 2) {
+                step(std::integral_constant<int, 0>{}, k);
+                step(std::integral_constant<int, 1>{}, k + 1);
+            }
+            if (k < kend) step(std::integral_constant<int, 0>{}, k++);
+            if (A.ckpt_every > 0 && k % A.ckpt_every == 0) {
+                // FP64 O(T) of this agent's current state (Eq. 13)
+                const float *xv = xs + (k & 1) * kRegStride;
+                double e = 0.0;
+#pragma unroll
+                for (int s = 0; s < SPT; ++s) {
+                    const int i = spin[s];
+                    if (i >= 0 && xr[s] >= 0.0f) {
+                        double er = A.a[i];
+                        for (int p = A.row_ptr[i]; p < A.row_ptr[i + 1]; ++p) {
+                            const int c = A.col[p];
+                            if (c > i && xv[c] >= 0.0f) er += A.b[p];
+                        }
+                        e += er;
                     }
-                    e += er;
                 }
+                const double tot = block_sum(e, red);
+                if (t == 0) A.etrace[static_cast<size_t>(ck) * M + m] = tot;
+                ++ck;
             }
-            const double tot = block_sum(e, red);
-            if (t == 0) A.etrace[static_cast<size_t>(ck) * M + m] = tot;
-            ++ck;
         }
     };
-    int k = 0;
-    for (; k + 1 < A.K; k += 2) {
-        step(std::integral_constant<int, 0>{}, k);
-        step(std::integral_constant<int, 1>{}, k + 1);
-    }
-    if (k < A.K) step(std::integral_constant<int, 0>{}, k);
+    // rows past slot 0 are short: 2 gathers, else RC
+    by_cap<RC>(cap0, [&](auto c0c) __attribute__((always_inline)) {
+        if constexpr (SPT == 1) {
+            run(c0c, std::integral_constant<int, 0>{});
+        } else {
+            if (!any_rest)
+                run(c0c, std::integral_constant<int, 0>{});
+            else if (cap_rest <= 2)
+                run(c0c, std::integral_constant<int, 2>{});
+            else
+                run(c0c, std::integral_constant<int, RC>{});
+        }
+    });
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
         const int i = spin[s];
@@ -215,16 +254,23 @@ hipError_t launch_row_order(int n, const int *row_ptr, int *perm, hipStream_t st
 template <int MODE, int MAXTPB, int SPT>
 static hipError_t launch_reg_rc(const ResidentArgs &A, const ResidentShape &S, hipStream_t st) {
     const dim3 grid(A.M), block(S.tpb);
+    // only the shapes the host can pick are built
     switch (S.rc) {
-        case 2: return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, 2>, grid, block, S.lds_bytes, st, A);
-        case 4: return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, 4>, grid, block, S.lds_bytes, st, A);
+        case 2:
+            if constexpr (reg_variant_fits(MAXTPB, SPT, 2))
+                return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, 2>, grid, block, S.lds_bytes, st, A);
+            break;
+        case 4:
+            if constexpr (reg_variant_fits(MAXTPB, SPT, 4))
+                return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, 4>, grid, block, S.lds_bytes, st, A);
+            break;
         case 8:
-            if constexpr (SPT <= 4)
+            if constexpr (reg_variant_fits(MAXTPB, SPT, 8))
                 return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, 8>, grid, block, S.lds_bytes, st, A);
-            else
-                return hipErrorInvalidValue;
-        default: return hipErrorInvalidValue;
+            break;
+        default: break;
     }
+    return hipErrorInvalidValue;
 }
 
 template <int MODE, int MAXTPB>
@@ -249,6 +295,7 @@ static hipError_t launch_reg_m(const ResidentArgs &A, const ResidentShape &S, hi
 
 hipError_t launch_resident_reg(int mode, const ResidentArgs &A, const ResidentShape &S,
                                hipStream_t st) {
+    if (mode == kASB) return launch_reg_m<kASB>(A, S, st);
     return mode == kDSB ? launch_reg_m<kDSB>(A, S, st) : launch_reg_m<kBSB>(A, S, st);
 }
 

@@ -130,15 +130,11 @@ sbt::ResidentShape resident_shape(int32_t n, int64_t nnz, int32_t max_row, int t
             const int cap_tpb = hinted ? tpb_hint : 1024;
             if (tpb > cap_tpb) continue;
             const int maxtpb = tpb <= 256 ? 256 : (tpb <= 512 ? 512 : 1024);
-            // VGPR estimate of the kernel (fit to the compiler's counts)
-            const int budget = maxtpb >= 1024 ? 128 : (maxtpb >= 512 ? 256 : 512);
-            auto vgprs = [&](int r) { return (7 * spt * r) / 2 + 12 * spt + 40; };
             int rc = max_row <= 2 ? 2 : (max_row <= 4 ? 4 : 8);
-            if (spt > 4 && rc > 4) rc = 4;
-            while (rc > 2 && vgprs(rc) > budget) rc >>= 1;
-            if (vgprs(rc) > budget) continue;
+            while (rc > 2 && !sbt::reg_variant_fits(maxtpb, spt, rc)) rc >>= 1;
+            if (!sbt::reg_variant_fits(maxtpb, spt, rc)) continue;
             const size_t lds =
-                sizeof(float) * 2 * sbt::kRegMaxN + sizeof(double) * (maxtpb / 64);
+                sizeof(float) * 2 * sbt::kRegStride + sizeof(double) * (maxtpb / 64);
             if (lds > static_cast<size_t>(lds_limit)) break;
             S.tpb = tpb;
             S.spt = spt;
@@ -172,10 +168,9 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
     if (p.precision == SBT_PREC_FP16 || p.precision == SBT_PREC_BF16)
         return fail(SBT_EUNSUPPORTED,
                     "16-bit couplings are solved by the batch functions (sbt_solve_batch)");
-    if (p.precision == SBT_PREC_FP8 || mode == SBT_ASB) {
+    if (p.precision == SBT_PREC_FP8) {
         if (p.kernel == SBT_KERNEL_RESIDENT)
-            return fail(SBT_EUNSUPPORTED, "%s runs on the streaming kernel only",
-                        mode == SBT_ASB ? "aSB" : "FP8 coupling storage");
+            return fail(SBT_EUNSUPPORTED, "FP8 coupling storage runs on the streaming kernel only");
         return SBT_KERNEL_STREAM;
     }
     if (p.kernel == SBT_KERNEL_STREAM) return SBT_KERNEL_STREAM;

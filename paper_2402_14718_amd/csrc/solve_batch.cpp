@@ -196,8 +196,8 @@ extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_prec
     const char *who = "sbt_batch_run";
     sbt::clear_error();
     if (!batch || !p || !out) return fail(SBT_EINVAL, "%s: NULL argument", who);
-    if (mode == SBT_ASB) return fail(SBT_EUNSUPPORTED, "%s: aSB runs on the streaming kernel only", who);
-    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "%s: unknown mode", who);
+    if (mode != SBT_BSB && mode != SBT_DSB && mode != SBT_ASB)
+        return fail(SBT_EINVAL, "%s: unknown mode", who);
     if (prec != SBT_PREC_FP16 && prec != SBT_PREC_BF16)
         return fail(SBT_EUNSUPPORTED, "%s: batches hold 16-bit couplings (FP16 or BF16)", who);
     int rc = check_batch_params(*p, who);
@@ -289,8 +289,8 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     if (!qs || !out || !out->energy || !out->best_agent)
         return fail(SBT_EINVAL, "%s: NULL argument", who);
     if (E < 1) return fail(SBT_EINVAL, "%s: n_events must be >= 1", who);
-    if (mode == SBT_ASB) return fail(SBT_EUNSUPPORTED, "%s: aSB runs on the streaming kernel only", who);
-    if (mode != SBT_BSB && mode != SBT_DSB) return fail(SBT_EINVAL, "%s: unknown mode", who);
+    if (mode != SBT_BSB && mode != SBT_DSB && mode != SBT_ASB)
+        return fail(SBT_EINVAL, "%s: unknown mode", who);
     if (prec != SBT_PREC_FP16 && prec != SBT_PREC_BF16)
         return fail(SBT_EUNSUPPORTED, "%s: batches hold 16-bit couplings (FP16 or BF16)", who);
     sbt_solve_params p;

@@ -49,12 +49,12 @@ def _events(specs_seeds):
     return evs, qs
 
 
-def _oracle_run(q, prec, mode, M, K, seed, event):
+def _oracle_run(q, prec, mode, M, K, seed, event, dt=1.0):
     b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
     isg = oising.from_qubo(q.a, b)
     Jq = isg.J.copy()
     Jq.data = QUANT[prec](Jq.data)
-    return b, isg, osb.run(Jq, isg.h, isg.c0, mode, M, K, seed=seed, event=event,
+    return b, isg, osb.run(Jq, isg.h, isg.c0, mode, M, K, dt=dt, seed=seed, event=event,
                            margin_steps=K)
 
 
@@ -87,6 +87,30 @@ def test_batch_trajectories_match_oracle_with_rounded_couplings(prec, mode):
         assert r["best_agent"][e] == best
         assert np.array_equal(r["T"][e], T[:, best])
         assert abs(r["offset"][e] - isg.C) <= 1e-9 * max(1.0, abs(isg.C))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_batch_asb_matches_oracle(prec):
+    """aSB (Eq. 1-2, no walls) through the batch kernel at dt = 0.1: every
+    event's trajectory within 1e-5 of the oracle run with the same rounded
+    couplings, and positions that leave [-1, 1]."""
+    evs, qs = _events(SMALL)
+    M, K, seed, dt = 64, 40, 21, 0.1
+    ds = sbt.DeviceBatchSolver(qs, "asb", prec,
+                               sbt.solve_params(agents=M, steps=K, seed=seed, dt=dt),
+                               want_agent_energy=True, want_agent_state=True)
+    ds.run()
+    r = ds.result()
+    beyond = 0.0
+    for e, q in enumerate(qs):
+        b, isg, ref = _oracle_run(q, prec, "asb", M, K, seed, e, dt=dt)
+        x = r["agent_x"][e]
+        err = np.linalg.norm(x - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
+        assert np.all(err <= 1e-5), (e, err.max())
+        beyond = max(beyond, np.abs(ref.x).max())
+        e_or = oenergy.qubo_energy(q.a, b, r["agent_T"][e])
+        assert np.allclose(r["agent_energy"][e], e_or, rtol=1e-12, atol=1e-9)
+    assert beyond > 1.0
 
 
 def test_batch_ragged_agents_and_event_sizes():

@@ -177,9 +177,10 @@ def test_edge_shapes_random_qubo(n, M, K, kernel):
     q = sbt.Qubo(n, a, b.indptr.astype(np.int64), b.indices.astype(np.int32), b.data.copy(),
                  np.zeros((n, 3), np.int64))
     isg = oising.from_qubo(a, b)
-    for mode in ("bsb", "dsb"):
-        r = sbt.solve(q, mode, agents=M, steps=K, seed=4, kernel=kernel, want_state=True)
-        ref = osb.run(isg.J, isg.h, isg.c0, mode, M, K, seed=4)
+    for mode in ("bsb", "dsb", "asb"):
+        dt = 0.1 if mode == "asb" else 1.0           # aSB: explicit steps of a cubic force
+        r = sbt.solve(q, mode, agents=M, steps=K, dt=dt, seed=4, kernel=kernel, want_state=True)
+        ref = osb.run(isg.J, isg.h, isg.c0, mode, M, K, dt=dt, seed=4)
         assert np.allclose(r["x"], ref.x, rtol=0, atol=1e-5)
         assert np.allclose(r["y"], ref.y, rtol=0, atol=1e-5)
         e_or = oenergy.qubo_energy(a, b, (r["x"] >= 0).astype(np.int8))

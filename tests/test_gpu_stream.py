@@ -120,7 +120,8 @@ def test_asb_trajectory_matches_oracle(prec, M):
     ev, q, b, isg = _event(tg.plain_spec(), 100)
     J = oquant.fp8_rows(isg.J)[0] if prec == "fp8" else isg.J
     K, dt, seed = 20, 0.1, 11
-    r = sbt.solve(q, "asb", agents=M, steps=K, dt=dt, seed=seed, precision=prec, want_state=True)
+    r = sbt.solve(q, "asb", agents=M, steps=K, dt=dt, seed=seed, precision=prec, kernel="stream",
+                  want_state=True)
     assert r["kernel"] == "stream"
     ref = osb.run(J, isg.h, isg.c0, "asb", M, K, dt=dt, seed=seed)
     err = np.linalg.norm(r["x"] - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
@@ -130,15 +131,18 @@ def test_asb_trajectory_matches_oracle(prec, M):
     assert np.all(yerr <= 1e-5), yerr.max()
 
 
-def test_asb_energies_and_unsupported_paths():
+def test_asb_energies_and_every_kernel():
+    """aSB energies are the FP64 QUBO objective of the returned spins; the
+    resident kernel runs the same steps bit for bit."""
     ev, q, b, isg = _event(tg.plain_spec(), 101)
-    r = sbt.solve(q, "asb", agents=64, steps=300, dt=0.1, seed=2, want_state=True)
+    r = sbt.solve(q, "asb", agents=64, steps=300, dt=0.1, seed=2, kernel="stream", want_state=True)
     T = (r["x"] >= 0).astype(np.int8)
     e_or = oenergy.qubo_energy(q.a, b, T)
     assert np.all(np.abs(r["agent_energy"] - e_or) <= 1e-9 * np.maximum(1.0, np.abs(e_or)))
+    rr = sbt.solve(q, "asb", agents=64, steps=300, dt=0.1, seed=2, kernel="resident",
+                   want_state=True)
+    assert r["kernel"] == "stream" and rr["kernel"] == "resident"
+    assert np.array_equal(rr["x"], r["x"]) and np.array_equal(rr["y"], r["y"])
     with pytest.raises(sbt.SbtError) as e:
-        sbt.solve(q, "asb", agents=8, steps=10, kernel="resident")
-    assert e.value.code == _lib.SBT_EUNSUPPORTED
-    with pytest.raises(sbt.SbtError) as e:
-        sbt.solve_batch([q], "asb", agents=8, steps=10)
+        sbt.solve(q, "asb", agents=8, steps=10, precision="fp8", kernel="resident")
     assert e.value.code == _lib.SBT_EUNSUPPORTED
