@@ -12,6 +12,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -45,25 +46,28 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every source and link the shared library; returns its path."""
+    """Compile every source and link the shared library; returns its path.
+    Sources compile in parallel (the kernel files take minutes each)."""
     hipcc = shutil.which("hipcc") or os.path.join(ROCM, "bin", "hipcc")
     gxx = shutil.which("g++") or "g++"
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []  # (command, object)
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([gxx, *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append(([gxx, *HOST_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in RUNTIME_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([gxx, *HOST_FLAGS, "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-c",
-              os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append(([gxx, *HOST_FLAGS, "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-c",
+                      os.path.join(CSRC, src), "-o", obj], obj))
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc, *HIP_FLAGS, *HIP_EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o",
-              obj], verbose)
-        objs.append(obj)
+        jobs.append(([hipcc, *HIP_FLAGS, *HIP_EXTRA_FLAGS.get(src, []), "-c",
+                      os.path.join(CSRC, src), "-o", obj], obj))
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        for f in [pool.submit(_run, cmd, verbose) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB_PATH + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
           f"-L{ROCM}/lib", "-lamdhip64", "-pthread", f"-Wl,-rpath,{ROCM}/lib"], verbose)

@@ -159,8 +159,8 @@ __device__ __forceinline__ void for_slots(F &&f) {
 template <int MODE, int JP>
 __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
     extern __shared__ __align__(16) unsigned char smem[];
-    float *xs = reinterpret_cast<float *>(smem);                     // [2][kBatchSlots]
-    double *red = reinterpret_cast<double *>(xs + 2 * kBatchSlots);  // [16][64]
+    float *xs = reinterpret_cast<float *>(smem);                     // [2][kBatchStride]
+    double *red = reinterpret_cast<double *>(xs + 2 * kBatchStride); // [16][64]
     int *item_s = reinterpret_cast<int *>(red + 16 * 64);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 
@@ -179,7 +179,13 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
         const bool agent_ok = agent < B.M;
 
         float xr[kS], yr[kS], hr[kS];
-        int spin[kS];
+        // LDS word each slot's position is stored to: i * A + a for spin i,
+        // a pad word past the slots for a lane without a spin
+        uint32_t wr[kS];
+        auto spin_of = [&](int S) __attribute__((always_inline)) -> int {
+            const uint32_t w = opaque(wr[S]);
+            return w < static_cast<uint32_t>(kBatchSlots) ? static_cast<int>(w >> lgA) : -1;
+        };
         uint32_t cp0[kCap[0]], cp1[kCap[1]], cp2[kCap[2]], cp3[kCap[3]], cp4[kCap[4]],
             cp5[kCap[5]], cp6[kCap[6]], cp7[kCap[7]], cp8[kCap[8]];
         auto cps = [&](auto sc) __attribute__((always_inline)) -> uint32_t * {
@@ -202,7 +208,9 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             const int j = S * kB + t;
             const int q = j >> lgA;
             const int i = (q < n && agent_ok) ? B.perm[E.row_off + q] : -1;
-            spin[S] = i;
+            // a lane without a spin in an active slot updates a zero
+            // oscillator into its own pad word, so steps need no branches
+            wr[S] = i >= 0 ? static_cast<uint32_t>(i * A + a) : static_cast<uint32_t>(kBatchSlots + lane);
             xr[S] = yr[S] = hr[S] = 0.0f;
 #pragma unroll
             for (int c = 0; c < CAP; ++c) cp[c] = 0;
@@ -232,6 +240,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) act_w |= __shfl_xor(act_w, off, 64);
         act_w = __builtin_amdgcn_readfirstlane(act_w);
+        const int n_act = 32 - __builtin_clz(act_w | 1);  // active slots form a prefix
         __syncthreads();
 
         const float c0 = B.c0[e];
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             double v = 0.0;
             for_slots([&](auto sc) __attribute__((always_inline)) {
                 constexpr int S = decltype(sc)::value;
-                const int i = static_cast<int>(opaque(static_cast<uint32_t>(spin[S])));
+                const int i = spin_of(S);
                 if (i >= 0 && xr[S] >= 0.0f) {
                     double er = B.a[E.row_off + i];
                     const int p0 = B.row_ptr[E.rp_off + i], p1 = B.row_ptr[E.rp_off + i + 1];
@@ -274,110 +283,137 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             return tot;
         };
 
-        auto step = [&](auto bufc, int k) __attribute__((always_inline)) {
-            constexpr int BUF = decltype(bufc)::value;
-            const unsigned char *xc = smem + BUF * kBatchSlots * 4;
-            float *xn = xs + (BUF ^ 1) * kBatchSlots;
-            const float g = B.sched[k];
-            float acc[kS];
-            for_slots([&](auto sc) __attribute__((always_inline)) { acc[decltype(sc)::value] = hr[decltype(sc)::value]; });
-            // slots 1..: fixed capacity; their gathers are issued after slot 0
-            // has been summed, which bounds the registers in flight
-            float v1[kCap[1]], v2[kCap[2]], v3[kCap[3]], v4[kCap[4]], v5[kCap[5]], v6[kCap[6]],
-                v7[kCap[7]], v8[kCap[8]];
-            auto vs = [&](auto sc) __attribute__((always_inline)) -> float * {
-                constexpr int S = decltype(sc)::value;
-                if constexpr (S == 1) return v1;
-                else if constexpr (S == 2) return v2;
-                else if constexpr (S == 3) return v3;
-                else if constexpr (S == 4) return v4;
-                else if constexpr (S == 5) return v5;
-                else if constexpr (S == 6) return v6;
-                else if constexpr (S == 7) return v7;
-                else return v8;
-            };
-            // slot 0: as many gathers as the wave's longest row needs
-            auto slot0 = [&](auto cc) __attribute__((always_inline)) {
-                constexpr int C = decltype(cc)::value;
-                float v0[C];
-                uint32_t w0[C];
+        // The step loop, specialised per wave on its active slots (NA, a
+        // prefix) and slot 0's gather count (C0), chosen once per item: a
+        // step runs straight through -- gathers, FMAs in CSR order, update,
+        // LDS store, barrier -- with rows longer than a slot's capacity
+        // (rare) continuing from global memory out of line.  Every variant
+        // meets the same barriers.
+        auto run = [&](auto nac, auto c0c) __attribute__((always_inline)) {
+            constexpr int NA = decltype(nac)::value;
+            constexpr int C0 = decltype(c0c)::value;
+            auto step = [&](auto bufc, int k) __attribute__((always_inline)) {
+                constexpr int BUF = decltype(bufc)::value;
+                const unsigned char *xc = smem + BUF * kBatchStride * 4;
+                float *xn = xs + (BUF ^ 1) * kBatchStride;
+                const float g = B.sched[k];
+                float acc[kS];
+                for_slots([&](auto sc) __attribute__((always_inline)) {
+                    constexpr int S = decltype(sc)::value;
+                    if constexpr (S < NA) acc[S] = hr[S];
+                });
+                // slot 0 first; the other slots' gathers are issued after
+                // slot 0 has been summed, which bounds the registers in flight
+                {
+                    float v0[C0];
+                    uint32_t w0[C0];
 #pragma unroll
-                for (int c = 0; c < C; ++c) w0[c] = opaque(cp0[c]);
+                    for (int c = 0; c < C0; ++c) w0[c] = opaque(cp0[c]);
 #pragma unroll
-                for (int c = 0; c < C; ++c) v0[c] = lds_at(xc, w0[c]);
+                    for (int c = 0; c < C0; ++c) v0[c] = lds_at(xc, w0[c]);
 #pragma unroll
-                for (int c = 0; c < C; ++c) acc[0] = __builtin_fmaf(packed_j<JP>(w0[c]), v0[c], acc[0]);
-            };
-            if (cap0 <= 4)
-                slot0(std::integral_constant<int, 4>{});
-            else if (cap0 <= 8)
-                slot0(std::integral_constant<int, 8>{});
-            else
-                slot0(std::integral_constant<int, kCap[0]>{});
-            for_slots([&](auto sc) __attribute__((always_inline)) {
-                constexpr int S = decltype(sc)::value;
-                if constexpr (S > 0) {
-                    if (act_w & (1 << S)) {
+                    for (int c = 0; c < C0; ++c) acc[0] = __builtin_fmaf(packed_j<JP>(w0[c]), v0[c], acc[0]);
+                }
+                float v1[kCap[1]], v2[kCap[2]], v3[kCap[3]], v4[kCap[4]], v5[kCap[5]], v6[kCap[6]],
+                    v7[kCap[7]], v8[kCap[8]];
+                auto vs = [&](auto sc) __attribute__((always_inline)) -> float * {
+                    constexpr int S = decltype(sc)::value;
+                    if constexpr (S == 1) return v1;
+                    else if constexpr (S == 2) return v2;
+                    else if constexpr (S == 3) return v3;
+                    else if constexpr (S == 4) return v4;
+                    else if constexpr (S == 5) return v5;
+                    else if constexpr (S == 6) return v6;
+                    else if constexpr (S == 7) return v7;
+                    else return v8;
+                };
+                for_slots([&](auto sc) __attribute__((always_inline)) {
+                    constexpr int S = decltype(sc)::value;
+                    if constexpr (S > 0 && S < NA) {
                         float *v = vs(sc);
                         const uint32_t *cp = cps(sc);
 #pragma unroll
                         for (int c = 0; c < kCap[S]; ++c) v[c] = lds_at(xc, opaque(cp[c]));
                     }
-                }
-            });
-            for_slots([&](auto sc) __attribute__((always_inline)) {
-                constexpr int S = decltype(sc)::value;
-                if constexpr (S > 0) {
-                    if (act_w & (1 << S)) {
+                });
+                for_slots([&](auto sc) __attribute__((always_inline)) {
+                    constexpr int S = decltype(sc)::value;
+                    if constexpr (S > 0 && S < NA) {
                         const float *v = vs(sc);
                         const uint32_t *cp = cps(sc);
 #pragma unroll
                         for (int c = 0; c < kCap[S]; ++c)
                             acc[S] = __builtin_fmaf(packed_j<JP>(opaque(cp[c])), v[c], acc[S]);
                     }
+                });
+                if (__builtin_expect(any_tail, 0)) {
+                    const float *xcf = reinterpret_cast<const float *>(xc);
+                    for_slots([&](auto sc) __attribute__((always_inline)) {
+                        constexpr int S = decltype(sc)::value;
+                        if constexpr (S < NA) {
+                            const int i = spin_of(S);
+                            if (i >= 0) {
+                                const int p1 = B.row_ptr[E.rp_off + i + 1];
+                                for (int p = B.row_ptr[E.rp_off + i] + kCap[S]; p < p1; ++p)
+                                    acc[S] = __builtin_fmaf(j16_to_f32<JP>(B.J16[E.nz_off + p]),
+                                                            xcf[B.col[E.nz_off + p] * A + a], acc[S]);
+                            }
+                        }
+                    });
                 }
-            });
-            if (any_tail) {
-                const float *xcf = reinterpret_cast<const float *>(xc);
                 for_slots([&](auto sc) __attribute__((always_inline)) {
                     constexpr int S = decltype(sc)::value;
-                    const int i = static_cast<int>(opaque(static_cast<uint32_t>(spin[S])));
-                    if (i >= 0) {
-                        const int p1 = B.row_ptr[E.rp_off + i + 1];
-                        for (int p = B.row_ptr[E.rp_off + i] + kCap[S]; p < p1; ++p)
-                            acc[S] = __builtin_fmaf(j16_to_f32<JP>(B.J16[E.nz_off + p]),
-                                                    xcf[B.col[E.nz_off + p] * A + a], acc[S]);
+                    if constexpr (S < NA) {
+                        sb_step<MODE>(xr[S], yr[S], acc[S], c0, g, dt, dta0);
+                        xn[opaque(wr[S])] = shared_value<MODE>(xr[S]);
                     }
                 });
-            }
-            for_slots([&](auto sc) __attribute__((always_inline)) {
-                constexpr int S = decltype(sc)::value;
-                if (spin[S] >= 0) {
-                    sb_step<MODE>(xr[S], yr[S], acc[S], c0, g, dt, dta0);
-                    const uint32_t w = opaque(static_cast<uint32_t>(spin[S]));
-                    xn[static_cast<int>(w) * A + a] = shared_value<MODE>(xr[S]);
+                __syncthreads();
+            };
+            // steps in runs between checkpoints; the buffer read at step k is k & 1
+            int k = 0;
+            while (k < B.K) {
+                const int kend =
+                    B.ckpt_every > 0 ? min(B.K, k - k % B.ckpt_every + B.ckpt_every) : B.K;
+                if (k & 1) step(std::integral_constant<int, 1>{}, k++);
+                for (; k + 1 < kend; k += 2) {
+                    step(std::integral_constant<int, 0>{}, k);
+                    step(std::integral_constant<int, 1>{}, k + 1);
                 }
-            });
-            __syncthreads();
-            if (B.ckpt_every > 0 && (k + 1) % B.ckpt_every == 0) {
-                const double en = agent_energy(xn);
-                if (t < A && agent0 + t < B.M)
-                    B.etrace[(static_cast<size_t>(e) * B.n_ckpt + ck) * B.M + agent0 + t] = en;
-                ++ck;
+                if (k < kend) step(std::integral_constant<int, 0>{}, k++);
+                if (B.ckpt_every > 0 && k % B.ckpt_every == 0) {
+                    const double en = agent_energy(xs + (k & 1) * kBatchStride);
+                    if (t < A && agent0 + t < B.M)
+                        B.etrace[(static_cast<size_t>(e) * B.n_ckpt + ck) * B.M + agent0 + t] = en;
+                    ++ck;
+                }
             }
         };
-        int k = 0;
-        for (; k + 1 < B.K; k += 2) {
-            step(std::integral_constant<int, 0>{}, k);
-            step(std::integral_constant<int, 1>{}, k + 1);
+        auto with_c0 = [&](auto nac) __attribute__((always_inline)) {
+            if (cap0 <= 4)
+                run(nac, std::integral_constant<int, 4>{});
+            else if (cap0 <= 8)
+                run(nac, std::integral_constant<int, 8>{});
+            else
+                run(nac, std::integral_constant<int, kCap[0]>{});
+        };
+        switch (n_act) {
+            case 1: with_c0(std::integral_constant<int, 1>{}); break;
+            case 2: with_c0(std::integral_constant<int, 2>{}); break;
+            case 3: with_c0(std::integral_constant<int, 3>{}); break;
+            case 4: with_c0(std::integral_constant<int, 4>{}); break;
+            case 5: with_c0(std::integral_constant<int, 5>{}); break;
+            case 6: with_c0(std::integral_constant<int, 6>{}); break;
+            case 7: with_c0(std::integral_constant<int, 7>{}); break;
+            case 8: with_c0(std::integral_constant<int, 8>{}); break;
+            default: with_c0(std::integral_constant<int, kS>{}); break;
         }
-        if (k < B.K) step(std::integral_constant<int, 0>{}, k);
-        const float *xfin = xs + (B.K & 1) * kBatchSlots;
+        const float *xfin = xs + (B.K & 1) * kBatchStride;
         const double en = agent_energy(xfin);
         if (t < A && agent0 + t < B.M) B.energy[static_cast<size_t>(e) * B.M + agent0 + t] = en;
         for_slots([&](auto sc) __attribute__((always_inline)) {
             constexpr int S = decltype(sc)::value;
-            const int i = spin[S];
+            const int i = spin_of(S);
             if (i >= 0) {
                 const size_t o = (static_cast<size_t>(E.row_off) + i) * B.M + agent;
                 B.T[o] = xr[S] >= 0.0f ? 1 : 0;
@@ -450,7 +486,7 @@ hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream
     batch_reset<<<1, 1, 0, st>>>(B.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = sizeof(float) * 2 * kBatchSlots + sizeof(double) * 16 * 64 + 16;
+    const size_t lds = sizeof(float) * 2 * kBatchStride + sizeof(double) * 16 * 64 + 16;
     const dim3 grid(B.grid), block(kB);
     if (mode == kDSB)
         return jprec == kJFp16 ? launch_with_lds(sb_batch<kDSB, kJFp16>, grid, block, lds, st, B)
