@@ -243,3 +243,50 @@ def test_c0_scan_host_entry_point():
     assert s["energy"][2] == one["energy"][0]
     with pytest.raises(sbt.SbtError):
         sbt.c0_scan(q, "dsb", [1.0, 0.0], "fp16", agents=8, steps=10)
+
+
+def test_batch_rows_past_slot_capacity_match_oracle():
+    """Events with hub rows of 40 couplings (past every slot's register
+    capacity: the out-of-line tail) and isolated spins, batched with plain
+    events: trajectories within 1e-5 of the oracle with FP16 couplings.  Eight
+    steps: FP32 rounding of 40-term sums stays far below the tolerance there
+    (over 40 steps the dynamics grow it to ~3e-5), while a coupling dropped
+    or counted twice moves the state by ~1e-2."""
+    rng = np.random.default_rng(11)
+    qs = []
+    for n in (300, 1200, 4000):
+        rows, cols, vals, pairs = [], [], [], set()
+        for i in range(4, n - 1):
+            if rng.random() < 0.7:
+                j = int(rng.integers(4, n))
+                if j != i:
+                    pairs.add((min(i, j), max(i, j)))
+        for h in rng.choice(np.arange(4, n), 3, replace=False):
+            for j in rng.choice(np.arange(4, n), 40, replace=False):
+                if j != h:
+                    pairs.add((min(h, j), max(h, j)))
+        for i, j in sorted(pairs):
+            w = 1.0 if rng.random() < 0.3 else -rng.uniform(0.2, 1.0)
+            rows += [i, j]
+            cols += [j, i]
+            vals += [w, w]
+        b = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+        b.sort_indices()
+        qs.append(sbt.Qubo(n, rng.uniform(0, 0.7, n), b.indptr.astype(np.int64),
+                           b.indices.astype(np.int32), b.data.copy(), np.zeros((n, 3), np.int64)))
+    qs += _events(SMALL[:2])[1]
+    assert max(int(np.diff(q.row_ptr).max()) for q in qs) > 16
+    M, K, seed = 48, 8, 5
+    ds = sbt.DeviceBatchSolver(qs, "bsb", "fp16", sbt.solve_params(agents=M, steps=K, seed=seed,
+                                                                   energy_every=3),
+                               want_agent_energy=True, want_agent_state=True)
+    ds.run()
+    r = ds.result()
+    for e, q in enumerate(qs):
+        b, isg, ref = _oracle_run(q, "fp16", "bsb", M, K, seed, e)
+        x = r["agent_x"][e]
+        err = np.linalg.norm(x - ref.x, axis=0) / np.maximum(np.linalg.norm(ref.x, axis=0), 1e-30)
+        close = ref.wall_margin < 1e-6
+        assert np.all((err <= 1e-5) | close), (e, err.max())
+        e_or = oenergy.qubo_energy(q.a, b, r["agent_T"][e])
+        assert np.allclose(r["agent_energy"][e], e_or, rtol=1e-12, atol=1e-9)

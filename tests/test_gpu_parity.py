@@ -201,3 +201,56 @@ def test_precision_size_event_kernels_agree():
     T = (rr["x"][:, cols] >= 0).astype(np.int8)
     e_or = oenergy.qubo_energy(q.a, b, T)
     assert np.allclose(rr["agent_energy"][cols], e_or, rtol=1e-12, atol=1e-9)
+
+
+def _hub_qubo(n, seed, hubs=3, hub_degree=40, isolated=5):
+    """Random symmetric QUBO with short rows (0-3 couplings), a few hub rows
+    far past any register capacity, and some isolated spins."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    pairs = set()
+    for i in range(isolated, n - 1):
+        for _ in range(int(rng.integers(0, 2))):
+            j = int(rng.integers(isolated, n))
+            if j != i:
+                pairs.add((min(i, j), max(i, j)))
+    for h in rng.choice(np.arange(isolated, n), hubs, replace=False):
+        for j in rng.choice(np.arange(isolated, n), hub_degree, replace=False):
+            if j != h:
+                pairs.add((min(h, j), max(h, j)))
+    for i, j in sorted(pairs):
+        w = 1.0 if rng.random() < 0.3 else -rng.uniform(0.2, 1.0)
+        rows += [i, j]
+        cols += [j, i]
+        vals += [w, w]
+    b = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    b.sort_indices()
+    a = rng.uniform(0, 0.7, n)
+    q = sbt.Qubo(n, a, b.indptr.astype(np.int64), b.indices.astype(np.int32), b.data.copy(),
+                 np.zeros((n, 3), np.int64))
+    return q, a, b
+
+
+@pytest.mark.parametrize("n,tpb", [(700, 0), (1500, 0), (3000, 0), (1500, 512), (1500, 256),
+                                   (200, 256)])
+def test_resident_shapes_with_long_rows_and_checkpoints(n, tpb):
+    """The register-row kernel across its shapes (1, 2, 4 and 8 spins per
+    thread, via the workgroup-size hint), with hub rows longer than any
+    register capacity (the out-of-line tail), isolated spins, lanes without
+    a spin, and checkpoints every 7 steps (runs that start on odd steps):
+    bit-identical to the streaming kernel, energies equal to the oracle's."""
+    q, a, b = _hub_qubo(n, n + tpb)
+    M, K = 70, 61
+    for mode in ("bsb", "dsb", "asb"):
+        dt = 0.1 if mode == "asb" else 1.0
+        kw = dict(agents=M, steps=K, dt=dt, seed=3, energy_every=7, want_state=True,
+                  want_trace=True)
+        rr = sbt.solve(q, mode, kernel="resident", tpb=tpb, **kw)
+        rs = sbt.solve(q, mode, kernel="stream", **kw)
+        assert rr["kernel"] == "resident" and rs["kernel"] == "stream"
+        assert np.array_equal(rr["x"], rs["x"]), mode
+        assert np.array_equal(rr["y"], rs["y"]), mode
+        # both are FP64 sums of the same states, in different orders
+        assert np.allclose(rr["trace"], rs["trace"], rtol=1e-12, atol=1e-9), mode
+        e_or = oenergy.qubo_energy(a, b, (rr["x"] >= 0).astype(np.int8))
+        assert np.allclose(rr["agent_energy"], e_or, rtol=1e-12, atol=1e-9)
