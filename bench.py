@@ -338,38 +338,58 @@ def measured_traffic(profile_name):
     return rec["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(q, n_target_s=12.0):
-    """The FP64 oracle integrator on the host, both forms, all 256 agents,
-    for a bounded number of steps; returned as spin-updates/s."""
-    import numpy as np
+def _sized_run(run_one, target_s):
+    """Grow a bSB run until it takes a second, then time bSB + dSB at the
+    step count that fills about target_s; returns (steps, seconds)."""
+    k = 25
+    while True:
+        t0 = time.perf_counter()
+        run_one("bsb", k)
+        dt = time.perf_counter() - t0
+        if dt >= 1.0:
+            break
+        k *= 4
+    k = max(20, int(k * target_s / (2.0 * dt)))
+    t0 = time.perf_counter()
+    for mode in ("bsb", "dsb"):
+        run_one(mode, k)
+    return k, time.perf_counter() - t0
+
+
+def cpu_baseline(q, target_s=8.0):
+    """The FP64 oracle on the host, both forms, all 256 agents, for a bounded
+    number of steps, as spin-updates/s: the C oracle with the agents spread
+    over every host thread OpenMP is given (the reported value), and the
+    NumPy/SciPy oracle on one thread (reported beside it)."""
     import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
 
     from oracle import ising as oising
     from oracle import sb as osb
+    from oracle import sb_c
 
+    if not os.path.exists(sb_c.LIB):
+        sb_c.build()
     b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
     isg = oising.from_qubo(q.a, b)
+    used = [0]
+
+    def run_c(mode, k):
+        used[0] = sb_c.run(isg.J, isg.h, isg.c0, mode, AGENTS, k, seed=SOLVER_SEED)[2]
+
+    k2, dt2 = _sized_run(run_c, target_s)
     with threadpool_limits(limits=1):
-        # size the sample: grow a bSB run until it takes a second, then
-        # scale to the target for both forms
-        k = 25
-        while True:
-            t0 = time.perf_counter()
-            osb.run(isg.J, isg.h, isg.c0, "bsb", AGENTS, k, seed=SOLVER_SEED)
-            dt = time.perf_counter() - t0
-            if dt >= 1.0:
-                break
-            k *= 4
-        k = max(20, int(k * n_target_s / (2.0 * dt)))
-        t0 = time.perf_counter()
-        for mode in ("bsb", "dsb"):
-            osb.run(isg.J, isg.h, isg.c0, mode, AGENTS, k, seed=SOLVER_SEED)
-        dt = time.perf_counter() - t0
-    ups = 2.0 * q.n * AGENTS * k / dt
-    return {"value": ups, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle FP64 bSB+dSB, {AGENTS} agents x {k} steps on the same event "
-                      f"({dt:.1f} s, one thread)"}
+        k1, dt1 = _sized_run(lambda mode, k: osb.run(isg.J, isg.h, isg.c0, mode, AGENTS, k,
+                                                     seed=SOLVER_SEED), target_s)
+    ups2 = 2.0 * q.n * AGENTS * k2 / dt2
+    ups1 = 2.0 * q.n * AGENTS * k1 / dt1
+    return {"value": ups2, "unit": "spin-updates/s", "cores": used[0], "kind": "oracle",
+            "sample": f"C FP64 oracle (oracle/sb_omp.c, OpenMP over agents), bSB+dSB, {AGENTS} "
+                      f"agents x {k2} steps on the same event ({dt2:.1f} s, {used[0]} threads)",
+            "python_oracle_one_thread": {
+                "value": ups1, "unit": "spin-updates/s", "cores": 1,
+                "sample": f"NumPy/SciPy FP64 oracle, bSB+dSB, {AGENTS} agents x {k1} steps "
+                          f"({dt1:.1f} s)"}}
 
 
 def main():
