@@ -290,3 +290,37 @@ def test_batch_rows_past_slot_capacity_match_oracle():
         assert np.all((err <= 1e-5) | close), (e, err.max())
         e_or = oenergy.qubo_energy(q.a, b, r["agent_T"][e])
         assert np.allclose(r["agent_energy"][e], e_or, rtol=1e-12, atol=1e-9)
+
+
+def test_batching_workload_all_events_quality_equals_plain_fp32():
+    """The whole batching workload (512 events, dSB, 128 agents x 3000
+    steps): one FP16 batch and one BF16 batch against the plain FP32 solver
+    run one event at a time.  Over all events the doublet efficiency and
+    purity (pooled TP / FN / FP) agree within 0.01, every event's best
+    energy is within 0.5% of the FP32 one, and every returned energy is the
+    FP64 objective of the returned spins."""
+    evs, qs = _events(tg.batching_specs())
+    assert len(qs) == 512
+    M, K = 128, 3000
+    counts = {}
+    fp32 = [sbt.solve(q, "dsb", agents=M, steps=K, seed=0, event=e) for e, q in enumerate(qs)]
+    Ts = {"fp32": [r["T"] for r in fp32]}
+    E32 = np.array([r["energy"] for r in fp32])
+    for prec in ("fp16", "bf16"):
+        r = sbt.solve_batch(qs, "dsb", prec, agents=M, steps=K, seed=0)
+        Ts[prec] = r["T"]
+        assert np.all(r["energy"] <= E32 + 0.005 * np.abs(E32)), prec
+        assert np.all(E32 <= r["energy"] + 0.005 * np.abs(r["energy"])), prec
+        for e in (0, 17, 511):
+            b = sp.csr_matrix((qs[e].b, qs[e].col, qs[e].row_ptr), shape=(qs[e].n, qs[e].n))
+            assert abs(oenergy.qubo_energy(qs[e].a, b, r["T"][e]) - r["energy"][e]) <= \
+                1e-9 * abs(r["energy"][e])
+    for form, T in Ts.items():
+        tp = fn = fp = 0
+        for ev, q, t in zip(evs, qs, T):
+            _, _, a, b_, c = otracks.evaluate(ev, q.trip_hits, t)
+            tp, fn, fp = tp + a, fn + b_, fp + c
+        counts[form] = (tp / (tp + fn), tp / (tp + fp))
+    for prec in ("fp16", "bf16"):
+        assert abs(counts[prec][0] - counts["fp32"][0]) <= 0.01, counts
+        assert abs(counts[prec][1] - counts["fp32"][1]) <= 0.01, counts
