@@ -61,9 +61,13 @@ __device__ __forceinline__ float lds_at(const unsigned char *base, uint32_t cp) 
 // Hides a loop-invariant register from the optimiser (an empty asm that
 // "modifies" it) so that values derived from it are recomputed where used
 // instead of being hoisted out of the step loop and kept live: the packed
-// couplings exist to save registers.  Emits no instruction.
+// couplings exist to save registers.  Emits no instruction.  `launder`
+// acts on the register in place (once per step on the loop-carried value:
+// no copy); `opaque` returns a laundered copy (for uses outside the loop).
+__device__ __forceinline__ void launder(uint32_t &v) { asm volatile("" : "+v"(v)); }
+
 __device__ __forceinline__ uint32_t opaque(uint32_t v) {
-    asm volatile("" : "+v"(v));
+    launder(v);
     return v;
 }
 
@@ -300,7 +304,14 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                 float acc[kS];
                 for_slots([&](auto sc) __attribute__((always_inline)) {
                     constexpr int S = decltype(sc)::value;
-                    if constexpr (S < NA) acc[S] = hr[S];
+                    if constexpr (S < NA) {
+                        acc[S] = hr[S];
+                        uint32_t *cp = cps(sc);
+                        constexpr int CAP = S == 0 ? C0 : kCap[S];
+#pragma unroll
+                        for (int c = 0; c < CAP; ++c) launder(cp[c]);
+                        launder(wr[S]);
+                    }
                 });
                 // slot 0 first; the other slots' gathers are issued after
                 // slot 0 has been summed, which bounds the registers in flight
@@ -308,7 +319,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                     float v0[C0];
                     uint32_t w0[C0];
 #pragma unroll
-                    for (int c = 0; c < C0; ++c) w0[c] = opaque(cp0[c]);
+                    for (int c = 0; c < C0; ++c) w0[c] = cp0[c];
 #pragma unroll
                     for (int c = 0; c < C0; ++c) v0[c] = lds_at(xc, w0[c]);
 #pragma unroll
@@ -333,7 +344,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                         float *v = vs(sc);
                         const uint32_t *cp = cps(sc);
 #pragma unroll
-                        for (int c = 0; c < kCap[S]; ++c) v[c] = lds_at(xc, opaque(cp[c]));
+                        for (int c = 0; c < kCap[S]; ++c) v[c] = lds_at(xc, cp[c]);
                     }
                 });
                 for_slots([&](auto sc) __attribute__((always_inline)) {
@@ -343,7 +354,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                         const uint32_t *cp = cps(sc);
 #pragma unroll
                         for (int c = 0; c < kCap[S]; ++c)
-                            acc[S] = __builtin_fmaf(packed_j<JP>(opaque(cp[c])), v[c], acc[S]);
+                            acc[S] = __builtin_fmaf(packed_j<JP>(cp[c]), v[c], acc[S]);
                     }
                 });
                 if (__builtin_expect(any_tail, 0)) {
@@ -365,7 +376,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                     constexpr int S = decltype(sc)::value;
                     if constexpr (S < NA) {
                         sb_step<MODE>(xr[S], yr[S], acc[S], c0, g, dt, dta0);
-                        xn[opaque(wr[S])] = shared_value<MODE>(xr[S]);
+                        xn[wr[S]] = shared_value<MODE>(xr[S]);
                     }
                 });
                 __syncthreads();
