@@ -125,6 +125,32 @@ __device__ __forceinline__ int wave_max_int(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// Exclusive prefix sum over the workgroup (thread order) of one int per
+// thread; `total` receives the sum over all threads.  `wsum` holds one int
+// per wave.  The workgroup size must be a multiple of 64, and every thread
+// must call it.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *wsum, int &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = static_cast<int>(blockDim.x) >> 6;
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int base = 0;
+    total = 0;
+    for (int w = 0; w < nw; ++w) {
+        const int s = wsum[w];
+        if (w < wave) base += s;
+        total += s;
+    }
+    __syncthreads();
+    return base + x - v;
+}
+
 // Deterministic sum over the workgroup of one double per thread (fixed
 // tree order); the result is valid in thread 0.  `red` holds one double
 // per wave.  Every thread of the workgroup must call it.

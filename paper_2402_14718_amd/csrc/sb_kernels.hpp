@@ -31,24 +31,41 @@ struct ResidentArgs {
 struct ResidentShape {
     int tpb;                     // threads per workgroup (register-row variant: any
                                  //   multiple of 64 up to 1024)
-    int spt;                     // spins per thread: 1, 2, 4, 8 (16 for the LDS-row variant)
+    int spt;                     // spins per thread: register-row 1, 2, 3, 4, 8; LDS-row a
+                                 //   power of two up to 16
     int rc;                      // > 0: register-row variant with this many couplings per
-                                 //   row in VGPRs (2, 4, 8); 0: LDS-row variant
+                                 //   row in VGPRs (2, 4, 8) for slot 0; 0: LDS-row variant
+    int rr;                      // register-row variant: couplings in VGPRs per row of the
+                                 //   other slots (rc, or 2)
     bool jlds;                   // LDS-row variant: J held in LDS
     size_t lds_bytes;
 };
 
-// Register-row variant: VGPR estimate of a thread holding spt spins with rc
-// couplings each (fit to the compiler's counts), the budget at a
-// workgroup size, and which (workgroup size, spt, rc) exist -- the host
-// picks a shape only among these.
-constexpr int reg_vgpr_estimate(int spt, int rc) { return 4 * spt * rc + 12 * spt + 40; }
+// Register-row variant: VGPR estimate of a thread holding spt spins, rc
+// couplings in registers for slot 0 and rr for each other slot (fit to the
+// compiler's counts), the budget at a workgroup size, and which shapes
+// exist -- the host picks a shape only among these.  Slot 0 holds the
+// longest rows, so when the same capacity for every slot does not fit, the
+// other slots get 2 (rows longer than a slot's capacity continue from
+// global memory).
+constexpr int reg_vgpr_estimate(int spt, int rc, int rr) {
+    return 4 * (rc + (spt - 1) * rr) + 12 * spt + 40;
+}
 constexpr int reg_vgpr_budget(int maxtpb) { return maxtpb >= 1024 ? 128 : (maxtpb >= 512 ? 256 : 512); }
-constexpr bool reg_variant_fits(int maxtpb, int spt, int rc) {
-    return !(spt > 4 && rc > 4) && reg_vgpr_estimate(spt, rc) <= reg_vgpr_budget(maxtpb);
+constexpr bool reg_fits(int maxtpb, int spt, int rc, int rr) {
+    return !(spt > 4 && rc > 4) && reg_vgpr_estimate(spt, rc, rr) <= reg_vgpr_budget(maxtpb);
+}
+// the shapes that are built: same capacity everywhere where it fits, else
+// (rc, 2) where that fits
+constexpr bool reg_variant_fits(int maxtpb, int spt, int rc, int rr) {
+    if (rr == rc) return reg_fits(maxtpb, spt, rc, rc);
+    return spt > 1 && rr == 2 && rc > 2 && !reg_fits(maxtpb, spt, rc, rc) &&
+           reg_fits(maxtpb, spt, rc, 2);
 }
 
 constexpr int kRegMaxN = 8192;   // register-row variant: largest n
+constexpr int kRegTailCap = 1792;  // register-row variant: couplings past the rows'
+                                   //   register capacity staged in LDS (14 KB)
 constexpr int kRegStride = kRegMaxN + 64;  // LDS position buffer: n words, then one pad
                                            //   word per lane of a wave
 

@@ -81,32 +81,39 @@ __device__ __forceinline__ void by_cap(int cap, F &&f) {
     }
 }
 
-template <int MODE, int MAXTPB, int SPT, int RC>
+// RC couplings of slot 0's row are held in registers, RR of every other
+// slot's (RR <= RC: slots past 0 hold the shorter rows).
+template <int MODE, int MAXTPB, int SPT, int RC, int RR>
 __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     float *xs = reinterpret_cast<float *>(smem);  // [2][kRegStride]
-    double *red = reinterpret_cast<double *>(xs + 2 * kRegStride);
+    double *red = reinterpret_cast<double *>(xs + 2 * kRegStride);  // [MAXTPB / 64]
+    // couplings past a row's register capacity: [kRegTailCap] columns, values
+    int *tcol = reinterpret_cast<int *>(red + MAXTPB / 64);
+    float *tJ = reinterpret_cast<float *>(tcol + kRegTailCap);
     const int n = A.n;
     const int t = threadIdx.x;
     const int m = blockIdx.x;
     const int M = A.M;
 
     float xr[SPT], yr[SPT], hr[SPT];
-    int spin[SPT], wr[SPT];
+    // LDS word each slot's position is stored to: the spin index, or a pad
+    // word past every spin for a lane without one
+    int wr[SPT];
     int cols[SPT][RC];
     float js[SPT][RC];
-    int tail0[SPT], tail1[SPT];
     int need0 = 0, need_rest = 0, rest = 0, tail = 0;
+    int tlen[SPT];  // couplings of the slot's row past its capacity
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
         const int j = s * static_cast<int>(blockDim.x) + t;
         const int i = j < n ? A.perm[j] : -1;
-        spin[s] = i;
         // a lane without a spin in this slot updates a zero oscillator and
         // stores it to its own pad word, so the step has no branches
         wr[s] = i >= 0 ? i : kRegMaxN + (t & 63);
         xr[s] = yr[s] = hr[s] = 0.0f;
-        tail0[s] = tail1[s] = 0;
+        tlen[s] = 0;
+        const int cap = s == 0 ? RC : RR;
 #pragma unroll
         for (int e = 0; e < RC; ++e) {
             cols[s][e] = 0;
@@ -120,20 +127,19 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
             const int p0 = A.row_ptr[i], p1 = A.row_ptr[i + 1];
 #pragma unroll
             for (int e = 0; e < RC; ++e) {
-                if (p0 + e < p1) {
+                if (e < cap && p0 + e < p1) {
                     cols[s][e] = A.col[p0 + e];
                     js[s][e] = A.J[p0 + e];
                 }
             }
-            tail0[s] = p0 + RC;
-            tail1[s] = p1;
             if (s == 0) {
                 need0 = p1 - p0;
             } else {
                 need_rest = max(need_rest, p1 - p0);
                 rest = 1;
             }
-            tail |= (p1 - p0 > RC) ? 1 : 0;
+            tail |= (p1 - p0 > cap) ? 1 : 0;
+            tlen[s] = max(0, p1 - p0 - cap);
             xs[i] = shared_value<MODE>(xr[s]);
         }
     }
@@ -141,6 +147,32 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
     const int cap_rest = wave_max_int(need_rest);
     const int any_rest = wave_max_int(rest);
     const int any_tail = wave_max_int(tail);
+    // Tails are staged in LDS once (offsets by a block scan), each slot
+    // keeping (offset << 12 | length) in one register; a kernel whose tails
+    // do not fit reads them from global memory instead.
+    int mine = 0;
+#pragma unroll
+    for (int s = 0; s < SPT; ++s) mine += tlen[s];
+    int total = 0;
+    const int before = block_exclusive_scan(mine, reinterpret_cast<int *>(red), total);
+    const bool lds_tails = total <= kRegTailCap;
+    int tpk[SPT];
+    {
+        int off = before;
+#pragma unroll
+        for (int s = 0; s < SPT; ++s) {
+            tpk[s] = (off << 12) | min(tlen[s], 4095);
+            if (lds_tails && tlen[s] > 0) {
+                const int i = wr[s];
+                const int p = A.row_ptr[i] + (s == 0 ? RC : RR);
+                for (int q = 0; q < tlen[s]; ++q) {
+                    tcol[off + q] = A.col[p + q];
+                    tJ[off + q] = A.J[p + q];
+                }
+            }
+            off += tlen[s];
+        }
+    }
     __syncthreads();
 
     const float c0 = static_cast<float>(A.scal[0]);
@@ -149,9 +181,9 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
     // The whole step loop, specialised per wave: C0 gathers for slot 0, CR
     // for every other slot (0: this wave holds no spin past slot 0).  The
     // choice is made once, so a step runs straight through: gathers, FMAs
-    // in CSR order, update, LDS store, barrier (rows longer than RC, rare,
-    // continue from global memory out of line).  Every variant meets the
-    // same barriers.
+    // in CSR order, update, LDS store, barrier (rows longer than their
+    // slot's capacity, rare, continue from global memory out of line).
+    // Every variant meets the same barriers.
     auto run = [&](auto c0c, auto crc) __attribute__((always_inline)) {
         constexpr int C0 = decltype(c0c)::value;
         constexpr int CR = decltype(crc)::value;
@@ -177,10 +209,19 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
                 for (int e = 0; e < C; ++e) acc[s] = __builtin_fmaf(js[s][e], v[s][e], acc[s]);
             }
             if (__builtin_expect(any_tail, 0)) {
+                if (lds_tails) {
 #pragma unroll
-                for (int s = 0; s < NS; ++s)
-                    for (int p = tail0[s]; p < tail1[s]; ++p)
-                        acc[s] = __builtin_fmaf(A.J[p], xc[A.col[p]], acc[s]);
+                    for (int s = 0; s < NS; ++s)
+                        for (int q = tpk[s] >> 12, q1 = q + (tpk[s] & 4095); q < q1; ++q)
+                            acc[s] = __builtin_fmaf(tJ[q], xc[tcol[q]], acc[s]);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        for (int p = wr[s] < n ? A.row_ptr[wr[s]] + (s == 0 ? RC : RR) : 0,
+                                 p1 = wr[s] < n ? A.row_ptr[wr[s] + 1] : 0;
+                             p < p1; ++p)
+                            acc[s] = __builtin_fmaf(A.J[p], xc[A.col[p]], acc[s]);
+                }
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -206,7 +247,7 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
                 double e = 0.0;
 #pragma unroll
                 for (int s = 0; s < SPT; ++s) {
-                    const int i = spin[s];
+                    const int i = wr[s] < n ? wr[s] : -1;
                     if (i >= 0 && xr[s] >= 0.0f) {
                         double er = A.a[i];
                         for (int p = A.row_ptr[i]; p < A.row_ptr[i + 1]; ++p) {
@@ -222,22 +263,22 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
             }
         }
     };
-    // rows past slot 0 are short: 2 gathers, else RC
+    // rows past slot 0 are short: 2 gathers, else RR
     by_cap<RC>(cap0, [&](auto c0c) __attribute__((always_inline)) {
         if constexpr (SPT == 1) {
             run(c0c, std::integral_constant<int, 0>{});
         } else {
             if (!any_rest)
                 run(c0c, std::integral_constant<int, 0>{});
-            else if (cap_rest <= 2)
+            else if (RR <= 2 || cap_rest <= 2)
                 run(c0c, std::integral_constant<int, 2>{});
             else
-                run(c0c, std::integral_constant<int, RC>{});
+                run(c0c, std::integral_constant<int, RR>{});
         }
     });
 #pragma unroll
     for (int s = 0; s < SPT; ++s) {
-        const int i = spin[s];
+        const int i = wr[s] < n ? wr[s] : -1;
         if (i >= 0) {
             const size_t o = static_cast<size_t>(i) * M + m;
             A.x[o] = xr[s];
@@ -251,26 +292,30 @@ hipError_t launch_row_order(int n, const int *row_ptr, int *perm, hipStream_t st
     return hipGetLastError();
 }
 
+template <int MODE, int MAXTPB, int SPT, int RC, int RR>
+static hipError_t launch_reg_shape(const ResidentArgs &A, const ResidentShape &S, hipStream_t st) {
+    if constexpr (reg_variant_fits(MAXTPB, SPT, RC, RR))
+        return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, RC, RR>, dim3(A.M), dim3(S.tpb),
+                               S.lds_bytes, st, A);
+    else
+        return hipErrorInvalidValue;
+}
+
+// only the shapes the host can pick are built
 template <int MODE, int MAXTPB, int SPT>
 static hipError_t launch_reg_rc(const ResidentArgs &A, const ResidentShape &S, hipStream_t st) {
-    const dim3 grid(A.M), block(S.tpb);
-    // only the shapes the host can pick are built
+    const bool split = S.rr != S.rc;
+    if (split && S.rr != 2) return hipErrorInvalidValue;
     switch (S.rc) {
-        case 2:
-            if constexpr (reg_variant_fits(MAXTPB, SPT, 2))
-                return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, 2>, grid, block, S.lds_bytes, st, A);
-            break;
+        case 2: return launch_reg_shape<MODE, MAXTPB, SPT, 2, 2>(A, S, st);
         case 4:
-            if constexpr (reg_variant_fits(MAXTPB, SPT, 4))
-                return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, 4>, grid, block, S.lds_bytes, st, A);
-            break;
+            return split ? launch_reg_shape<MODE, MAXTPB, SPT, 4, 2>(A, S, st)
+                         : launch_reg_shape<MODE, MAXTPB, SPT, 4, 4>(A, S, st);
         case 8:
-            if constexpr (reg_variant_fits(MAXTPB, SPT, 8))
-                return launch_with_lds(sb_resident_reg<MODE, MAXTPB, SPT, 8>, grid, block, S.lds_bytes, st, A);
-            break;
-        default: break;
+            return split ? launch_reg_shape<MODE, MAXTPB, SPT, 8, 2>(A, S, st)
+                         : launch_reg_shape<MODE, MAXTPB, SPT, 8, 8>(A, S, st);
+        default: return hipErrorInvalidValue;
     }
-    return hipErrorInvalidValue;
 }
 
 template <int MODE, int MAXTPB>
@@ -278,6 +323,7 @@ static hipError_t launch_reg_spt(const ResidentArgs &A, const ResidentShape &S, 
     switch (S.spt) {
         case 1: return launch_reg_rc<MODE, MAXTPB, 1>(A, S, st);
         case 2: return launch_reg_rc<MODE, MAXTPB, 2>(A, S, st);
+        case 3: return launch_reg_rc<MODE, MAXTPB, 3>(A, S, st);
         case 4: return launch_reg_rc<MODE, MAXTPB, 4>(A, S, st);
         case 8: return launch_reg_rc<MODE, MAXTPB, 8>(A, S, st);
         default: return hipErrorInvalidValue;

@@ -115,7 +115,7 @@ int device_lds_limit() {
 // register budget; otherwise the LDS-row variant while positions fit LDS.
 sbt::ResidentShape resident_shape(int32_t n, int64_t nnz, int32_t max_row, int tpb_hint,
                                   int lds_limit) {
-    sbt::ResidentShape S{0, 0, 0, false, 0};
+    sbt::ResidentShape S{0, 0, 0, 0, false, 0};
     auto pow2_at_least = [](int v) {
         int p = 1;
         while (p < v) p <<= 1;
@@ -125,20 +125,31 @@ sbt::ResidentShape resident_shape(int32_t n, int64_t nnz, int32_t max_row, int t
     // register-row variant: the fewest spins per thread whose workgroup
     // (a multiple of 64 threads) fits in 1024, or the hinted size
     if (n <= sbt::kRegMaxN) {
-        for (int spt = 1; spt <= 8; spt <<= 1) {
+        for (const int spt : {1, 2, 3, 4, 8}) {
             const int tpb = ((n + spt - 1) / spt + 63) / 64 * 64;
             const int cap_tpb = hinted ? tpb_hint : 1024;
             if (tpb > cap_tpb) continue;
             const int maxtpb = tpb <= 256 ? 256 : (tpb <= 512 ? 512 : 1024);
-            int rc = max_row <= 2 ? 2 : (max_row <= 4 ? 4 : 8);
-            while (rc > 2 && !sbt::reg_variant_fits(maxtpb, spt, rc)) rc >>= 1;
-            if (!sbt::reg_variant_fits(maxtpb, spt, rc)) continue;
+            int rc = max_row <= 2 ? 2 : (max_row <= 4 ? 4 : 8), rr = 0;
+            for (; rc >= 2; rc >>= 1) {
+                if (sbt::reg_variant_fits(maxtpb, spt, rc, rc)) {
+                    rr = rc;
+                    break;
+                }
+                if (sbt::reg_variant_fits(maxtpb, spt, rc, 2)) {
+                    rr = 2;
+                    break;
+                }
+            }
+            if (rr == 0) continue;
             const size_t lds =
-                sizeof(float) * 2 * sbt::kRegStride + sizeof(double) * (maxtpb / 64);
+                sizeof(float) * 2 * sbt::kRegStride + sizeof(double) * (maxtpb / 64) +
+                (sizeof(int) + sizeof(float)) * sbt::kRegTailCap;
             if (lds > static_cast<size_t>(lds_limit)) break;
             S.tpb = tpb;
             S.spt = spt;
             S.rc = rc;
+            S.rr = rr;
             S.lds_bytes = lds;
             return S;
         }

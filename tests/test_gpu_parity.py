@@ -231,15 +231,18 @@ def _hub_qubo(n, seed, hubs=3, hub_degree=40, isolated=5):
     return q, a, b
 
 
-@pytest.mark.parametrize("n,tpb", [(700, 0), (1500, 0), (3000, 0), (1500, 512), (1500, 256),
-                                   (200, 256)])
-def test_resident_shapes_with_long_rows_and_checkpoints(n, tpb):
-    """The register-row kernel across its shapes (1, 2, 4 and 8 spins per
-    thread, via the workgroup-size hint), with hub rows longer than any
-    register capacity (the out-of-line tail), isolated spins, lanes without
-    a spin, and checkpoints every 7 steps (runs that start on odd steps):
-    bit-identical to the streaming kernel, energies equal to the oracle's."""
-    q, a, b = _hub_qubo(n, n + tpb)
+@pytest.mark.parametrize("n,tpb,hubs", [(700, 0, 3), (1500, 0, 3), (3000, 0, 3), (3500, 0, 3),
+                                        (1500, 512, 3), (1500, 256, 3), (200, 256, 3),
+                                        (2000, 0, 80)])
+def test_resident_shapes_with_long_rows_and_checkpoints(n, tpb, hubs):
+    """The register-row kernel across its shapes (1, 2, 3, 4 and 8 spins per
+    thread, via the workgroup-size hint; slot 0's capacity above the other
+    slots'), with hub rows longer than any register capacity (their tails
+    staged in LDS, or read from global memory when 80 hubs overflow the LDS
+    tail area), isolated spins, lanes without a spin, and checkpoints every
+    7 steps (runs that start on odd steps): bit-identical to the streaming
+    kernel, energies equal to the oracle's."""
+    q, a, b = _hub_qubo(n, n + tpb, hubs=hubs)
     M, K = 70, 61
     for mode in ("bsb", "dsb", "asb"):
         dt = 0.1 if mode == "asb" else 1.0
