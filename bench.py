@@ -154,7 +154,7 @@ def precision_form(sbt, tg, torch, np):
     return out
 
 
-def batched_form(sbt, tg, torch, np, with_fp32=True):
+def batched_form(sbt, tg, torch, np, with_fp32=True, gpu_build=True):
     """512 events of 20-1000 particles, dSB, 128 agents x 3000 steps: one
     persistent batched kernel (FP16 / BF16 couplings) against plain FP32
     solving the events one at a time.  Per-event energies are compared with
@@ -166,15 +166,19 @@ def batched_form(sbt, tg, torch, np, with_fp32=True):
     hits = [tg.generate(s, seed).hits_struct() for s, seed in specs]
     # QUBO construction of every event on the GPU (wall time, downloads
     # included); the host builder timed on a sample of events, whose
-    # structure must match
-    t0 = time.perf_counter()
-    built = [sbt.build_qubo_gpu(h) for h in hits]
-    gpu_build_s = time.perf_counter() - t0
-    qs = [q for q, _ in built]
-    sample = 64
+    # structure must match (on every event, and no GPU construction, with
+    # --batch-host-build)
+    sample = 64 if gpu_build else len(hits)
     t0 = time.perf_counter()
     host = [sbt.build_qubo(h) for h in hits[:sample]]
     host_sample_s = time.perf_counter() - t0
+    if gpu_build:
+        t0 = time.perf_counter()
+        built = [sbt.build_qubo_gpu(h) for h in hits]
+        gpu_build_s = time.perf_counter() - t0
+    else:  # host-built QUBOs (profiling runs: only the solver's kernels on the GPU)
+        built, gpu_build_s = [(q, 0.0) for q in host], None
+    qs = [q for q, _ in built]
     same = all(np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col, b.col) and
                np.array_equal(a.trip_hits, b.trip_hits) for a, b in zip(qs, host))
     M, K = 128, 3000
@@ -184,10 +188,10 @@ def batched_form(sbt, tg, torch, np, with_fp32=True):
                        "event seeds 1000-1511; dSB, 128 agents x 3000 steps",
            "events": len(qs), "sum_n": sum_n, "max_n": max(q.n for q in qs),
            "qubo_build": {"gpu_all_events_s": gpu_build_s,
-                          "gpu_device_s": float(sum(d for _, d in built)),
+                          "gpu_device_s": float(sum(d for _, d in built)) if gpu_build else None,
                           "host_all_events_s_from_sample": host_sample_s * len(qs) / sample,
                           "host_sample": f"first {sample} events, {host_sample_s:.2f} s",
-                          "same_structure_on_sample": bool(same)}}
+                          "same_structure_on_sample": bool(same) if gpu_build else None}}
     if with_fp32:
         plain = [sbt.DeviceSolver(q, "dsb", sbt.solve_params(agents=M, steps=K, seed=0, event=e))
                  for e, q in enumerate(qs)]
@@ -262,7 +266,7 @@ def batched_form(sbt, tg, torch, np, with_fp32=True):
                               "events_within_0.5pct_of_fp32": int(np.sum(gap <= 0.005))})
         log(f"batched form: {prec} batch done")
     # hits to every event's best spins on the GPU: construction + one batch
-    out["end_to_end_fp16_s"] = gpu_build_s + out["fp16"]["seconds"]
+    out["end_to_end_fp16_s"] = None if gpu_build_s is None else gpu_build_s + out["fp16"]["seconds"]
     return out
 
 
@@ -427,6 +431,9 @@ def main():
     ap.add_argument("--batch-skip-fp32", action="store_true",
                     help="batched form without the FP32 one-event-at-a-time comparison "
                          "(for counter collection)")
+    ap.add_argument("--batch-host-build", action="store_true",
+                    help="batched form on host-built QUBOs, without the GPU builder's "
+                         "launches (for counter collection)")
     ap.add_argument("--stress-steps", type=int, default=10000,
                     help="SB steps of the stress form (10000 is the workload's)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
@@ -458,7 +465,8 @@ def main():
         sys.exit(1)
     if args.only:
         form = {"precision": lambda: precision_form(sbt, tg, torch, np),
-                "batched": lambda: batched_form(sbt, tg, torch, np, not args.batch_skip_fp32),
+                "batched": lambda: batched_form(sbt, tg, torch, np, not args.batch_skip_fp32,
+                                                not args.batch_host_build),
                 "stress": lambda: stress_form(sbt, tg, torch, np, args.stress_steps)}[args.only]
         print(json.dumps({f"{args.only}_form": form()}), flush=True)
         return

@@ -26,7 +26,9 @@ ARCH = "gfx950"
 
 HOST_SOURCES = ["status.cpp", "build_qubo.cpp", "order.cpp", "anneal.cpp"]
 RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
-HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_batch.hip", "sb_stream.hip",
+HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_resident_reg_bsb.hip",
+               "sb_resident_reg_dsb.hip", "sb_resident_reg_asb.hip", "sb_batch.hip",
+               "sb_batch_bsb.hip", "sb_batch_dsb.hip", "sb_batch_asb.hip", "sb_stream.hip",
                "build_qubo_gpu.hip"]
 # the GPU QUBO builder evaluates the host builder's cut expressions: no
 # floating-point contraction, like the host file

@@ -157,6 +157,10 @@ struct BatchArgs {
 
 hipError_t launch_batch_prep(int jprec, const BatchArgs &B, hipStream_t st);
 hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream_t st);
+// the step kernel of one mode (one translation unit each)
+hipError_t launch_batch_steps_bsb(int jprec, const BatchArgs &B, hipStream_t st);
+hipError_t launch_batch_steps_dsb(int jprec, const BatchArgs &B, hipStream_t st);
+hipError_t launch_batch_steps_asb(int jprec, const BatchArgs &B, hipStream_t st);
 hipError_t launch_batch_select(const BatchArgs &B, hipStream_t st);
 
 hipError_t launch_prep(int n, const double *a, const int *row_ptr, const int *col, const double *b,
@@ -169,6 +173,10 @@ hipError_t launch_resident(int mode, const ResidentArgs &A, const ResidentShape 
 hipError_t launch_resident_reg(int mode, const ResidentArgs &A, const ResidentShape &S,
                                hipStream_t st);
 hipError_t launch_row_order(int n, const int *row_ptr, int *perm, hipStream_t st);
+// the register-row step kernel of one mode (one translation unit each)
+hipError_t launch_resident_reg_bsb(const ResidentArgs &A, const ResidentShape &S, hipStream_t st);
+hipError_t launch_resident_reg_dsb(const ResidentArgs &A, const ResidentShape &S, hipStream_t st);
+hipError_t launch_resident_reg_asb(const ResidentArgs &A, const ResidentShape &S, hipStream_t st);
 hipError_t launch_stream2(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
                           float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st);
 hipError_t launch_sign_planes(int n, int M, const float *x, uint64_t *S, hipStream_t st);
