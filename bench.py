@@ -30,6 +30,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MI355X_FP32_VECTOR_TFLOPS = 157.3
+# FP32 FMAs without the packed (two per lane) instructions, which the
+# library's kernels are built without: 256 CUs x 4 SIMDs x 16 lanes x 2 flop
+# x 2.4 GHz
+MI355X_FP32_UNPACKED_TFLOPS = 78.6
 MI355X_HBM_GBS = 8000.0
 EVENT_SEED = 100
 AGENTS = 256
@@ -247,6 +251,8 @@ def batched_form(sbt, tg, torch, np, with_fp32=True, gpu_build=True):
                      "roofline": {"bound": "alu", "achieved": achieved,
                                   "peak": MI355X_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                                   "frac": achieved / MI355X_FP32_VECTOR_TFLOPS,
+                                  "peak_without_packed_fp32": MI355X_FP32_UNPACKED_TFLOPS,
+                                  "frac_without_packed_fp32": achieved / MI355X_FP32_UNPACKED_TFLOPS,
                                   "traffic": measured_traffic(f"sb_batch_batching_{prec}.md"),
                                   "kernel": "sb_batch", "launch_ms": launch_s * 1e3}}
         if with_fp32:
@@ -520,6 +526,8 @@ def main():
         achieved = flops / launch_s / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": MI355X_FP32_VECTOR_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_VECTOR_TFLOPS,
+                "peak_without_packed_fp32": MI355X_FP32_UNPACKED_TFLOPS,
+                "frac_without_packed_fp32": achieved / MI355X_FP32_UNPACKED_TFLOPS,
                 "traffic": measured_traffic("sb_resident_reg_plain.md"),
                 "kernel": "sb_resident_reg", "launch_ms": launch_s * 1e3,
                 "state_bytes_if_streamed_GBs": bytes_ / launch_s / 1e9}
