@@ -134,7 +134,7 @@ __global__ __launch_bounds__(MAXTPB) void sb_resident_reg(ResidentArgs A) {
         int off = before;
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
-            tpk[s] = (off << 12) | min(tlen[s], 4095);
+            tpk[s] = lds_tails ? (off << 12) | tlen[s] : 0;  // off, tlen < 2^11 here
             if (lds_tails && tlen[s] > 0) {
                 const int i = wr[s];
                 const int p = A.row_ptr[i] + (s == 0 ? RC : RR);
