@@ -56,11 +56,14 @@ constexpr bool reg_fits(int maxtpb, int spt, int rc, int rr) {
     return !(spt > 4 && rc > 4) && reg_vgpr_estimate(spt, rc, rr) <= reg_vgpr_budget(maxtpb);
 }
 // the shapes that are built: same capacity everywhere where it fits, else
-// (rc, 2) where that fits
+// (rc, 2) where that fits with kSplitSlack VGPRs to spare (the compiler
+// keeps the step loop of such shapes spill-free -- checked on the ISA of
+// (1024 threads, 4 spins, 8/2) -- spilling only in the code around it)
+constexpr int kSplitSlack = 16;
 constexpr bool reg_variant_fits(int maxtpb, int spt, int rc, int rr) {
     if (rr == rc) return reg_fits(maxtpb, spt, rc, rc);
-    return spt > 1 && rr == 2 && rc > 2 && !reg_fits(maxtpb, spt, rc, rc) &&
-           reg_fits(maxtpb, spt, rc, 2);
+    return spt > 1 && rr == 2 && rc > 2 && !reg_fits(maxtpb, spt, rc, rc) && !(spt > 4 && rc > 4) &&
+           reg_vgpr_estimate(spt, rc, 2) <= reg_vgpr_budget(maxtpb) + kSplitSlack;
 }
 
 constexpr int kRegMaxN = 8192;   // register-row variant: largest n
