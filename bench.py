@@ -149,6 +149,25 @@ def precision_form(sbt, tg, torch, np):
                      "ttt_checkpoint": ttt_checkpoint(make(K, TTT_EVERY), K,
                                                       e_star + 0.005 * abs(e_star), torch,
                                                       trace_of)}
+        if name == "fp32" and out[name]["kernel"] == "stream":
+            # one streaming launch per step: its duration from the library's
+            # step events, against the step's algorithmic HBM bytes
+            b, ev_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b.record()
+            ev_.record()
+            torch.cuda.synchronize()
+            s._dr.step_begin, s._dr.step_end = b.cuda_event, ev_.cuda_event
+            s.run()
+            torch.cuda.synchronize()
+            s._dr.step_begin = s._dr.step_end = None
+            launch_s = b.elapsed_time(ev_) * 1e-3 / K
+            byts = stream_bytes_dsb(q.n, q.nnz, M)
+            achieved = byts / launch_s / 1e9
+            out[name]["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_GBS,
+                                     "unit": "GB/s", "frac": achieved / MI355X_HBM_GBS,
+                                     "traffic": measured_traffic("sb_stream_precision_dsb.md"),
+                                     "kernel": "sb_stream",
+                                     "launch_ms": launch_s * 1e3, "bytes_per_launch": byts}
         del s
     e_low = min([e_star] + [out[n]["best"] for n in forms])
     out["ttt99_target"] = 0.999 * e_low
@@ -281,6 +300,15 @@ def stream_bytes(n, nnz, agents, jbytes):
     x, y read and written per spin update, each coupling's column and value
     once, h, row pointers and the per-row scale once."""
     return 16.0 * n * agents + (4.0 + jbytes) * nnz + 12.0 * n
+
+
+def stream_bytes_dsb(n, nnz, agents):
+    """Algorithmic HBM bytes of one dSB streaming launch: x, y read and
+    written in place per spin update, the 64-agent sign words of every spin
+    read once and written once, each coupling's column and value once, h,
+    row pointers and the per-row scale once."""
+    words = (agents + 63) // 64
+    return 16.0 * n * agents + 16.0 * n * words + 8.0 * nnz + 12.0 * n
 
 
 def stress_form(sbt, tg, torch, np, K=10000):
