@@ -484,8 +484,8 @@ def main():
         print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 3}))
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; the solver shards over agents with "
-              "no per-step communication, so --gpus N > 1 is not run here", file=sys.stderr)
+        print("bench.py measures one GPU; the solver shards over agents with no per-step "
+              "communication, so --gpus N > 1 is not run", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
