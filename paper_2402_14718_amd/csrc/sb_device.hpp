@@ -49,16 +49,11 @@ __device__ __forceinline__ float philox_word_to_unit(uint32_t r) {
     return static_cast<float>(static_cast<int32_t>(r >> 8) - (1 << 23)) * 0x1p-26f;
 }
 
-__device__ __forceinline__ float sgnf(float v) { return v >= 0.0f ? 1.0f : -1.0f; }
-
-// The coupling operand: x itself (bSB, Eq. 6) or sgn(x) (dSB, Eq. 10).
-template <int MODE>
-__device__ __forceinline__ float coupling_operand(float v) {
-    if constexpr (MODE == kDSB)
-        return sgnf(v);
-    else
-        return v;
-}
+// sgn(x) with sgn(0) = +1, as copysign(1, x): one bitfield insert.  The
+// two differ only at x = -0, which no position ever holds: starts are +0 or
+// nonzero, and the steps' fused multiply-adds and clamp return -0 only
+// when their addend already is -0.
+__device__ __forceinline__ float sgnf(float v) { return __builtin_copysignf(1.0f, v); }
 
 // Schedule factor (a0 - a_k) with a_k = a0 k / K, evaluated in FP64.
 __device__ __forceinline__ float schedule_gap(double a0, int k, int K) {
@@ -102,7 +97,8 @@ __device__ __forceinline__ void sb_step(float &x, float &y, float F, float c0, f
         sb_update(x, y, F, c0, g, dt, dta0);
 }
 
-// What the coupling reads of a neighbour: its position (bSB, aSB) or sign (dSB).
+// What the coupling reads of a neighbour: its position (bSB, Eq. 6; aSB) or
+// its sign (dSB, Eq. 10).
 template <int MODE>
 __device__ __forceinline__ float shared_value(float x) {
     if constexpr (MODE == kDSB)
