@@ -79,6 +79,14 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
 
 }  // namespace
 
+// Couplings gathered per step for slot S: C0 for slot 0; the slot's capacity
+// for the others, or at most 2 when every row past slot 0 of the wave is
+// that short (SH).
+template <int C0, bool SH>
+constexpr int slot_gathers(int S) {
+    return S == 0 ? C0 : (SH && kCap[S] > 2 ? 2 : kCap[S]);
+}
+
 // Calls f(integral_constant<int, S>) for S = 0 .. kS-1, so per-slot
 // capacities are constant expressions and every register array is indexed
 // with constants.
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             else if constexpr (S == 7) return cp7;
             else return cp8;
         };
-        int need0 = 0, tail = 0, act = 0;
+        int need0 = 0, tail = 0, act = 0, rest = 0;
         for_slots([&](auto sc) __attribute__((always_inline)) {
             constexpr int S = decltype(sc)::value;
             constexpr int CAP = kCap[S];
@@ -162,7 +170,10 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                         cp[c] = static_cast<uint32_t>((B.col[E.nz_off + p0 + c] * A + a) * 4) |
                                 (static_cast<uint32_t>(B.J16[E.nz_off + p0 + c]) << 16);
                 }
-                if (S == 0) need0 = p1 - p0;
+                if (S == 0)
+                    need0 = p1 - p0;
+                else
+                    rest = max(rest, min(p1 - p0, CAP));
                 tail |= (p1 - p0 > CAP) ? 1 : 0;
                 act |= 1 << S;
                 xs[i * A + a] = shared_value<MODE>(xr[S]);
@@ -170,6 +181,8 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
         });
         const int cap0 = wave_max_int(need0);
         const int any_tail = wave_max_int(tail);
+        // every row past slot 0 in this wave has at most two couplings
+        const bool short_rest = wave_max_int(rest) <= 2;
         int act_w = act;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) act_w |= __shfl_xor(act_w, off, 64);
@@ -223,9 +236,12 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
         // LDS store, barrier -- with rows longer than a slot's capacity
         // (rare) continuing from global memory out of line.  Every variant
         // meets the same barriers.
-        auto run = [&](auto nac, auto c0c) __attribute__((always_inline)) {
+        // SH: slots past 0 gather min(capacity, 2) couplings (the entries
+        // beyond are zero padding in such a wave)
+        auto run = [&](auto nac, auto c0c, auto shc) __attribute__((always_inline)) {
             constexpr int NA = decltype(nac)::value;
             constexpr int C0 = decltype(c0c)::value;
+            constexpr bool SH = decltype(shc)::value;
             auto step = [&](auto bufc, int k) __attribute__((always_inline)) {
                 constexpr int BUF = decltype(bufc)::value;
                 const unsigned char *xc = smem + BUF * kBatchStride * 4;
@@ -237,7 +253,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                     if constexpr (S < NA) {
                         acc[S] = hr[S];
                         uint32_t *cp = cps(sc);
-                        constexpr int CAP = S == 0 ? C0 : kCap[S];
+                        constexpr int CAP = slot_gathers<C0, SH>(S);
 #pragma unroll
                         for (int c = 0; c < CAP; ++c) launder(cp[c]);
                         launder(wr[S]);
@@ -274,7 +290,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                         float *v = vs(sc);
                         const uint32_t *cp = cps(sc);
 #pragma unroll
-                        for (int c = 0; c < kCap[S]; ++c) v[c] = lds_at(xc, cp[c]);
+                        for (int c = 0; c < slot_gathers<C0, SH>(S); ++c) v[c] = lds_at(xc, cp[c]);
                     }
                 });
                 for_slots([&](auto sc) __attribute__((always_inline)) {
@@ -283,7 +299,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                         const float *v = vs(sc);
                         const uint32_t *cp = cps(sc);
 #pragma unroll
-                        for (int c = 0; c < kCap[S]; ++c)
+                        for (int c = 0; c < slot_gathers<C0, SH>(S); ++c)
                             acc[S] = __builtin_fmaf(packed_j<JP>(cp[c]), v[c], acc[S]);
                     }
                 });
@@ -330,13 +346,19 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                 }
             }
         };
+        auto with_sh = [&](auto nac, auto c0c) __attribute__((always_inline)) {
+            if (short_rest)
+                run(nac, c0c, std::true_type{});
+            else
+                run(nac, c0c, std::false_type{});
+        };
         auto with_c0 = [&](auto nac) __attribute__((always_inline)) {
             if (cap0 <= 4)
-                run(nac, std::integral_constant<int, 4>{});
+                with_sh(nac, std::integral_constant<int, 4>{});
             else if (cap0 <= 8)
-                run(nac, std::integral_constant<int, 8>{});
+                with_sh(nac, std::integral_constant<int, 8>{});
             else
-                run(nac, std::integral_constant<int, kCap[0]>{});
+                with_sh(nac, std::integral_constant<int, kCap[0]>{});
         };
         switch (n_act) {
             case 1: with_c0(std::integral_constant<int, 1>{}); break;
