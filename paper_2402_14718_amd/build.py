@@ -28,8 +28,11 @@ HOST_SOURCES = ["status.cpp", "build_qubo.cpp", "order.cpp", "anneal.cpp"]
 RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
 HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_resident_reg_bsb.hip",
                "sb_resident_reg_dsb.hip", "sb_resident_reg_asb.hip", "sb_batch.hip",
-               "sb_batch_bsb.hip", "sb_batch_dsb.hip", "sb_batch_asb.hip", "sb_stream.hip",
-               "build_qubo_gpu.hip"]
+               "sb_stream.hip", "build_qubo_gpu.hip"]
+# one source built several times: (source, object tag, extra flags) -- the
+# batched step kernel once per (mode, coupling format), in parallel
+HIP_VARIANTS = [("sb_batch_mode.hip", f"{m}_{j}", [f"-DSBT_BATCH_MODE={mi}", f"-DSBT_BATCH_JP={ji}"])
+                for mi, m in enumerate(("bsb", "dsb", "asb")) for ji, j in enumerate(("fp16", "bf16"))]
 # the GPU QUBO builder evaluates the host builder's cut expressions: no
 # floating-point contraction, like the host file
 HIP_EXTRA_FLAGS = {"build_qubo_gpu.hip": ["-ffp-contract=off"]}
@@ -65,6 +68,9 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, src + ".o")
         jobs.append(([hipcc, *HIP_FLAGS, *HIP_EXTRA_FLAGS.get(src, []), "-c",
                       os.path.join(CSRC, src), "-o", obj], obj))
+    for src, tag, flags in HIP_VARIANTS:
+        obj = os.path.join(BUILD, f"{src}.{tag}.o")
+        jobs.append(([hipcc, *HIP_FLAGS, *flags, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
     with ThreadPoolExecutor(max_workers=workers) as pool:
         for f in [pool.submit(_run, cmd, verbose) for cmd, _ in jobs]:

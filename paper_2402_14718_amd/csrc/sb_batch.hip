@@ -1,7 +1,7 @@
 // Batched SB over many events (gfx950): per-event preparation, the work
 // counter, best-agent selection, and the dispatch to the step kernel of
-// each mode (sb_batch_step.hpp, built once per mode in
-// sb_batch_{bsb,dsb,asb}.hip).
+// each mode and coupling format (sb_batch_step.hpp, instantiated once per
+// pair by sb_batch_mode.hip).
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
@@ -150,9 +150,12 @@ hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream
     batch_reset<<<1, 1, 0, st>>>(B.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (mode == kDSB) return launch_batch_steps_dsb(jprec, B, st);
-    if (mode == kASB) return launch_batch_steps_asb(jprec, B, st);
-    return launch_batch_steps_bsb(jprec, B, st);
+    const bool f16 = jprec == kJFp16;
+    if (mode == kDSB)
+        return f16 ? launch_batch_steps_tu<kDSB, kJFp16>(B, st) : launch_batch_steps_tu<kDSB, kJBf16>(B, st);
+    if (mode == kASB)
+        return f16 ? launch_batch_steps_tu<kASB, kJFp16>(B, st) : launch_batch_steps_tu<kASB, kJBf16>(B, st);
+    return f16 ? launch_batch_steps_tu<kBSB, kJFp16>(B, st) : launch_batch_steps_tu<kBSB, kJBf16>(B, st);
 }
 
 hipError_t launch_batch_select(const BatchArgs &B, hipStream_t st) {

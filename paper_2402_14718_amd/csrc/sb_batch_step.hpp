@@ -19,9 +19,9 @@
 // slots all belong to agent t % A).  Register capacity per slot follows the
 // row-length profile by rank: slot 0 holds the longest rows.
 //
-// This header holds the step kernel; sb_batch_{bsb,dsb,asb}.hip build one
-// mode each (in parallel), sb_batch.hip the per-event preparation and the
-// best-agent selection.
+// This header holds the step kernel; sb_batch_mode.hip instantiates it for
+// one (mode, coupling format) per build of that file (in parallel),
+// sb_batch.hip holds the per-event preparation and the best-agent selection.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -387,14 +387,12 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
     }
 }
 
-// The step kernel of one mode, FP16 or BF16 couplings (the work counter
-// must already be zero).
-template <int MODE>
-hipError_t launch_batch_steps_mode(int jprec, const BatchArgs &B, hipStream_t st) {
+// The step kernel of one mode and coupling format (the work counter must
+// already be zero).
+template <int MODE, int JP>
+hipError_t launch_batch_steps_tu(const BatchArgs &B, hipStream_t st) {
     const size_t lds = sizeof(float) * 2 * kBatchStride + sizeof(double) * 16 * 64 + 16;
-    const dim3 grid(B.grid), block(kB);
-    return jprec == kJFp16 ? launch_with_lds(sb_batch<MODE, kJFp16>, grid, block, lds, st, B)
-                           : launch_with_lds(sb_batch<MODE, kJBf16>, grid, block, lds, st, B);
+    return launch_with_lds(sb_batch<MODE, JP>, dim3(B.grid), dim3(kB), lds, st, B);
 }
 
 }  // namespace sbt

@@ -160,10 +160,10 @@ struct BatchArgs {
 
 hipError_t launch_batch_prep(int jprec, const BatchArgs &B, hipStream_t st);
 hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream_t st);
-// the step kernel of one mode (one translation unit each)
-hipError_t launch_batch_steps_bsb(int jprec, const BatchArgs &B, hipStream_t st);
-hipError_t launch_batch_steps_dsb(int jprec, const BatchArgs &B, hipStream_t st);
-hipError_t launch_batch_steps_asb(int jprec, const BatchArgs &B, hipStream_t st);
+// the step kernel of one mode and coupling format, instantiated in its own
+// translation unit (sb_batch_mode.hip, built once per pair)
+template <int MODE, int JP>
+hipError_t launch_batch_steps_tu(const BatchArgs &B, hipStream_t st);
 hipError_t launch_batch_select(const BatchArgs &B, hipStream_t st);
 
 hipError_t launch_prep(int n, const double *a, const int *row_ptr, const int *col, const double *b,
