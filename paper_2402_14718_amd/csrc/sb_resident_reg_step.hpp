@@ -1,4 +1,4 @@
-// Register-row resident SB kernel (gfx950) and the spin ordering it uses.
+// Register-row resident SB kernel (gfx950).
 //
 // Paper section "Simulated Bifurcation": all K symplectic-Euler steps of
 // bSB (Eq. 5-8) or dSB (Eq. 9-12) for one agent run inside one workgroup.
@@ -17,6 +17,13 @@
 // the sign of a zero sum, which never grows into a nonzero difference.  A
 // spin's arithmetic does not depend on which thread runs it, so results are
 // bit-identical to the streaming kernel.
+//
+// Register capacity: slot 0 holds up to RC couplings of its row, the other
+// slots RR (RC, or 2 when RC everywhere does not fit the VGPR budget: slot
+// 0 holds the longest rows).  Couplings past a slot's capacity are copied
+// once into an LDS area at kernel start (placed by a block scan) and summed
+// from there after the held ones, in CSR order; if they do not fit, from
+// global memory.
 //
 // This header holds the step kernel and its shape dispatch;
 // sb_resident_reg_{bsb,dsb,asb}.hip build one mode each (in parallel),
