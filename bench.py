@@ -414,6 +414,59 @@ def _sized_run(run_one, target_s):
     return k, time.perf_counter() - t0
 
 
+def _oracle_form_rate(qs, mode, agents, target_s, threads_used):
+    """C oracle (all host threads) on the QUBOs `qs`: spin-updates/s from the
+    difference of a 2-step run and a longer one (x4 until the difference
+    reaches a quarter of target_s), so the per-run copies of the state
+    cancel."""
+    import scipy.sparse as sp
+
+    from oracle import ising as oising
+    from oracle import sb_c
+
+    isgs = [oising.from_qubo(q.a, sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n)))
+            for q in qs]
+
+    def run(k):
+        t0 = time.perf_counter()
+        for e, isg in enumerate(isgs):
+            threads_used[0] = sb_c.run(isg.J, isg.h, isg.c0, mode, agents, k, seed=SOLVER_SEED,
+                                       event=e)[2]
+        return time.perf_counter() - t0
+
+    t_lo = run(2)
+    k = 8
+    dt = run(k) - t_lo
+    while dt < target_s / 4 and k < 1 << 20:
+        k *= 4
+        dt = run(k) - t_lo
+    return {"spin_updates_per_s": sum(q.n for q in qs) * agents * (k - 2) / dt, "mode": mode,
+            "agents": agents, "steps": f"{k} minus 2", "seconds": dt}
+
+
+def cpu_forms_baseline(sbt, tg, target_s=4.0):
+    """The C oracle on every host thread for the precision, batching and
+    stress workloads (a bounded number of steps each; per-step cost is
+    constant, so the rate carries over to the full step counts)."""
+    used = [0]
+    ref = load_golden("oracle_best_precision.json")
+    out = {"precision": _oracle_form_rate(
+        [sbt.build_qubo(tg.generate(tg.precision_spec(), ref["event_seed"]).hits_struct())],
+        "dsb", 1024, target_s, used)}
+    qs = [sbt.build_qubo_gpu(tg.generate(sp_, seed).hits_struct())[0]
+          for sp_, seed in tg.batching_specs()]
+    out["batching"] = _oracle_form_rate(qs, "dsb", 128, target_s, used)
+    del qs
+    ev = tg.generate(tg.stress_spec(), 300)
+    bp = sbt.build_params_default()
+    bp.z0_max = tg.STRESS_Z0_MAX
+    q = sbt.build_qubo_gpu(ev.hits_struct(), bp)[0]
+    q = sbt.permute_qubo(q, sbt.phi_order(q, ev.hits_struct()))
+    out["stress"] = _oracle_form_rate([q], "bsb", 512, target_s, used)
+    out["threads"] = used[0]
+    return out
+
+
 def cpu_baseline(q, target_s=8.0):
     """The FP64 oracle on the host, both forms, all 256 agents, for a bounded
     number of steps, as spin-updates/s: the C oracle with the agents spread
@@ -625,6 +678,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on the host (bounded sample)")
         result["cpu_baseline"] = cpu_baseline(q)
+        if not args.no_forms:
+            log("timing the C oracle on the other workloads (bounded samples)")
+            result["cpu_baseline"]["forms"] = cpu_forms_baseline(sbt, tg)
     print(json.dumps(result), flush=True)
 
 
