@@ -417,8 +417,8 @@ def _sized_run(run_one, target_s):
 def _oracle_form_rate(qs, mode, agents, target_s, threads_used):
     """C oracle (all host threads) on the QUBOs `qs`: spin-updates/s from the
     difference of a 2-step run and a longer one (x4 until the difference
-    reaches a quarter of target_s), so the per-run copies of the state
-    cancel."""
+    reaches half of target_s), so the per-run copies of the state and the
+    per-call overheads cancel."""
     import scipy.sparse as sp
 
     from oracle import ising as oising
@@ -437,7 +437,7 @@ def _oracle_form_rate(qs, mode, agents, target_s, threads_used):
     t_lo = run(2)
     k = 8
     dt = run(k) - t_lo
-    while dt < target_s / 4 and k < 1 << 20:
+    while dt < target_s / 2 and k < 1 << 20:
         k *= 4
         dt = run(k) - t_lo
     return {"spin_updates_per_s": sum(q.n for q in qs) * agents * (k - 2) / dt, "mode": mode,
