@@ -104,6 +104,8 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
     float *xs = reinterpret_cast<float *>(smem);                     // [2][kBatchStride]
     double *red = reinterpret_cast<double *>(xs + 2 * kBatchStride); // [16][64]
     int *item_s = reinterpret_cast<int *>(red + 16 * 64);
+    // couplings past a slot's register capacity, packed like the held ones
+    uint32_t *tails = reinterpret_cast<uint32_t *>(item_s + 4);  // [kBatchTailCap]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 
     for (;;) {
@@ -143,6 +145,10 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             else return cp8;
         };
         int need0 = 0, tail = 0, act = 0, rest = 0;
+        // tail lengths of the slots, 4 bits each: slots 0-7 in tp_lo, slot 8
+        // in the low bits of tp_hi (whose upper bits get the LDS offset)
+        uint32_t tp_lo = 0, tp_hi = 0;
+        int tsum = 0, tbig = 0;
         for_slots([&](auto sc) __attribute__((always_inline)) {
             constexpr int S = decltype(sc)::value;
             constexpr int CAP = kCap[S];
@@ -175,6 +181,14 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                 else
                     rest = max(rest, min(p1 - p0, CAP));
                 tail |= (p1 - p0 > CAP) ? 1 : 0;
+                const int tl = max(0, p1 - p0 - CAP);
+                tbig |= tl > 15 ? 1 : 0;
+                const uint32_t tl4 = static_cast<uint32_t>(min(tl, 15));
+                if constexpr (S < 8)
+                    tp_lo |= tl4 << (4 * S);
+                else
+                    tp_hi |= tl4;
+                tsum += tl;
                 act |= 1 << S;
                 xs[i * A + a] = shared_value<MODE>(xr[S]);
             }
@@ -183,6 +197,27 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
         const int any_tail = wave_max_int(tail);
         // every row past slot 0 in this wave has at most two couplings
         const bool short_rest = wave_max_int(rest) <= 2;
+        // tails staged in LDS once per item (offsets by a block scan); an
+        // item whose tails do not fit, or hold more than 15 couplings for
+        // one row, reads them from global memory
+        int t_total = 0, big_total = 0;
+        const int t_base = block_exclusive_scan(tsum, reinterpret_cast<int *>(red), t_total);
+        (void)block_exclusive_scan(tbig, reinterpret_cast<int *>(red), big_total);
+        const bool lds_tails = t_total <= kBatchTailCap && big_total == 0;
+        if (lds_tails && tsum > 0) {
+            int o = t_base;
+            for_slots([&](auto sc) __attribute__((always_inline)) {
+                constexpr int S = decltype(sc)::value;
+                const int i = spin_of(S);
+                if (i >= 0) {
+                    const int p0 = B.row_ptr[E.rp_off + i] + kCap[S], p1 = B.row_ptr[E.rp_off + i + 1];
+                    for (int p = p0; p < p1; ++p)
+                        tails[o++] = static_cast<uint32_t>((B.col[E.nz_off + p] * A + a) * 4) |
+                                     (static_cast<uint32_t>(B.J16[E.nz_off + p]) << 16);
+                }
+            });
+        }
+        tp_hi |= lds_tails ? static_cast<uint32_t>(t_base) << 4 : 0u;
         int act_w = act;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) act_w |= __shfl_xor(act_w, off, 64);
@@ -303,7 +338,21 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                             acc[S] = __builtin_fmaf(packed_j<JP>(cp[c]), v[c], acc[S]);
                     }
                 });
-                if (__builtin_expect(any_tail, 0)) {
+                if (__builtin_expect(any_tail, 0) && lds_tails) {
+                    // CSR order within each slot's row, after the held couplings
+                    int o = static_cast<int>(tp_hi >> 4);
+                    for_slots([&](auto sc) __attribute__((always_inline)) {
+                        constexpr int S = decltype(sc)::value;
+                        if constexpr (S < NA) {
+                            const int len = static_cast<int>((S < 8 ? tp_lo >> (4 * S) : tp_hi) & 15u);
+                            for (int u = 0; u < len; ++u) {
+                                const uint32_t w = tails[o + u];
+                                acc[S] = __builtin_fmaf(packed_j<JP>(w), lds_at(xc, w), acc[S]);
+                            }
+                            o += len;
+                        }
+                    });
+                } else if (__builtin_expect(any_tail, 0)) {
                     const float *xcf = reinterpret_cast<const float *>(xc);
                     for_slots([&](auto sc) __attribute__((always_inline)) {
                         constexpr int S = decltype(sc)::value;
@@ -391,7 +440,8 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
 // already be zero).
 template <int MODE, int JP>
 hipError_t launch_batch_steps_tu(const BatchArgs &B, hipStream_t st) {
-    const size_t lds = sizeof(float) * 2 * kBatchStride + sizeof(double) * 16 * 64 + 16;
+    const size_t lds = sizeof(float) * 2 * kBatchStride + sizeof(double) * 16 * 64 + 16 +
+                       sizeof(uint32_t) * kBatchTailCap;
     return launch_with_lds(sb_batch<MODE, JP>, dim3(B.grid), dim3(kB), lds, st, B);
 }
 

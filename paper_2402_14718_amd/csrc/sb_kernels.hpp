@@ -115,6 +115,8 @@ struct StreamArgs {
 constexpr int kBatchTPB = 1024;                     // threads per workgroup
 constexpr int kBatchSPT = 9;                        // slots per thread
 constexpr int kBatchSlots = kBatchTPB * kBatchSPT;  // largest n * agents per item
+constexpr int kBatchTailCap = 8192;                 // batch: couplings past the slots' register
+                                                    //   capacity staged in LDS (32 KB)
 constexpr int kBatchStride = kBatchSlots + 64;      // LDS position buffer: slots, then
                                                     //   one pad word per lane of a wave
 enum : int { kJFp16 = 0, kJBf16 = 1, kJFp32 = 2, kJFp8 = 3 };  // coupling formats
