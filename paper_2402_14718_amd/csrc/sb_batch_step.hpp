@@ -44,7 +44,8 @@ constexpr int kS = kBatchSPT;     // slots per thread
 constexpr int kCap[kS] = {16, 8, 5, 4, 3, 2, 2, 2, 1};
 
 // A held coupling is one VGPR: LDS byte address of the neighbour in the
-// low 16 bits, the 16-bit coupling in the high 16 bits.  FP16 converts
+// first position buffer in the low 16 bits, the 16-bit coupling in the high
+// 16 bits.  FP16 converts
 // inside the multiply-add (v_fma_mix); BF16 is the upper half of an FP32.
 template <int JP>
 __device__ __forceinline__ float packed_j(uint32_t cp) {
@@ -60,8 +61,25 @@ __device__ __forceinline__ float j16_to_f32(uint16_t bits) {
     return packed_j<JP>(static_cast<uint32_t>(bits) << 16);
 }
 
-__device__ __forceinline__ float lds_at(const unsigned char *base, uint32_t cp) {
-    return *reinterpret_cast<const float *>(base + (cp & 0xFFFFu));
+// LDS words by absolute address (an address-space-3 pointer made from the
+// integer): a constant displacement -- which position buffer a step reads
+// or writes -- then folds into the instruction's offset field instead of
+// costing an add per access.
+typedef __attribute__((address_space(3))) float lds_float;
+typedef __attribute__((address_space(3))) unsigned char lds_byte;
+
+__device__ __forceinline__ float lds_load(uint32_t addr) {
+    return *(const lds_float *)(static_cast<uintptr_t>(addr));
+}
+
+__device__ __forceinline__ void lds_store(uint32_t addr, float v) {
+    *(lds_float *)(static_cast<uintptr_t>(addr)) = v;
+}
+
+// The neighbour a held coupling names, in the buffer at displacement XO.
+template <uint32_t XO>
+__device__ __forceinline__ float lds_at(uint32_t cp) {
+    return lds_load((cp & 0xFFFFu) + XO);
 }
 
 // Hides a loop-invariant register from the optimiser (an empty asm that
@@ -123,12 +141,16 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
         const bool agent_ok = agent < B.M;
 
         float xr[kS], yr[kS], hr[kS];
-        // LDS word each slot's position is stored to: i * A + a for spin i,
-        // a pad word past the slots for a lane without a spin
+        // LDS address of the first position buffer (the dynamic LDS base; the
+        // launch checks that it is 0, so every packed address fits 16 bits)
+        const uint32_t lds0 = static_cast<uint32_t>(reinterpret_cast<uintptr_t>((lds_byte *)smem));
+        // LDS address, in the first position buffer, of the word each slot's
+        // position is stored to: lds0 + 4 (i * A + a) for spin i, a pad
+        // word past the slots for a lane without a spin
         uint32_t wr[kS];
         auto spin_of = [&](int S) __attribute__((always_inline)) -> int {
-            const uint32_t w = opaque(wr[S]);
-            return w < static_cast<uint32_t>(kBatchSlots) ? static_cast<int>(w >> lgA) : -1;
+            const uint32_t w = opaque(wr[S]) - lds0;
+            return w < static_cast<uint32_t>(4 * kBatchSlots) ? static_cast<int>(w >> (lgA + 2)) : -1;
         };
         uint32_t cp0[kCap[0]], cp1[kCap[1]], cp2[kCap[2]], cp3[kCap[3]], cp4[kCap[4]],
             cp5[kCap[5]], cp6[kCap[6]], cp7[kCap[7]], cp8[kCap[8]];
@@ -158,7 +180,8 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             const int i = (q < n && agent_ok) ? B.perm[E.row_off + q] : -1;
             // a lane without a spin in an active slot updates a zero
             // oscillator into its own pad word, so steps need no branches
-            wr[S] = i >= 0 ? static_cast<uint32_t>(i * A + a) : static_cast<uint32_t>(kBatchSlots + lane);
+            wr[S] = lds0 + 4u * (i >= 0 ? static_cast<uint32_t>(i * A + a)
+                                        : static_cast<uint32_t>(kBatchSlots + lane));
             xr[S] = yr[S] = hr[S] = 0.0f;
 #pragma unroll
             for (int c = 0; c < CAP; ++c) cp[c] = 0;
@@ -173,7 +196,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
 #pragma unroll
                 for (int c = 0; c < CAP; ++c) {
                     if (p0 + c < p1)
-                        cp[c] = static_cast<uint32_t>((B.col[E.nz_off + p0 + c] * A + a) * 4) |
+                        cp[c] = (lds0 + static_cast<uint32_t>((B.col[E.nz_off + p0 + c] * A + a) * 4)) |
                                 (static_cast<uint32_t>(B.J16[E.nz_off + p0 + c]) << 16);
                 }
                 if (S == 0)
@@ -212,7 +235,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                 if (i >= 0) {
                     const int p0 = B.row_ptr[E.rp_off + i] + kCap[S], p1 = B.row_ptr[E.rp_off + i + 1];
                     for (int p = p0; p < p1; ++p)
-                        tails[o++] = static_cast<uint32_t>((B.col[E.nz_off + p] * A + a) * 4) |
+                        tails[o++] = (lds0 + static_cast<uint32_t>((B.col[E.nz_off + p] * A + a) * 4)) |
                                      (static_cast<uint32_t>(B.J16[E.nz_off + p]) << 16);
                 }
             });
@@ -279,8 +302,9 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             constexpr bool SH = decltype(shc)::value;
             auto step = [&](auto bufc, int k) __attribute__((always_inline)) {
                 constexpr int BUF = decltype(bufc)::value;
-                const unsigned char *xc = smem + BUF * kBatchStride * 4;
-                float *xn = xs + (BUF ^ 1) * kBatchStride;
+                constexpr uint32_t XO = BUF * kBatchStride * 4;        // buffer read
+                constexpr uint32_t XN = (BUF ^ 1) * kBatchStride * 4;  // buffer written
+                const unsigned char *xc = smem + XO;
                 const float g = B.sched[k];
                 float acc[kS];
                 for_slots([&](auto sc) __attribute__((always_inline)) {
@@ -302,7 +326,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
 #pragma unroll
                     for (int c = 0; c < C0; ++c) w0[c] = cp0[c];
 #pragma unroll
-                    for (int c = 0; c < C0; ++c) v0[c] = lds_at(xc, w0[c]);
+                    for (int c = 0; c < C0; ++c) v0[c] = lds_at<XO>(w0[c]);
 #pragma unroll
                     for (int c = 0; c < C0; ++c) acc[0] = __builtin_fmaf(packed_j<JP>(w0[c]), v0[c], acc[0]);
                 }
@@ -325,7 +349,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                         float *v = vs(sc);
                         const uint32_t *cp = cps(sc);
 #pragma unroll
-                        for (int c = 0; c < slot_gathers<C0, SH>(S); ++c) v[c] = lds_at(xc, cp[c]);
+                        for (int c = 0; c < slot_gathers<C0, SH>(S); ++c) v[c] = lds_at<XO>(cp[c]);
                     }
                 });
                 for_slots([&](auto sc) __attribute__((always_inline)) {
@@ -347,7 +371,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                             const int len = static_cast<int>((S < 8 ? tp_lo >> (4 * S) : tp_hi) & 15u);
                             for (int u = 0; u < len; ++u) {
                                 const uint32_t w = tails[o + u];
-                                acc[S] = __builtin_fmaf(packed_j<JP>(w), lds_at(xc, w), acc[S]);
+                                acc[S] = __builtin_fmaf(packed_j<JP>(w), lds_at<XO>(w), acc[S]);
                             }
                             o += len;
                         }
@@ -371,7 +395,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                     constexpr int S = decltype(sc)::value;
                     if constexpr (S < NA) {
                         sb_step<MODE>(xr[S], yr[S], acc[S], c0, g, dt, dta0);
-                        xn[wr[S]] = shared_value<MODE>(xr[S]);
+                        lds_store(wr[S] + XN, shared_value<MODE>(xr[S]));
                     }
                 });
                 __syncthreads();
@@ -442,6 +466,15 @@ template <int MODE, int JP>
 hipError_t launch_batch_steps_tu(const BatchArgs &B, hipStream_t st) {
     const size_t lds = sizeof(float) * 2 * kBatchStride + sizeof(double) * 16 * 64 + 16 +
                        sizeof(uint32_t) * kBatchTailCap;
+    // the packed 16-bit neighbour addresses assume the dynamic LDS starts at
+    // address 0, which holds when the kernel has no static LDS
+    static const bool base_zero = [] {
+        hipFuncAttributes fa{};
+        return hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(sb_batch<MODE, JP>)) ==
+                   hipSuccess &&
+               fa.sharedSizeBytes == 0;
+    }();
+    if (!base_zero) return hipErrorInvalidConfiguration;
     return launch_with_lds(sb_batch<MODE, JP>, dim3(B.grid), dim3(kB), lds, st, B);
 }
 
