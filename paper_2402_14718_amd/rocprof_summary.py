@@ -1,7 +1,7 @@
 """Summarise rocprofv3 CSV output into a short markdown profile record.
 
     python -m paper_2402_14718_amd.rocprof_summary --title T --kernel REGEX \\
-        --trace DIR --fetch DIR --write DIR [--sq DIR] \\
+        --trace DIR --fetch DIR --write DIR [--sq DIR ...] \\
         --copy-fetch DIR --copy-write DIR --command CMD ... > profiles/NAME.md
 
 Each DIR is a rocprofv3 output directory (``-f csv``).  FETCH_SIZE and
@@ -75,7 +75,8 @@ def main(argv=None):
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
-    ap.add_argument("--sq")
+    ap.add_argument("--sq", action="append", default=[],
+                    help="folder of one SQ counter pass (repeatable; passes are merged)")
     ap.add_argument("--copy-fetch", required=True)
     ap.add_argument("--copy-write", required=True)
     ap.add_argument("--command", action="append", default=[])
@@ -123,9 +124,10 @@ def main(argv=None):
               f"{hbm_bytes/1e6:.2f} MB per launch = {hbm_bytes/avg_ns:.2f} GB/s.", ""]
     sq = None
     if a.sq:
-        ks = counters(a.sq)
-        name_s, vs = pick(ks, a.kernel)
-        sq = {c: sum(v) / len(v) for c, v in vs.items()}
+        sq = {}
+        for d in a.sq:
+            _, vs = pick(counters(d), a.kernel)
+            sq.update({c: sum(v) / len(v) for c, v in vs.items()})
         lines += ["## Instruction counters (SQ, summed over the chip, per dispatch)", "",
                   "| counter | value |", "|---|---|"]
         for c, v in sorted(sq.items()):
@@ -135,6 +137,18 @@ def main(argv=None):
             lines += ["", f"VALU issue: {sq['SQ_INSTS_VALU']:.4g} wave-instructions against "
                       f"{slots:.4g} wave64 issue slots in the kernel's duration "
                       f"(256 CU x 4 SIMD x 2.4 GHz / 4 cycles) = {sq['SQ_INSTS_VALU']/slots:.2f}."]
+        if "SQ_LDS_IDX_ACTIVE" in sq and "GRBM_GUI_ACTIVE" in sq:
+            # GRBM_GUI_ACTIVE comes summed over the 8 XCDs: per-XCD active
+            # cycles x 32 CUs per XCD = CU cycles of the chip
+            cu_cycles = sq["GRBM_GUI_ACTIVE"] / 8 * 256
+            lines += ["", f"LDS: indexed-access cycles {sq['SQ_LDS_IDX_ACTIVE']:.4g} = "
+                      f"{sq['SQ_LDS_IDX_ACTIVE']/cu_cycles:.2f} of the CU cycles "
+                      f"(GRBM_GUI_ACTIVE / 8 XCDs x 256 CUs); bank-conflict cycles "
+                      f"{sq.get('SQ_LDS_BANK_CONFLICT', 0.0):.4g} = "
+                      f"{sq.get('SQ_LDS_BANK_CONFLICT', 0.0)/cu_cycles:.2f} of the CU cycles, "
+                      f"{sq.get('SQ_LDS_BANK_CONFLICT', 0.0)/max(1.0, sq['SQ_LDS_IDX_ACTIVE']):.2f} "
+                      f"of the LDS cycles; out-of-range LDS accesses "
+                      f"{sq.get('SQ_LDS_MEM_VIOLATIONS', 0.0):.0f}."]
         lines.append("")
     for n in a.note:
         lines += [n, ""]
