@@ -273,6 +273,7 @@ def batched_form(sbt, tg, torch, np, with_fp32=True, gpu_build=True):
                                   "peak_without_packed_fp32": MI355X_FP32_UNPACKED_TFLOPS,
                                   "frac_without_packed_fp32": achieved / MI355X_FP32_UNPACKED_TFLOPS,
                                   "traffic": measured_traffic(f"sb_batch_batching_{prec}.md"),
+                                  "lds": measured_lds(f"sb_batch_batching_{prec}.md"),
                                   "kernel": "sb_batch", "launch_ms": launch_s * 1e3}}
         if with_fp32:
             bt = sbt.DeviceBatchSolver(qs, "dsb", prec, sbt.solve_params(
@@ -394,6 +395,25 @@ def measured_traffic(profile_name):
     if not rec or rec.get("sources_sha") != rs.sources_hash(rec["family"]):
         return None
     return rec["hbm_bytes_per_launch"]
+
+
+def measured_lds(profile_name):
+    """LDS use of the kernel from the committed rocprofv3 counter record, as
+    fractions of the chip's CU cycles (GRBM_GUI_ACTIVE comes summed over the
+    8 XCDs): cycles the LDS serves indexed accesses, and of those the cycles
+    stalled on bank conflicts.  None when the record lacks those counters or
+    the kernel's sources changed after they were taken."""
+    from paper_2402_14718_amd import rocprof_summary as rs
+    rec = rs.read_record(os.path.join(ROOT, "profiles", profile_name))
+    if not rec or rec.get("sources_sha") != rs.sources_hash(rec["family"]):
+        return None
+    sq = rec.get("sq") or {}
+    if "SQ_LDS_IDX_ACTIVE" not in sq or "GRBM_GUI_ACTIVE" not in sq:
+        return None
+    cu_cycles = sq["GRBM_GUI_ACTIVE"] / 8 * 256
+    return {"busy_frac": sq["SQ_LDS_IDX_ACTIVE"] / cu_cycles,
+            "bank_conflict_frac": sq.get("SQ_LDS_BANK_CONFLICT", 0.0) / cu_cycles,
+            "source": f"profiles/{profile_name}"}
 
 
 def _sized_run(run_one, target_s):
@@ -610,6 +630,7 @@ def main():
                 "peak_without_packed_fp32": MI355X_FP32_UNPACKED_TFLOPS,
                 "frac_without_packed_fp32": achieved / MI355X_FP32_UNPACKED_TFLOPS,
                 "traffic": measured_traffic("sb_resident_reg_plain.md"),
+                "lds": measured_lds("sb_resident_reg_plain.md"),
                 "kernel": "sb_resident_reg", "launch_ms": launch_s * 1e3,
                 "state_bytes_if_streamed_GBs": bytes_ / launch_s / 1e9}
     else:
