@@ -324,3 +324,78 @@ def test_batching_workload_all_events_quality_equals_plain_fp32():
     for prec in ("fp16", "bf16"):
         assert abs(counts[prec][0] - counts["fp32"][0]) <= 0.01, counts
         assert abs(counts[prec][1] - counts["fp32"][1]) <= 0.01, counts
+
+
+def _random_qubo(n, k, seed):
+    """QUBO on a random graph: each spin coupled to k random others (degrees
+    about 2k), 30% repulsive (+1) and 70% attractive (-U(0.2, 1)) weights."""
+    rng = np.random.default_rng(seed)
+    pairs = set()
+    for i in range(n):
+        for j in rng.integers(0, n, k):
+            if j != i:
+                pairs.add((min(i, int(j)), max(i, int(j))))
+    rows, cols, vals = [], [], []
+    for i, j in sorted(pairs):
+        w = 1.0 if rng.random() < 0.3 else -rng.uniform(0.2, 1.0)
+        rows += [i, j]
+        cols += [j, i]
+        vals += [w, w]
+    b = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    b.sort_indices()
+    return sbt.Qubo(n, rng.uniform(0, 0.7, n), b.indptr.astype(np.int64),
+                    b.indices.astype(np.int32), b.data.copy(), np.zeros((n, 3), np.int64))
+
+
+def _batch_tail_path(q, M):
+    """Agents per item and the couplings past the slots' register capacities
+    (their total over one item's lanes, and the longest) under the batch
+    kernel's layout: A = the largest power of two with n A <= 9216 slots
+    (A <= M), spins by decreasing min(row length, 63) then id, position j =
+    slot * 1024 + thread holding spin rank j / A, capacities 16, 8, 5, 4, 3,
+    2, 2, 2, 1 by slot.  Tails go through LDS when the total fits 8192 words
+    and none is longer than 15, otherwise through global memory."""
+    cap = np.array([16, 8, 5, 4, 3, 2, 2, 2, 1])
+    lg = 0
+    while (2 << lg) <= M and q.n * (2 << lg) <= 9216:
+        lg += 1
+    ln = np.diff(q.row_ptr)
+    perm = np.lexsort((np.arange(q.n), -np.minimum(ln, 63)))
+    j = np.arange(9 * 1024)
+    r = j >> lg
+    ok = r < q.n
+    tails = np.maximum(0, ln[perm[r[ok]]] - cap[j[ok] >> 10])
+    return 1 << lg, int(tails.sum()), int(tails.max())
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+def test_batch_tails_in_lds_and_overflowing_match_oracle(mode, prec):
+    """Rows past their slot's register capacity in both of the batch
+    kernel's tail paths with short tails (no hub): an item whose tails fit
+    the LDS array (n = 2000, four agents per item) and items whose tails
+    overflow it and continue from global memory (n = 6000 with one agent per
+    item, n = 1000 with eight).  Trajectories within 1e-5 of the oracle run
+    with the same rounded couplings over eight steps, except agents the
+    oracle finds within 1e-6 of a wall (or, dSB, of a sign change); returned
+    energies are the FP64 objective of the returned spins."""
+    M, K, seed = 8, 8, 13
+    qs = [_random_qubo(2000, 2, 7), _random_qubo(6000, 4, 7), _random_qubo(1000, 3, 7)]
+    paths = [_batch_tail_path(q, M) for q in qs]
+    assert paths[0][0] == 4 and 0 < paths[0][1] <= 8192 and paths[0][2] <= 15
+    assert paths[1][0] == 1 and paths[1][1] > 8192 and paths[1][2] <= 15
+    assert paths[2][0] == 8 and paths[2][1] > 8192 and paths[2][2] <= 15
+    ds = sbt.DeviceBatchSolver(qs, mode, prec, sbt.solve_params(agents=M, steps=K, seed=seed),
+                               want_agent_energy=True, want_agent_state=True)
+    ds.run()
+    r = ds.result()
+    for e, q in enumerate(qs):
+        b, isg, ref = _oracle_run(q, prec, mode, M, K, seed, e)
+        x = r["agent_x"][e]
+        err = np.linalg.norm(x - ref.x, axis=0) / np.maximum(np.linalg.norm(ref.x, axis=0), 1e-30)
+        close = ref.wall_margin < 1e-6
+        if mode == "dsb":
+            close |= ref.sign_margin < 1e-6
+        assert np.all((err <= 1e-5) | close), (e, err.max())
+        e_or = oenergy.qubo_energy(q.a, b, r["agent_T"][e])
+        assert np.allclose(r["agent_energy"][e], e_or, rtol=1e-12, atol=1e-9)
