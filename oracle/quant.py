@@ -5,7 +5,15 @@ CPU baseline use this package.
 
 The paper fixes no number format for SB; the library offers forms that
 store J in a narrow format while positions, momenta and accumulation stay
-FP32 and energies FP64.  This module writes out the FP8 form:
+FP32 and energies FP64.  This module writes out the 16-bit and FP8 forms:
+
+* IEEE binary16 ("FP16"): 10 stored mantissa bits, exponents -14 .. 15,
+  subnormals k * 2^-24; the coupling used is the FP64 J rounded once to the
+  nearest binary16 value, ties to the even significand.
+* bfloat16 ("BF16"): the upper half of a binary32 (8 exponent bits, 7
+  stored mantissa bits); the FP64 J is first rounded to binary32 (the
+  kernels' coupling type) and that value rounded to the nearest bfloat16,
+  ties to the even significand.
 
 * OCP 8-bit E4M3 ("e4m3fn"): sign bit, 4 exponent bits with bias 7, 3
   mantissa bits; exponent field 0 holds subnormals m/8 * 2^-6; the pattern
@@ -59,6 +67,57 @@ def e4m3_encode(v) -> np.ndarray:
     code = (e.astype(np.int64) << 3) | np.rint(m).astype(np.int64)
     code = np.where(np.signbit(v) & (r > 0), code | 0x80, code)
     return code.astype(np.uint8)
+
+
+def _round_to_grid(v, mant_bits, min_exp):
+    """Round FP64 values to the nearest value with `mant_bits` stored
+    mantissa bits and exponents >= min_exp (subnormals below), ties to the
+    even significand, with no upper bound (callers stay in range).  The
+    spacing at |v| is 2^(max(E, min_exp) - mant_bits), E = floor(log2|v|);
+    v / spacing is exact (a power-of-two scaling) and rint rounds half to
+    even."""
+    v = np.asarray(v, dtype=np.float64)
+    a = np.abs(v)
+    with np.errstate(divide="ignore"):
+        E = np.where(a > 0, np.floor(np.log2(np.where(a > 0, a, 1.0))), float(min_exp))
+    # log2 of a value just below a power of two can round up to it: pull
+    # E back where 2^E exceeds a
+    E = np.where(np.exp2(E) > a, E - 1.0, E)
+    q = np.exp2(np.maximum(E, float(min_exp)) - mant_bits)
+    return np.copysign(np.rint(a / q) * q, v)
+
+
+def fp16_value(v) -> np.ndarray:
+    """FP64 values rounded once to the nearest binary16 value (ties to
+    even), returned as FP64; |v| must stay below 65520 (no overflow)."""
+    v = np.asarray(v, dtype=np.float64)
+    if np.any(np.abs(v) >= 65520.0) or not np.all(np.isfinite(v)):
+        raise ValueError("fp16_value takes finite |v| < 65520")
+    return _round_to_grid(v, 10, -14)
+
+
+def bf16_value(v) -> np.ndarray:
+    """FP64 values rounded to binary32 and then to the nearest bfloat16
+    value (ties to even), returned as FP64."""
+    v32 = np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+    if not np.all(np.isfinite(v32)):
+        raise ValueError("bf16_value takes values finite in binary32")
+    return _round_to_grid(v32, 7, -126)
+
+
+def fp16_couplings(J: sp.csr_matrix) -> sp.csr_matrix:
+    """The FP16 coupling form: every stored J_ij rounded to binary16."""
+    J = sp.csr_matrix(J, dtype=np.float64, copy=True)
+    J.data = fp16_value(J.data)
+    return J
+
+
+def bf16_couplings(J: sp.csr_matrix) -> sp.csr_matrix:
+    """The BF16 coupling form: every stored J_ij rounded to binary32, then
+    to bfloat16."""
+    J = sp.csr_matrix(J, dtype=np.float64, copy=True)
+    J.data = bf16_value(J.data)
+    return J
 
 
 def fp8_rows(J: sp.csr_matrix):

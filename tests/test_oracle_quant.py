@@ -87,3 +87,93 @@ def test_row_form_scales_each_row_to_the_format_maximum():
         assert np.all(err <= 2.0 ** -4 + 1e-6)
     # structure is unchanged
     assert np.array_equal(Jq.indptr, A.indptr) and np.array_equal(Jq.indices, A.indices)
+
+
+# ------------------------------------------------------- 16-bit forms
+
+def _all_finite_fp16():
+    v = np.arange(1 << 16, dtype=np.uint16).view(np.float16)
+    return v[np.isfinite(v)].astype(np.float64)
+
+
+def test_fp16_every_value_midpoint_and_neighbour_matches_numpy():
+    """Every finite binary16 value, every midpoint between neighbours
+    (exact in FP64) and the FP64 values just below and above each midpoint,
+    rounded by the oracle and by NumPy's own float64 -> float16 cast."""
+    v = np.unique(_all_finite_fp16())
+    mids = (v[:-1] + v[1:]) / 2.0
+    cases = np.concatenate([v, mids, np.nextafter(mids, -np.inf), np.nextafter(mids, np.inf)])
+    cases = cases[np.abs(cases) < 65504.0]
+    ref = cases.astype(np.float16).astype(np.float64)
+    assert np.array_equal(quant.fp16_value(cases), ref)
+
+
+def test_fp16_random_couplings_match_numpy():
+    rng = np.random.default_rng(5)
+    v = rng.normal(0, 0.3, 200_000) * np.exp2(rng.integers(-30, 4, 200_000))
+    assert np.array_equal(quant.fp16_value(v), v.astype(np.float16).astype(np.float64))
+
+
+def test_fp16_ties_and_subnormals_by_hand():
+    one_ulp = 2.0 ** -10
+    assert quant.fp16_value(1.0 + one_ulp / 2) == 1.0                 # tie -> even
+    assert quant.fp16_value(1.0 + 1.5 * one_ulp) == 1.0 + 2 * one_ulp  # tie -> even
+    assert quant.fp16_value(2.0 ** -24) == 2.0 ** -24                  # smallest subnormal
+    assert quant.fp16_value(2.0 ** -25) == 0.0                         # tie to zero (even)
+    assert quant.fp16_value(3 * 2.0 ** -26) == 2.0 ** -24
+    assert quant.fp16_value(-0.25) == -0.25
+    with pytest.raises(ValueError):
+        quant.fp16_value(70000.0)
+
+
+def _bf16_grid(lo_exp, hi_exp):
+    """Every positive bfloat16 value with exponent in [lo_exp, hi_exp]
+    (subnormals included when lo_exp <= -126), as FP64."""
+    m = np.arange(128, dtype=np.float64)
+    out = [m * 2.0 ** (-126 - 7)] if lo_exp <= -126 else []
+    for e in range(max(lo_exp, -126), hi_exp + 1):
+        out.append((1.0 + m / 128.0) * 2.0 ** e)
+    return np.unique(np.concatenate(out))
+
+
+def _torch_bf16(v64):
+    t = torch.from_numpy(np.asarray(v64, dtype=np.float64)).to(torch.float32)
+    return t.to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def test_bf16_every_midpoint_and_neighbour_matches_torch():
+    """bfloat16 values from the subnormals to 2^40, the midpoints between
+    neighbours (exact in binary32) and the binary32 values next to each
+    midpoint, both signs, against torch's float32 -> bfloat16 cast."""
+    v = _bf16_grid(-133, 40)
+    mids = (v[:-1] + v[1:]) / 2.0
+    m32 = mids.astype(np.float32)
+    assert np.array_equal(m32.astype(np.float64), mids)
+    cases = np.concatenate([v, mids, np.nextafter(m32, np.float32(-np.inf)).astype(np.float64),
+                            np.nextafter(m32, np.float32(np.inf)).astype(np.float64)])
+    cases = np.concatenate([cases, -cases])
+    assert np.array_equal(quant.bf16_value(cases), _torch_bf16(cases))
+
+
+def test_bf16_rounds_through_binary32_first():
+    """An FP64 value a hair above a bfloat16 midpoint, closer to the
+    midpoint than half a binary32 ulp, becomes the midpoint in binary32 and
+    then ties to even -- the kernels' two-step conversion (torch's cast of
+    the binary32 value agrees)."""
+    lo = 1.0
+    mid = lo + 2.0 ** -8                       # halfway to 1 + 2^-7
+    v = mid + 2.0 ** -30                       # below half a binary32 ulp (2^-24)
+    assert np.float64(np.float32(v)) == mid
+    assert quant.bf16_value(v) == 1.0           # tie -> even (1.0), not up
+    assert _torch_bf16([v])[0] == 1.0
+    rng = np.random.default_rng(8)
+    r = rng.normal(0, 0.3, 200_000) * np.exp2(rng.integers(-40, 4, 200_000))
+    assert np.array_equal(quant.bf16_value(r), _torch_bf16(r))
+
+
+def test_16bit_coupling_forms_keep_the_sparsity():
+    J = sp.random(40, 40, density=0.1, random_state=3, format="csr")
+    for f, g in ((quant.fp16_couplings, quant.fp16_value), (quant.bf16_couplings, quant.bf16_value)):
+        Jq = f(J)
+        assert np.array_equal(Jq.indptr, J.indptr) and np.array_equal(Jq.indices, J.indices)
+        assert np.array_equal(Jq.data, g(J.data))

@@ -245,3 +245,102 @@ def test_asb_has_no_walls_and_odd_symmetry():
     assert np.abs(r1.x).max() > 1.0
     rb = sb.run(J, np.zeros(n), 1.0, "bsb", 4, 200, dt=0.1, x0=x0, y0=y0)
     assert np.abs(rb.x).max() <= 1.0
+
+
+# ------------------------------------------------ checkpoints and margins
+
+def _dense_objective(a, bdense, T):
+    """Eq. 13 as a dense quadratic form per column of T (j < i pairs)."""
+    T = np.asarray(T, dtype=np.float64)
+    return T.T @ a + np.einsum("ik,ij,jk->k", T, np.tril(bdense, -1), T)
+
+
+@pytest.mark.parametrize("every", [1, 3, 4, 7])
+def test_checkpoint_energies_follow_the_free_oscillator(every):
+    """J = 0, h = 0: every spin follows the 2x2 matrix product, so the
+    readout after step k is known independently; the checkpoint energies of
+    an unrelated QUBO (a, b) are then its dense quadratic form at those T,
+    recorded after steps every, 2 every, ... (odd `every` puts checkpoints
+    on odd steps), and the trace is their running minimum over agents."""
+    n, m, K, dt, a0 = 7, 5, 29, 0.5, 1.3
+    a, bcsr, bdense = _qubo_csr(n, 12, density=0.5)
+    from oracle.philox import initial_state
+    x0, y0 = initial_state(n, m, 4)
+    r = sb.run(sp.csr_matrix((n, n)), np.zeros(n), 0.9, "bsb", m, K, dt=dt, a0=a0, seed=4,
+               ckpt_every=every, qubo=(a, bcsr))
+    n_ck = K // every
+    assert r.agent_trace.shape == (n_ck, m) and r.trace.shape == (n_ck,)
+    best = math.inf
+    for c in range(n_ck):
+        k = (c + 1) * every
+        T = np.zeros((n, m), dtype=np.int8)
+        for i in range(n):
+            for j in range(m):
+                v = np.array([x0[i, j], y0[i, j]])
+                for s in range(k):
+                    g = a0 - a0 * s / K
+                    v = np.array([[1.0 - dt * dt * a0 * g, dt * a0], [-dt * g, 1.0]]) @ v
+                T[i, j] = 1 if v[0] >= 0 else 0
+        expect = _dense_objective(a, bdense, T)
+        assert np.allclose(r.agent_trace[c], expect, rtol=0, atol=1e-12), c
+        best = min(best, float(expect.min()))
+        assert r.trace[c] == pytest.approx(best, abs=1e-12)
+    assert np.all(np.diff(r.trace) <= 0)
+
+
+def test_last_checkpoint_is_the_final_readout():
+    ev = tg.generate(tg.plain_spec(30), 5)
+    q = qubo.build_event(ev)
+    isg = ising.from_qubo(q.a, q.b)
+    r = sb.run(isg.J, isg.h, isg.c0, "dsb", 6, 60, seed=2, ckpt_every=20, qubo=(q.a, q.b))
+    E = energy.qubo_energy(q.a, q.b, sb.readout(r.x))
+    assert np.array_equal(r.agent_trace[-1], E)
+    assert r.trace[-1] == min(r.agent_trace.min(), E.min())
+
+
+def test_checkpoints_need_a_qubo():
+    with pytest.raises(ValueError):
+        sb.run(sp.csr_matrix((2, 2)), np.zeros(2), 1.0, "bsb", 1, 4, ckpt_every=2)
+
+
+def test_sign_margin_is_the_smallest_position_used_by_hand():
+    """dSB, J = 0, h = 0, a0 = 1, dt = 1/2, two steps (a_0 = 0, a_1 = 1/2).
+    Spin 0 starts at x = 2^-23, y = 0: step 0 gives y = -2^-24, x =
+    2^-23 - 2^-25 = 3 * 2^-25; step 1 gives y = -2^-24 - 3 * 2^-27 and
+    x = 3 * 2^-25 - 2^-25 - 3 * 2^-28 = 13 * 2^-28.  Spin 1 stays far
+    from zero.  The margin over two steps is the smallest |x| whose sign was
+    used (2^-23, 3 * 2^-25) or read out (13 * 2^-28): 13 * 2^-28 ~ 4.8e-8;
+    over one step it is still the final readout."""
+    x0 = np.array([[2.0 ** -23], [0.5]])
+    y0 = np.zeros((2, 1))
+    J = sp.csr_matrix((2, 2))
+    r = sb.run(J, np.zeros(2), 1.0, "dsb", 1, 2, dt=0.5, x0=x0, y0=y0, margin_steps=2)
+    assert r.x[0, 0] == 13 * 2.0 ** -28
+    assert r.sign_margin[0] == 13 * 2.0 ** -28
+    # a start nearer zero than anything after it is caught at step 0
+    x0 = np.array([[-(2.0 ** -30)], [0.5]])
+    y0 = np.array([[-(2.0 ** -10)], [0.0]])
+    r = sb.run(J, np.zeros(2), 1.0, "dsb", 1, 2, dt=0.5, x0=x0, y0=y0, margin_steps=2)
+    assert r.sign_margin[0] == 2.0 ** -30
+    # margins are per agent: a second agent far from zero keeps its own
+    x0 = np.array([[2.0 ** -23, 0.25], [0.5, -0.5]])
+    r = sb.run(J, np.zeros(2), 1.0, "dsb", 2, 2, dt=0.5, x0=x0, y0=np.zeros((2, 2)),
+               margin_steps=2)
+    assert r.sign_margin[0] == 13 * 2.0 ** -28 and r.sign_margin[1] > 0.1
+
+
+def test_wall_margin_is_the_closest_approach_to_the_wall_by_hand():
+    """bSB, J = 0, h = 0, a0 = dt = 1, one step (a_0 = 0): y' = y - x,
+    x' = x + y' = y, exact for dyadic values.  Agent 0 lands at 1 - 2^-20
+    (inside, margin 2^-20), agent 1 at 1 + 2^-21 (clamped, margin 2^-21),
+    agent 2 at -(1 - 2^-22) (margin 2^-22, sign irrelevant)."""
+    x0 = np.array([[0.5, 0.25, -0.5]])
+    y0 = np.array([[1.0 - 2.0 ** -20, 1.0 + 2.0 ** -21, -(1.0 - 2.0 ** -22)]])
+    r = sb.run(sp.csr_matrix((1, 1)), np.zeros(1), 1.0, "bsb", 3, 1, x0=x0, y0=y0,
+               margin_steps=1)
+    assert list(r.wall_margin) == [2.0 ** -20, 2.0 ** -21, 2.0 ** -22]
+    assert r.x[0, 1] == 1.0 and r.y[0, 1] == 0.0
+    # steps past margin_steps are not logged
+    r = sb.run(sp.csr_matrix((1, 1)), np.zeros(1), 1.0, "bsb", 3, 1, x0=x0, y0=y0,
+               margin_steps=0)
+    assert np.all(np.isinf(r.wall_margin))
