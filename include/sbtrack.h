@@ -237,6 +237,10 @@ typedef struct {
     int32_t best_agent;   /* out: argmin of O over agents, lowest on ties     */
     int32_t kernel_used;  /* out: sbt_kernel that ran                         */
     double elapsed_s;     /* out: device time of the solve (HIP events)       */
+    double *agent_trace;  /* caller [(steps/energy_every) * agents] or NULL:  */
+                          /*   O(T) of every agent at every checkpoint        */
+                          /*   (checkpoint-major; checkpoint c is the state   */
+                          /*   after (c+1) * energy_every steps)              */
 } sbt_result;
 
 /* Solve one QUBO held in host memory: upload, run every step on the GPU,
@@ -280,6 +284,9 @@ typedef struct {
     void *step_begin;     /* hipEvent_t or NULL: recorded on the stream just  */
     void *step_end;       /*   before the first and after the last SB-step    */
                           /*   kernel, to time the step phase                 */
+    double *agent_trace;  /* device [(steps/energy_every) * agents] or NULL:  */
+                          /*   O(T) of every agent at every checkpoint,       */
+                          /*   checkpoint-major (see sbt_result)              */
 } sbt_dev_result;
 
 /* Bytes of device workspace sbt_solve_dev needs for this shape; 0 on
@@ -342,6 +349,9 @@ typedef struct {
                              /*   contiguous, starting at agents * sum_{f<e} n_f) */
     float *agent_x;          /* device [sum n * agents] or NULL: final positions, */
                              /*   same layout                                     */
+    double *agent_trace;     /* device [E * (steps / energy_every) * agents] or   */
+                             /*   NULL: O(T) of every agent at every checkpoint   */
+                             /*   (event-major, then checkpoint, then agent)      */
 } sbt_dev_batch_result;
 
 /* Device workspace bytes for a batch of these sizes (0 on invalid input). */
@@ -378,6 +388,8 @@ typedef struct {
     double *agent_energy;    /* caller [E * agents] or NULL                        */
     double *trace;           /* caller [E * (steps / energy_every)] or NULL        */
     double elapsed_s;        /* out: device time of plan + run                     */
+    double *agent_trace;     /* caller [E * (steps / energy_every) * agents] or    */
+                             /*   NULL: as sbt_dev_batch_result.agent_trace        */
 } sbt_batch_result;
 
 /* Host convenience: validate and upload the QUBOs, plan, run, download. */

@@ -196,6 +196,7 @@ def solve(q: Qubo, mode: str, agents: int = 32, steps: int = 2000, dt: float = 1
     E = np.zeros(agents, dtype=np.float64)
     n_ck = steps // energy_every if energy_every > 0 else 0
     trace = np.zeros(n_ck, dtype=np.float64) if want_trace else None
+    atrace = np.zeros((n_ck, agents), dtype=np.float64) if want_trace and n_ck else None
     xf = np.zeros((q.n, agents), dtype=np.float32) if want_state else None
     yf = np.zeros((q.n, agents), dtype=np.float32) if want_state else None
     r = _lib.SbtResult()
@@ -203,12 +204,15 @@ def solve(q: Qubo, mode: str, agents: int = 32, steps: int = 2000, dt: float = 1
     r.agent_energy = E.ctypes.data_as(C.POINTER(C.c_double))
     if trace is not None:
         r.trace = trace.ctypes.data_as(C.POINTER(C.c_double))
+    if atrace is not None:
+        r.agent_trace = atrace.ctypes.data_as(C.POINTER(C.c_double))
     if xf is not None:
         r.x_final = xf.ctypes.data_as(C.POINTER(C.c_float))
         r.y_final = yf.ctypes.data_as(C.POINTER(C.c_float))
     check(load().sbt_solve(C.byref(s), MODES[mode], C.byref(p), C.byref(r)))
     return {"T": T, "agent_energy": E, "energy": r.energy, "best_agent": int(r.best_agent),
-            "c0": r.c0, "ising_offset": r.ising_offset, "trace": trace, "x": xf, "y": yf,
+            "c0": r.c0, "ising_offset": r.ising_offset, "trace": trace, "agent_trace": atrace,
+            "x": xf, "y": yf,
             "kernel": KERNEL_NAMES[int(r.kernel_used)], "elapsed_s": r.elapsed_s}
 
 
@@ -260,13 +264,15 @@ class DeviceSolver:
         n_ck = params.steps // params.energy_every if params.energy_every > 0 else 0
         self.trace = (torch.empty(n_ck, dtype=torch.float64, device=dev)
                       if want_trace and n_ck > 0 else None)
+        self.agent_trace = (torch.empty((n_ck, M), dtype=torch.float64, device=dev)
+                            if want_trace and n_ck > 0 else None)
         self._dq = _lib.SbtDevQubo(q.n, q.nnz, self.a.data_ptr(), self.row_ptr.data_ptr(),
                                    self.col.data_ptr(), self.b.data_ptr())
         ptr = lambda x: x.data_ptr() if x is not None else None
         self._dr = _lib.SbtDevResult(self.T.data_ptr(), self.agent_energy.data_ptr(),
                                      self.best_energy.data_ptr(), self.best_agent.data_ptr(),
                                      self.scalars.data_ptr(), ptr(self.x), ptr(self.y),
-                                     ptr(self.trace))
+                                     ptr(self.trace), None, None, ptr(self.agent_trace))
         self.max_row = q.max_row_nnz()
         self.kernel = select_kernel(q.n, q.nnz, self.max_row, mode, params)
 
@@ -286,6 +292,8 @@ class DeviceSolver:
                 "x": None if self.x is None else self.x.cpu().numpy(),
                 "y": None if self.y is None else self.y.cpu().numpy(),
                 "trace": None if self.trace is None else self.trace.cpu().numpy(),
+                "agent_trace": (None if self.agent_trace is None
+                                else self.agent_trace.cpu().numpy()),
                 "kernel": self.kernel}
 
 
@@ -324,6 +332,7 @@ def solve_batch(qubos, mode: str, precision: str = "fp16", agents: int = 128,
     ae = np.zeros(E * agents) if want_agent_energy else None
     n_ck = steps // energy_every if energy_every > 0 else 0
     tr = np.zeros(E * n_ck) if want_trace else None
+    atr = np.zeros(E * n_ck * agents) if want_trace and n_ck else None
     r = _lib.SbtBatchResult()
     r.energy = energy_.ctypes.data_as(C.POINTER(C.c_double))
     r.best_agent = best.ctypes.data_as(C.POINTER(C.c_int32))
@@ -332,11 +341,15 @@ def solve_batch(qubos, mode: str, precision: str = "fp16", agents: int = 128,
         r.agent_energy = ae.ctypes.data_as(C.POINTER(C.c_double))
     if tr is not None:
         r.trace = tr.ctypes.data_as(C.POINTER(C.c_double))
+    if atr is not None:
+        r.agent_trace = atr.ctypes.data_as(C.POINTER(C.c_double))
     check(load().sbt_solve_batch(arr, E, MODES[mode], PRECISIONS[precision], C.byref(p),
                                  C.byref(r)))
     return {"energy": energy_, "best_agent": best, "T": _split(T, [q.n for q in qubos]),
             "agent_energy": None if ae is None else ae.reshape(E, agents),
-            "trace": None if tr is None else tr.reshape(E, n_ck), "elapsed_s": r.elapsed_s}
+            "trace": None if tr is None else tr.reshape(E, n_ck),
+            "agent_trace": None if atr is None else atr.reshape(E, n_ck, agents),
+            "elapsed_s": r.elapsed_s}
 
 
 def c0_scan(q: Qubo, mode: str, factors, precision: str = "fp16", agents: int = 128,
@@ -393,6 +406,8 @@ class DeviceBatchSolver:
         self.n_ckpt = n_ck
         self.trace = (torch.empty(E * n_ck, dtype=torch.float64, device=dev)
                       if want_trace and n_ck > 0 else None)
+        self.agent_trace = (torch.empty(E * n_ck * M, dtype=torch.float64, device=dev)
+                            if want_trace and n_ck > 0 else None)
         st = torch.cuda.current_stream()
         self._c0_scale = (None if c0_scale is None
                           else np.ascontiguousarray(c0_scale, dtype=np.float64))
@@ -415,7 +430,8 @@ class DeviceBatchSolver:
         self._dr = _lib.SbtDevBatchResult(self.best_energy.data_ptr(), self.best_agent.data_ptr(),
                                           self.best_T.data_ptr(), ptr(self.agent_energy),
                                           self.offset.data_ptr(), ptr(self.trace), None, None,
-                                          ptr(self.agent_T), ptr(self.agent_x))
+                                          ptr(self.agent_T), ptr(self.agent_x),
+                                          ptr(self.agent_trace))
 
     def run(self, stream=None) -> None:
         st = stream if stream is not None else self.torch.cuda.current_stream()
@@ -435,6 +451,8 @@ class DeviceBatchSolver:
                                  else self.agent_energy.cpu().numpy().reshape(self.E, M)),
                 "trace": (None if self.trace is None
                           else self.trace.cpu().numpy().reshape(self.E, self.n_ckpt)),
+                "agent_trace": (None if self.agent_trace is None else
+                                self.agent_trace.cpu().numpy().reshape(self.E, self.n_ckpt, M)),
                 "agent_T": (None if self.agent_T is None else
                             [v.reshape(-1, M) for v in _split(self.agent_T.cpu().numpy(),
                                                               [s * M for s in self.sizes])]),

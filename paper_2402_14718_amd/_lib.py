@@ -63,7 +63,8 @@ class SbtResult(C.Structure):
                 ("trace", C.POINTER(C.c_double)), ("x_final", C.POINTER(C.c_float)),
                 ("y_final", C.POINTER(C.c_float)), ("energy", C.c_double),
                 ("ising_offset", C.c_double), ("c0", C.c_double), ("best_agent", C.c_int32),
-                ("kernel_used", C.c_int32), ("elapsed_s", C.c_double)]
+                ("kernel_used", C.c_int32), ("elapsed_s", C.c_double),
+                ("agent_trace", C.POINTER(C.c_double))]
 
 
 class SbtDevQubo(C.Structure):
@@ -75,7 +76,7 @@ class SbtDevResult(C.Structure):
     _fields_ = [("T", C.c_void_p), ("agent_energy", C.c_void_p), ("best_energy", C.c_void_p),
                 ("best_agent", C.c_void_p), ("scalars", C.c_void_p), ("x_final", C.c_void_p),
                 ("y_final", C.c_void_p), ("trace", C.c_void_p), ("step_begin", C.c_void_p),
-                ("step_end", C.c_void_p)]
+                ("step_end", C.c_void_p), ("agent_trace", C.c_void_p)]
 
 
 SBT_PREC_FP32 = 0
@@ -93,13 +94,14 @@ class SbtDevBatchResult(C.Structure):
     _fields_ = [("best_energy", C.c_void_p), ("best_agent", C.c_void_p), ("best_T", C.c_void_p),
                 ("agent_energy", C.c_void_p), ("offset", C.c_void_p), ("trace", C.c_void_p),
                 ("step_begin", C.c_void_p), ("step_end", C.c_void_p), ("agent_T", C.c_void_p),
-                ("agent_x", C.c_void_p)]
+                ("agent_x", C.c_void_p), ("agent_trace", C.c_void_p)]
 
 
 class SbtBatchResult(C.Structure):
     _fields_ = [("energy", C.POINTER(C.c_double)), ("best_agent", C.POINTER(C.c_int32)),
                 ("T", C.POINTER(C.c_int8)), ("agent_energy", C.POINTER(C.c_double)),
-                ("trace", C.POINTER(C.c_double)), ("elapsed_s", C.c_double)]
+                ("trace", C.POINTER(C.c_double)), ("elapsed_s", C.c_double),
+                ("agent_trace", C.POINTER(C.c_double))]
 
 
 # (name, restype, argtypes) of every exported function, as in sbtrack.h

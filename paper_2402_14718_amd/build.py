@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["status.cpp", "build_qubo.cpp", "order.cpp", "anneal.cpp"]
+HOST_SOURCES = ["status.cpp", "validate.cpp", "build_qubo.cpp", "order.cpp", "anneal.cpp"]
 RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
 HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_resident_reg_bsb.hip",
                "sb_resident_reg_dsb.hip", "sb_resident_reg_asb.hip", "sb_batch.hip",

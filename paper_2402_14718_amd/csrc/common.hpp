@@ -1,4 +1,5 @@
-// Shared host-side helpers of the sbtrack library: status reporting.
+// Shared host-side helpers of the sbtrack library: status reporting and
+// host-side argument checks.
 #pragma once
 
 #include <cstdarg>
@@ -21,5 +22,12 @@ void clear_error();
 // defaults when pp is NULL), clears *out; SBT_OK or an error status.
 int check_build_inputs(const sbt_hit *hits, int64_t n_hits, const sbt_build_params *pp,
                        sbt_qubo **out, sbt_build_params *p, const char *who);
+
+// Full check of a host QUBO (validate.cpp): n >= 1; row_ptr non-decreasing
+// within [0, nnz] (checked for every row before any row is read); columns
+// in range, ascending, off the diagonal; finite a and b; b symmetric.
+// `what` names the QUBO in messages ("qubo", "event 3").  *max_row (may be
+// NULL) receives the longest row.  SBT_OK or SBT_EINVAL.
+int validate_qubo_host(const sbt_qubo *q, const char *who, const char *what, int32_t *max_row);
 
 }  // namespace sbt

@@ -273,7 +273,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
     if (!workspace || workspace_bytes < L.total)
         return fail(SBT_EINVAL, "%s: workspace of %zu bytes is smaller than the %zu needed", who,
                     workspace_bytes, L.total);
-    if (out->trace && L.n_ckpt == 0)
+    if ((out->trace || out->agent_trace) && L.n_ckpt == 0)
         return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
 
     sbt::ResidentShape shape;
@@ -382,6 +382,9 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
     SBT_HIP(sbt::launch_select_best(n, M, out->agent_energy, xfinal, out->best_energy,
                                     out->best_agent, out->T, st));
     if (out->trace) SBT_HIP(sbt::launch_trace_reduce(L.n_ckpt, M, etrace, out->trace, st));
+    if (out->agent_trace)
+        SBT_HIP(hipMemcpyAsync(out->agent_trace, etrace, sizeof(double) * L.n_ckpt * M,
+                               hipMemcpyDeviceToDevice, st));
     const size_t nm = static_cast<size_t>(n) * M;
     if (out->x_final)
         SBT_HIP(hipMemcpyAsync(out->x_final, xfinal, nm * sizeof(float), hipMemcpyDeviceToDevice, st));
@@ -413,39 +416,6 @@ struct HostStream {
     }
 };
 
-int validate_host_qubo(const sbt_qubo *q, int32_t *max_row) {
-    const char *who = "sbt_solve";
-    if (!q) return fail(SBT_EINVAL, "%s: qubo is NULL", who);
-    if (q->n < 1) return fail(SBT_EINVAL, "%s: empty QUBO (n = %d)", who, q->n);
-    if (!q->a || !q->row_ptr || (q->nnz > 0 && (!q->col || !q->b)))
-        return fail(SBT_EINVAL, "%s: QUBO array is NULL", who);
-    if (q->row_ptr[0] != 0 || q->row_ptr[q->n] != q->nnz)
-        return fail(SBT_EINVAL, "%s: row_ptr does not span [0, nnz]", who);
-    int32_t mr = 0;
-    for (int32_t i = 0; i < q->n; ++i) {
-        if (!std::isfinite(q->a[i])) return fail(SBT_EINVAL, "%s: a[%d] is not finite", who, i);
-        const int64_t lo = q->row_ptr[i], hi = q->row_ptr[i + 1];
-        if (hi < lo) return fail(SBT_EINVAL, "%s: row_ptr decreases at row %d", who, i);
-        mr = std::max<int32_t>(mr, static_cast<int32_t>(hi - lo));
-        for (int64_t e = lo; e < hi; ++e) {
-            const int32_t j = q->col[e];
-            if (j < 0 || j >= q->n) return fail(SBT_EINVAL, "%s: column %d out of range", who, j);
-            if (j == i) return fail(SBT_EINVAL, "%s: diagonal entry in row %d", who, i);
-            if (e > lo && q->col[e - 1] >= j)
-                return fail(SBT_EINVAL, "%s: columns of row %d not ascending", who, i);
-            if (!std::isfinite(q->b[e])) return fail(SBT_EINVAL, "%s: b is not finite", who);
-            // symmetry: b_ji must equal b_ij
-            const int32_t *c0 = q->col + q->row_ptr[j];
-            const int32_t *c1 = q->col + q->row_ptr[j + 1];
-            const int32_t *f = std::lower_bound(c0, c1, i);
-            if (f == c1 || *f != i || q->b[q->row_ptr[j] + (f - c0)] != q->b[e])
-                return fail(SBT_EINVAL, "%s: b is not symmetric at (%d, %d)", who, i, j);
-        }
-    }
-    *max_row = mr;
-    return SBT_OK;
-}
-
 }  // namespace
 
 extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_params *pp,
@@ -462,14 +432,14 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
     int rc = check_params(p, who);
     if (rc) return rc;
     int32_t max_row = 0;
-    rc = validate_host_qubo(q, &max_row);
+    rc = sbt::validate_qubo_host(q, who, "qubo", &max_row);
     if (rc) return rc;
     rc = check_shape(q->n, q->nnz, p.agents, who);
     if (rc) return rc;
     const int32_t n = q->n, M = p.agents;
     const int64_t nnz = q->nnz;
     const int n_ckpt = p.energy_every > 0 ? p.steps / p.energy_every : 0;
-    if (out->trace && n_ckpt == 0)
+    if ((out->trace || out->agent_trace) && n_ckpt == 0)
         return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
 
     std::vector<int32_t> rp32(n + 1);
@@ -477,7 +447,7 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
     const size_t ws_bytes = make_layout(n, nnz, M, p.steps, p.energy_every, mode, p.precision).total;
     const size_t nm = static_cast<size_t>(n) * M;
 
-    DevBuf da, drp, dcol, db, dws, dT, dE, dbe, dbm, dsc, dx, dy, dtr;
+    DevBuf da, drp, dcol, db, dws, dT, dE, dbe, dbm, dsc, dx, dy, dtr, dat;
     auto alloc = [&](DevBuf &b, size_t bytes) {
         return hipMalloc(&b.p, std::max<size_t>(bytes, 1));
     };
@@ -487,7 +457,8 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
         alloc(dbe, sizeof(double)) || alloc(dbm, sizeof(int32_t)) || alloc(dsc, 4 * sizeof(double)) ||
         (out->x_final && alloc(dx, sizeof(float) * nm)) ||
         (out->y_final && alloc(dy, sizeof(float) * nm)) ||
-        (out->trace && alloc(dtr, sizeof(double) * n_ckpt)))
+        (out->trace && alloc(dtr, sizeof(double) * n_ckpt)) ||
+        (out->agent_trace && alloc(dat, sizeof(double) * n_ckpt * M)))
         return fail(SBT_ENOMEM, "%s: device allocation failed", who);
     HostStream hs;
     SBT_HIP(hipStreamCreateWithFlags(&hs.s, hipStreamNonBlocking));
@@ -510,6 +481,7 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
     dr.x_final = static_cast<float *>(dx.p);
     dr.y_final = static_cast<float *>(dy.p);
     dr.trace = static_cast<double *>(dtr.p);
+    dr.agent_trace = static_cast<double *>(dat.p);
     const int kernel = pick_kernel(n, nnz, max_row, mode, p, device_lds_limit(), nullptr);
     if (kernel < 0) return kernel;
     SBT_HIP(hipEventRecord(hs.e0, hs.s));
@@ -530,6 +502,9 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
         SBT_HIP(hipMemcpyAsync(out->y_final, dy.p, sizeof(float) * nm, hipMemcpyDeviceToHost, hs.s));
     if (out->trace)
         SBT_HIP(hipMemcpyAsync(out->trace, dtr.p, sizeof(double) * n_ckpt, hipMemcpyDeviceToHost, hs.s));
+    if (out->agent_trace)
+        SBT_HIP(hipMemcpyAsync(out->agent_trace, dat.p, sizeof(double) * n_ckpt * M,
+                               hipMemcpyDeviceToHost, hs.s));
     SBT_HIP(hipStreamSynchronize(hs.s));
     float ms = 0.0f;
     SBT_HIP(hipEventElapsedTime(&ms, hs.e0, hs.e1));

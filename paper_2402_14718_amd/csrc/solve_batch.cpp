@@ -213,7 +213,7 @@ extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_prec
         return fail(SBT_EINVAL, "%s: batch array is NULL", who);
     if (!out->best_energy || !out->best_agent || !out->best_T)
         return fail(SBT_EINVAL, "%s: result pointer is NULL", who);
-    if (out->trace && L.n_ckpt == 0)
+    if ((out->trace || out->agent_trace) && L.n_ckpt == 0)
         return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
     char *ws = static_cast<char *>(workspace);
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -267,6 +267,10 @@ extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_prec
         e = sbt::launch_batch_select(B, st);
         if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch select: %s", who, hipGetErrorString(e));
     }
+    if (out->agent_trace)
+        SBT_HIP(hipMemcpyAsync(out->agent_trace, B.etrace,
+                               sizeof(double) * S.ev.size() * L.n_ckpt * p->agents,
+                               hipMemcpyDeviceToDevice, st));
     return SBT_OK;
 }
 
@@ -303,23 +307,10 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     int64_t sum_n = 0, sum_nnz = 0;
     for (int32_t e = 0; e < E; ++e) {
         const sbt_qubo *q = qs[e];
-        if (!q || q->n < 1 || !q->a || !q->row_ptr || (q->nnz > 0 && (!q->col || !q->b)))
-            return fail(SBT_EINVAL, "%s: event %d is empty or malformed", who, e);
-        if (q->row_ptr[0] != 0 || q->row_ptr[q->n] != q->nnz)
-            return fail(SBT_EINVAL, "%s: event %d row_ptr does not span [0, nnz]", who, e);
-        for (int32_t i = 0; i < q->n; ++i) {
-            if (!std::isfinite(q->a[i])) return fail(SBT_EINVAL, "%s: event %d: a not finite", who, e);
-            for (int64_t k = q->row_ptr[i]; k < q->row_ptr[i + 1]; ++k) {
-                const int32_t j = q->col[k];
-                if (j < 0 || j >= q->n || j == i || (k > q->row_ptr[i] && q->col[k - 1] >= j) ||
-                    !std::isfinite(q->b[k]))
-                    return fail(SBT_EINVAL, "%s: event %d: malformed row %d", who, e, i);
-                const int32_t *c0 = q->col + q->row_ptr[j], *c1 = q->col + q->row_ptr[j + 1];
-                const int32_t *f = std::lower_bound(c0, c1, i);
-                if (f == c1 || *f != i || q->b[q->row_ptr[j] + (f - c0)] != q->b[k])
-                    return fail(SBT_EINVAL, "%s: event %d: b is not symmetric", who, e);
-            }
-        }
+        char what[32];
+        snprintf(what, sizeof what, "event %d", e);
+        const int vrc = sbt::validate_qubo_host(q, who, what, nullptr);
+        if (vrc) return vrc;
         n[e] = q->n;
         nnz[e] = q->nnz;
         sum_n += q->n;
@@ -349,16 +340,17 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     const size_t ws_bytes = sbt_batch_workspace_bytes(n.data(), nnz.data(), E, &p);
     if (ws_bytes == 0) return SBT_EINVAL;
     const int n_ck = p.energy_every > 0 ? p.steps / p.energy_every : 0;
-    if (out->trace && n_ck == 0)
+    if ((out->trace || out->agent_trace) && n_ck == 0)
         return fail(SBT_EINVAL, "%s: trace requested but energy_every gives no checkpoint", who);
-    DevBuf da, drp, dcol, db, dws, dbe, dba, dbt, dae, dtr;
+    DevBuf da, drp, dcol, db, dws, dbe, dba, dbt, dae, dtr, dat;
     const size_t M = static_cast<size_t>(p.agents);
     if (hipMalloc(&da.p, sizeof(double) * sum_n) || hipMalloc(&drp.p, sizeof(int32_t) * rp.size()) ||
         hipMalloc(&dcol.p, sizeof(int32_t) * col.size()) || hipMalloc(&db.p, sizeof(double) * b.size()) ||
         hipMalloc(&dws.p, ws_bytes) || hipMalloc(&dbe.p, sizeof(double) * E) ||
         hipMalloc(&dba.p, sizeof(int32_t) * E) || hipMalloc(&dbt.p, sum_n) ||
         hipMalloc(&dae.p, sizeof(double) * E * M) ||
-        (out->trace && hipMalloc(&dtr.p, sizeof(double) * E * n_ck)))
+        (out->trace && hipMalloc(&dtr.p, sizeof(double) * E * n_ck)) ||
+        (out->agent_trace && hipMalloc(&dat.p, sizeof(double) * E * n_ck * M)))
         return fail(SBT_ENOMEM, "%s: device allocation failed", who);
     hipStream_t st = nullptr;
     SBT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
@@ -392,6 +384,7 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     dr.best_T = static_cast<int8_t *>(dbt.p);
     dr.agent_energy = static_cast<double *>(dae.p);
     dr.trace = static_cast<double *>(dtr.p);
+    dr.agent_trace = static_cast<double *>(dat.p);
     rc = sbt_batch_run(&dbch, mode, prec, &p, dws.p, ws_bytes, &dr, st);
     if (rc) return rc;
     SBT_HIP(hipEventRecord(e1, st));
@@ -402,6 +395,9 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
         SBT_HIP(hipMemcpyAsync(out->agent_energy, dae.p, sizeof(double) * E * M, hipMemcpyDeviceToHost, st));
     if (out->trace)
         SBT_HIP(hipMemcpyAsync(out->trace, dtr.p, sizeof(double) * E * n_ck, hipMemcpyDeviceToHost, st));
+    if (out->agent_trace)
+        SBT_HIP(hipMemcpyAsync(out->agent_trace, dat.p, sizeof(double) * E * n_ck * M,
+                               hipMemcpyDeviceToHost, st));
     SBT_HIP(hipStreamSynchronize(st));
     float ms = 0.0f;
     SBT_HIP(hipEventElapsedTime(&ms, e0, e1));

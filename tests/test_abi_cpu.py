@@ -209,3 +209,22 @@ def test_permutation_rejects_bad_input():
     with pytest.raises(sbt.SbtError) as e:
         sbt.phi_order(q, hits[:3])                # triplets name hits not given
     assert e.value.code == _lib.SBT_EINVAL
+
+
+@pytest.mark.parametrize("row_ptr,nnz", [([0, 10, 5], 5), ([0, 3, 1, 4], 4), ([0, -2, 4], 4)])
+def test_malformed_row_pointers_rejected_before_rows_are_read(row_ptr, nnz):
+    """A row_ptr that decreases or leaves [0, nnz] between its two ends is
+    refused (SBT_EINVAL) by the single, batch and c0-scan entry points
+    before any row is walked."""
+    n = len(row_ptr) - 1
+    q = sbt.Qubo(n, np.zeros(n), np.array(row_ptr, np.int64),
+                 np.zeros(nnz, np.int32), np.zeros(nnz), np.zeros((n, 3), np.int64))
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve(q, "dsb", agents=4, steps=5)
+    assert e.value.code == _lib.SBT_EINVAL and "row_ptr" in str(e.value)
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve_batch([q], "dsb", "fp16", agents=4, steps=5)
+    assert e.value.code == _lib.SBT_EINVAL and "row_ptr" in str(e.value)
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.c0_scan(q, "dsb", [1.0, 2.0], agents=4, steps=5)
+    assert e.value.code == _lib.SBT_EINVAL and "row_ptr" in str(e.value)

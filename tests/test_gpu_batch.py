@@ -2,8 +2,9 @@
 the C ABI) against the FP64 oracle.
 
 The batch holds couplings in 16 bits (FP16 or BF16).  The oracle is run
-with the same rounded couplings (FP16: one rounding of the FP64 J; BF16:
-FP64 -> FP32 -> BF16 round-to-nearest-even), everything else in FP64, so
+with the same rounded couplings (``oracle.quant``: FP16 is one rounding of
+the FP64 J; BF16 is FP64 -> FP32 -> BF16, round to nearest even; both
+pinned against NumPy's and torch's own conversions), everything else in FP64, so
 the FP32 trajectories must stay within 1e-5 relative over 50 steps as for
 the FP32 path.  Energies of the returned spins are exact FP64 (1e-9); the
 quality against plain FP32 solves is compared at full length.
@@ -15,6 +16,7 @@ import scipy.sparse as sp
 import trackgen as tg
 from oracle import energy as oenergy
 from oracle import ising as oising
+from oracle import quant as oquant
 from oracle import sb as osb
 from oracle import tracks as otracks
 
@@ -27,17 +29,7 @@ if not torch.cuda.is_available():
 import paper_2402_14718_amd as sbt  # noqa: E402
 
 
-def q_fp16(J):
-    return J.astype(np.float16).astype(np.float64)
-
-
-def q_bf16(J):
-    u = J.astype(np.float32).view(np.uint32).astype(np.uint64)
-    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return r.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-QUANT = {"fp16": q_fp16, "bf16": q_bf16}
+QUANT = {"fp16": oquant.fp16_value, "bf16": oquant.bf16_value}
 
 
 def _events(specs_seeds):
@@ -212,7 +204,7 @@ def test_c0_scan_copies_match_oracle_with_scaled_c0(dt, K):
     b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(q.n, q.n))
     isg = oising.from_qubo(q.a, b)
     Jq = isg.J.copy()
-    Jq.data = q_fp16(Jq.data)
+    Jq.data = oquant.fp16_value(Jq.data)
     for k, f in enumerate(factors):
         ref = osb.run(Jq, isg.h, isg.c0 * f, "dsb", M, K, dt=dt, seed=seed, event=0,
                       margin_steps=K)
