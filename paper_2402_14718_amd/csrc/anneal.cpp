@@ -103,8 +103,10 @@ extern "C" int sbt_anneal_cpu(const sbt_qubo *q, const sbt_anneal_params *pp, in
     const char *who = "sbt_anneal_cpu";
     sbt::clear_error();
     if (!q || !T_best || !energy) return sbt::fail(SBT_EINVAL, "%s: NULL argument", who);
-    if (q->n < 1 || !q->a || !q->row_ptr || (q->nnz > 0 && (!q->col || !q->b)))
-        return sbt::fail(SBT_EINVAL, "%s: empty or malformed QUBO", who);
+    // flips update the neighbours' local fields from row i's entries, which
+    // needs b symmetric as well as well formed
+    const int vrc = sbt::validate_qubo_host(q, who, "qubo", nullptr);
+    if (vrc) return vrc;
     sbt_anneal_params p;
     if (pp)
         p = *pp;
@@ -112,15 +114,9 @@ extern "C" int sbt_anneal_cpu(const sbt_qubo *q, const sbt_anneal_params *pp, in
         sbt_anneal_params_default(&p);
     if (p.shots < 1 || p.sweeps < 1 || p.threads < 0)
         return sbt::fail(SBT_EINVAL, "%s: shots and sweeps must be >= 1, threads >= 0", who);
-    if (q->row_ptr[0] != 0 || q->row_ptr[q->n] != q->nnz)
-        return sbt::fail(SBT_EINVAL, "%s: row_ptr does not span [0, nnz]", who);
-    for (int64_t k = 0; k < q->nnz; ++k)
-        if (q->col[k] < 0 || q->col[k] >= q->n || !std::isfinite(q->b[k]))
-            return sbt::fail(SBT_EINVAL, "%s: malformed coupling %lld", who, static_cast<long long>(k));
     // default temperatures from the coefficient ranges
     double dmax = 0.0, dmin = std::numeric_limits<double>::infinity();
     for (int32_t i = 0; i < q->n; ++i) {
-        if (!std::isfinite(q->a[i])) return sbt::fail(SBT_EINVAL, "%s: a[%d] not finite", who, i);
         double row = std::fabs(q->a[i]);
         if (q->a[i] != 0.0) dmin = std::min(dmin, std::fabs(q->a[i]));
         for (int64_t k = q->row_ptr[i]; k < q->row_ptr[i + 1]; ++k) {

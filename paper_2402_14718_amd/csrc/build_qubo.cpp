@@ -434,6 +434,8 @@ extern "C" void sbt_qubo_free(sbt_qubo *q) {
 extern "C" int sbt_energy(const sbt_qubo *q, const int8_t *T, double *energy) {
     sbt::clear_error();
     if (!q || !T || !energy) return sbt::fail(SBT_EINVAL, "sbt_energy: NULL argument");
+    const int vrc = sbt::validate_qubo_structure(q, "sbt_energy", "qubo");
+    if (vrc) return vrc;
     // Neumaier-compensated sum of a_i T_i and b_ij T_i T_j over j > i
     double s = 0.0, c = 0.0;
     auto add = [&](double v) {

@@ -30,4 +30,8 @@ int check_build_inputs(const sbt_hit *hits, int64_t n_hits, const sbt_build_para
 // NULL) receives the longest row.  SBT_OK or SBT_EINVAL.
 int validate_qubo_host(const sbt_qubo *q, const char *who, const char *what, int32_t *max_row);
 
+// The array structure alone (n >= 0 allowed; row_ptr non-decreasing from 0
+// to nnz, columns in range): what reading every row safely needs.
+int validate_qubo_structure(const sbt_qubo *q, const char *who, const char *what);
+
 }  // namespace sbt

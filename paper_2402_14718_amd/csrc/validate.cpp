@@ -13,6 +13,23 @@
 
 namespace sbt {
 
+int validate_qubo_structure(const sbt_qubo *q, const char *who, const char *what) {
+    if (!q) return fail(SBT_EINVAL, "%s: %s is NULL", who, what);
+    if (q->n < 0 || q->nnz < 0) return fail(SBT_EINVAL, "%s: %s has a negative size", who, what);
+    if (q->n == 0) return SBT_OK;
+    if (!q->a || !q->row_ptr || (q->nnz > 0 && (!q->col || !q->b)))
+        return fail(SBT_EINVAL, "%s: %s has a NULL array", who, what);
+    if (q->row_ptr[0] != 0 || q->row_ptr[q->n] != q->nnz)
+        return fail(SBT_EINVAL, "%s: %s row_ptr does not span [0, nnz]", who, what);
+    for (int32_t i = 0; i < q->n; ++i)
+        if (q->row_ptr[i + 1] < q->row_ptr[i])
+            return fail(SBT_EINVAL, "%s: %s row_ptr decreases at row %d", who, what, i);
+    for (int64_t e = 0; e < q->nnz; ++e)
+        if (q->col[e] < 0 || q->col[e] >= q->n)
+            return fail(SBT_EINVAL, "%s: %s column %d out of range", who, what, q->col[e]);
+    return SBT_OK;
+}
+
 int validate_qubo_host(const sbt_qubo *q, const char *who, const char *what, int32_t *max_row) {
     if (!q) return fail(SBT_EINVAL, "%s: %s is NULL", who, what);
     if (q->n < 1) return fail(SBT_EINVAL, "%s: %s is empty (n = %d)", who, what, q->n);
