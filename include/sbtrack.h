@@ -308,6 +308,23 @@ int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
                   const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
                   const sbt_dev_result *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as sbt_solve_dev with no workspace argument.  Its scratch lives in
+ * a fixed array of SBT_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends; the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  Inputs and
+ * outputs are the caller's device buffers, as for sbt_solve_dev.
+ * All calls on one device share that array and it keeps the last call's
+ * contents, so calls that overlap on one device (other streams, other host
+ * threads) race: serialise them.
+ * Errors: SBT_EINVAL when sbt_workspace_bytes for this shape exceeds
+ * SBT_NOALLOC_SCRATCH_BYTES (checked before any device call), otherwise as
+ * sbt_solve_dev. */
+#define SBT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int sbt_solve_dev_noalloc(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
+                          const sbt_solve_params *p, const sbt_dev_result *out, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches of events (HIP)
  *

@@ -283,6 +283,16 @@ class DeviceSolver:
                                    C.byref(self.params), C.c_void_p(self.workspace.data_ptr()),
                                    self.ws_bytes, C.byref(self._dr), C.c_void_p(st.cuda_stream)))
 
+    def run_noalloc(self, stream=None) -> None:
+        """The same solve through sbt_solve_dev_noalloc: scratch from the
+        library's fixed per-device array instead of this object's
+        workspace (for callers that cannot allocate)."""
+        torch = self.torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        check(load().sbt_solve_dev_noalloc(C.byref(self._dq), self.max_row, MODES[self.mode],
+                                           C.byref(self.params), C.byref(self._dr),
+                                           C.c_void_p(st.cuda_stream)))
+
     def result(self) -> dict:
         self.torch.cuda.synchronize()
         return {"T": self.T.cpu().numpy(), "agent_energy": self.agent_energy.cpu().numpy(),

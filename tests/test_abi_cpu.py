@@ -228,3 +228,22 @@ def test_malformed_row_pointers_rejected_before_rows_are_read(row_ptr, nnz):
     with pytest.raises(sbt.SbtError) as e:
         sbt.c0_scan(q, "dsb", [1.0, 2.0], agents=4, steps=5)
     assert e.value.code == _lib.SBT_EINVAL and "row_ptr" in str(e.value)
+
+
+def test_noalloc_entry_point_refuses_oversized_shapes_before_any_device_call():
+    """sbt_solve_dev_noalloc checks the workspace this shape needs against
+    its fixed array before touching a device (the pointers here are never
+    read), and rejects invalid parameters the same way."""
+    lib = sbt.load()
+    fake = C.c_void_p(0x1000)
+    dq = _lib.SbtDevQubo(1480, 2722, fake, fake, fake, fake)
+    dr = _lib.SbtDevResult(fake, fake, fake, fake)
+    p = sbt.solve_params(agents=8192, steps=100)
+    need = sbt.workspace_bytes(1480, 2722, "bsb", p)
+    assert need > 64 << 20
+    rc = lib.sbt_solve_dev_noalloc(C.byref(dq), 12, _lib.SBT_BSB, C.byref(p), C.byref(dr), None)
+    assert rc == _lib.SBT_EINVAL
+    assert "limit" in lib.sbt_last_error().decode()
+    p = sbt.solve_params(agents=0)
+    rc = lib.sbt_solve_dev_noalloc(C.byref(dq), 12, _lib.SBT_BSB, C.byref(p), C.byref(dr), None)
+    assert rc == _lib.SBT_EINVAL
