@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Simulated-bifurcation throughput on one MI355X.
 
-Workload ("plain"): one synthetic barrel event -- 10 layers at
-r = 32 ... 1020 mm, 2 T, 200 helical particles (pT log-uniform 0.5-20 GeV,
-|eta| < 1.5) plus 10% noise hits, event seed 100 -- turned into the triplet
-QUBO by the library's host builder (not timed, as in the paper).  One bench
-step is a complete solve of that QUBO in both SB forms, bSB and dSB, each
-with 256 agents x 5000 symplectic-Euler steps: Ising preparation, Philox
-start, all steps, FP64 energies of every agent and best-agent selection,
-all on the GPU with the QUBO already resident in HBM.
+Headline workload ("batching"): 512 synthetic barrel events -- 10 layers at
+r = 32 ... 1020 mm, 2 T, 20 + floor(981 U) helical particles each (pT
+log-uniform 0.5-20 GeV, |eta| < 1.5) plus 10% noise hits, event seeds
+1000-1511 -- turned into triplet QUBOs by the library's GPU builder (not
+timed, as in the paper).  One bench step is a complete batched dSB solve
+of all 512 events, 128 agents x 3000 symplectic-Euler steps each, in one
+persistent kernel with BF16 couplings (FP32 state and accumulation): Ising
+preparation, Philox start, every step, FP64 energies of every agent and the
+best agent per event, all on the GPU with the QUBOs already resident in HBM.
 
-Prints one JSON line with spin-updates/s (N * agents * steps * 2 forms per
-bench step), the roofline position of the SB step kernel (timed live with
-HIP events on its stream), the time to reach the FP64 oracle's best energy
-within 0.5%, and the oracle timed on the host on a bounded sample.
+Prints one JSON line with spin-updates/s (sum N * agents * steps per bench
+step), the roofline position of the batch step kernel (timed live with HIP
+events on its stream), time-to-target against the FP64 oracle's best energy
+of every event (the same solve with FP16 couplings, and plain FP32 solving
+the events one at a time, beside it), the plain, precision and stress
+workloads as extra keys, and the oracle timed on the host on a bounded
+sample.
 """
 from __future__ import annotations
 
@@ -177,20 +181,13 @@ def precision_form(sbt, tg, torch, np):
     return out
 
 
-def batched_form(sbt, tg, torch, np, with_fp32=True, gpu_build=True):
-    """512 events of 20-1000 particles, dSB, 128 agents x 3000 steps: one
-    persistent batched kernel (FP16 / BF16 couplings) against plain FP32
-    solving the events one at a time.  Per-event energies are compared with
-    the plain FP32 results (the FP64 oracle cannot run this batch); the
-    checkpoint time-to-target is the time until every event's best-so-far
-    FP64 O(T) is within 0.5% of its FP32 best (FP32: the sum over events of
-    each solve's time to its own first such checkpoint)."""
+def batching_qubos(sbt, tg, gpu_build=True):
+    """The 512 batching events: hits from trackgen, QUBOs built on the GPU
+    (wall time, downloads included), the host builder timed on a sample of
+    events whose structure must match (every event, and no GPU construction,
+    with gpu_build=False)."""
     specs = tg.batching_specs()
     hits = [tg.generate(s, seed).hits_struct() for s, seed in specs]
-    # QUBO construction of every event on the GPU (wall time, downloads
-    # included); the host builder timed on a sample of events, whose
-    # structure must match (on every event, and no GPU construction, with
-    # --batch-host-build)
     sample = 64 if gpu_build else len(hits)
     t0 = time.perf_counter()
     host = [sbt.build_qubo(h) for h in hits[:sample]]
@@ -204,17 +201,127 @@ def batched_form(sbt, tg, torch, np, with_fp32=True, gpu_build=True):
     qs = [q for q, _ in built]
     same = all(np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col, b.col) and
                np.array_equal(a.trip_hits, b.trip_hits) for a, b in zip(qs, host))
-    M, K = 128, 3000
+    info = {"gpu_all_events_s": gpu_build_s,
+            "gpu_device_s": float(sum(d for _, d in built)) if gpu_build else None,
+            "host_all_events_s_from_sample": host_sample_s * len(qs) / sample,
+            "host_sample": f"first {sample} events, {host_sample_s:.2f} s",
+            "same_structure_on_sample": bool(same) if gpu_build else None}
+    return qs, info
+
+
+BATCH_M, BATCH_K = 128, 3000
+
+
+def batch_step_phase(bs, torch):
+    """Duration of the batch step kernel (every step of every event) from
+    the library's HIP events, recorded on the launch stream around it."""
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record()
+    e.record()
+    torch.cuda.synchronize()
+    bs._dr.step_begin, bs._dr.step_end = b.cuda_event, e.cuda_event
+    bs.run()
+    torch.cuda.synchronize()
+    bs._dr.step_begin = bs._dr.step_end = None
+    return b.elapsed_time(e) * 1e-3
+
+
+def batch_roofline(launch_s, sum_n, sum_nnz, prec):
+    """ALU roofline of the batch step kernel: useful FP32 flops (an FMA per
+    stored coupling and 8 per spin update, per agent and step) over its
+    measured duration."""
+    flops = float(BATCH_K) * BATCH_M * (2.0 * sum_nnz + 8.0 * sum_n)
+    achieved = flops / launch_s / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": MI355X_FP32_VECTOR_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_VECTOR_TFLOPS,
+            "peak_without_packed_fp32": MI355X_FP32_UNPACKED_TFLOPS,
+            "frac_without_packed_fp32": achieved / MI355X_FP32_UNPACKED_TFLOPS,
+            "traffic": measured_traffic(f"sb_batch_batching_{prec}.md"),
+            "lds": measured_lds(f"sb_batch_batching_{prec}.md"),
+            "kernel": "sb_batch", "launch_ms": launch_s * 1e3, "flops_per_launch": flops}
+
+
+def batch_ttt(sbt, torch, qs, prec, targets):
+    """Checkpoint time-to-target of one batched solve of all events, measured
+    inside the launch: the kernel stamps the device wall clock when each
+    agent's work item starts and when each of its checkpoint energies is
+    known; event e reaches its target at the earliest stamp of a checkpoint
+    energy at or below it; the batch at the latest such event time, counted
+    from the first item's start, plus the per-event preparation before the
+    step kernel (HIP events)."""
+    bt = sbt.DeviceBatchSolver(qs, "dsb", prec, sbt.solve_params(
+        agents=BATCH_M, steps=BATCH_K, seed=0, energy_every=TTT_EVERY), want_trace=True,
+        want_clock=True)
+    bt.run()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for x in ev:
+        x.record()
+    torch.cuda.synchronize()
+    bt._dr.step_begin, bt._dr.step_end = ev[1].cuda_event, ev[2].cuda_event
+    ev[0].record()
+    bt.run()
+    torch.cuda.synchronize()
+    bt._dr.step_begin = bt._dr.step_end = None
+    prep_s = ev[0].elapsed_time(ev[1]) * 1e-3
+    r = bt.result()
+    hz = sbt.wall_clock_hz()
+    clk, at = r["ckpt_clock"].astype(np.float64), r["agent_trace"]
+    t_first = clk[:, 0, :].min()
+    per_event = np.full(len(qs), np.nan)
+    for e in range(len(qs)):
+        hit = at[e] <= targets[e]
+        if hit.any():
+            per_event[e] = (clk[e, 1:, :][hit].min() - t_first) / hz
+    reached = ~np.isnan(per_event)
+    out = {"events_reached": int(reached.sum()), "prep_s": prep_s,
+           "kernel_s": ev[1].elapsed_time(ev[2]) * 1e-3,
+           "seconds": (prep_s + float(np.nanmax(per_event))) if reached.all() else None,
+           "median_event_s": float(np.nanmedian(per_event)) if reached.any() else None}
+    del bt
+    return out
+
+
+def batching_form(sbt, tg, torch, np, qs, build_info, gold, warmup, steps, with_fp32=True):
+    """512 events of 20-1000 particles, dSB, 128 agents x 3000 steps: one
+    persistent batched kernel (BF16 / FP16 couplings, FP32 state and
+    accumulation, FP64 energies) against plain FP32 solving the events one
+    at a time; time-to-target against the FP64 oracle's best per event
+    (tests/golden/oracle_best_batching.json, written by the oracle only)."""
+    M, K = BATCH_M, BATCH_K
     sum_n = sum(q.n for q in qs)
     sum_nnz = sum(q.nnz for q in qs)
+    e_star = np.array([g["best"] for g in gold["per_event"]])
+    assert [g["n"] for g in gold["per_event"]] == [q.n for q in qs], "golden events differ"
+    targets = e_star + 0.005 * np.abs(e_star)
     out = {"workload": "batching: 512 events, 20 + floor(981 U) particles (U from seed 999), "
                        "event seeds 1000-1511; dSB, 128 agents x 3000 steps",
-           "events": len(qs), "sum_n": sum_n, "max_n": max(q.n for q in qs),
-           "qubo_build": {"gpu_all_events_s": gpu_build_s,
-                          "gpu_device_s": float(sum(d for _, d in built)) if gpu_build else None,
-                          "host_all_events_s_from_sample": host_sample_s * len(qs) / sample,
-                          "host_sample": f"first {sample} events, {host_sample_s:.2f} s",
-                          "same_structure_on_sample": bool(same) if gpu_build else None}}
+           "events": len(qs), "sum_n": sum_n, "sum_nnz": sum_nnz, "max_n": max(q.n for q in qs),
+           "qubo_build": build_info,
+           "oracle_best": "FP64 oracle (C), same agents, steps, seed and Philox streams, "
+                          "per event: tests/golden/oracle_best_batching.json"}
+    for prec in ("bf16", "fp16"):
+        bs = sbt.DeviceBatchSolver(qs, "dsb", prec, sbt.solve_params(agents=M, steps=K, seed=0))
+        for _ in range(warmup):
+            bs.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            bs.run()
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / steps
+        launch_s = float(np.mean([batch_step_phase(bs, torch) for _ in range(2)]))
+        res = bs.result()
+        gap = (res["energy"] - e_star) / np.abs(e_star)
+        out[prec] = {"seconds": tb, "spin_updates_per_s": sum_n * M * K / tb,
+                     "work_items": bs.n_items,
+                     "roofline": batch_roofline(launch_s, sum_n, sum_nnz, prec),
+                     "rel_gap_to_oracle_best": {"mean": float(gap.mean()), "max": float(gap.max()),
+                                                "min": float(gap.min())},
+                     "events_within_0.5pct_of_oracle": int(np.sum(res["energy"] <= targets)),
+                     "ttt_checkpoint": batch_ttt(sbt, torch, qs, prec, targets)}
+        del bs
+        log(f"batching: {prec} batch {tb * 1e3:.1f} ms")
     if with_fp32:
         plain = [sbt.DeviceSolver(q, "dsb", sbt.solve_params(agents=M, steps=K, seed=0, event=e))
                  for e, q in enumerate(qs)]
@@ -225,11 +332,14 @@ def batched_form(sbt, tg, torch, np, with_fp32=True, gpu_build=True):
 
         t = timed_runs(run_plain, torch, reps=1)
         e32 = np.array([float(s.best_energy.item()) for s in plain])
-        out["fp32_one_event_at_a_time"] = {"seconds": t, "spin_updates_per_s": sum_n * M * K / t}
         del plain
-        # checkpoint time-to-target against each event's FP32 best: every
-        # event's best-so-far within 0.5% of it
-        target = e32 + 0.005 * np.abs(e32)
+        gap = (e32 - e_star) / np.abs(e_star)
+        fp32 = {"seconds": t, "spin_updates_per_s": sum_n * M * K / t,
+                "rel_gap_to_oracle_best": {"mean": float(gap.mean()), "max": float(gap.max()),
+                                           "min": float(gap.min())},
+                "events_within_0.5pct_of_oracle": int(np.sum(e32 <= targets))}
+        # time-to-target one event at a time: each solve's duration (HIP
+        # events) up to its first checkpoint at or below the target
         traced = [sbt.DeviceSolver(q, "dsb", sbt.solve_params(agents=M, steps=K, seed=0, event=e,
                                                              energy_every=TTT_EVERY),
                                    want_trace=True) for e, q in enumerate(qs)]
@@ -243,56 +353,27 @@ def batched_form(sbt, tg, torch, np, with_fp32=True, gpu_build=True):
             s.run()
             e.record()
         torch.cuda.synchronize()
-        ttt32 = 0.0
+        ttt32, reached = 0.0, 0
         for e, (s, (b0, e0)) in enumerate(zip(traced, pairs)):
-            hit = np.nonzero(s.result()["trace"] <= target[e])[0]
-            ttt32 += b0.elapsed_time(e0) * 1e-3 * (hit[0] + 1) * TTT_EVERY / K
-        out["fp32_one_event_at_a_time"]["ttt_checkpoint_all_events"] = ttt32
+            hit = np.nonzero(s.result()["trace"] <= targets[e])[0]
+            solve_s = b0.elapsed_time(e0) * 1e-3
+            if hit.size:
+                reached += 1
+                ttt32 += solve_s * (hit[0] + 1) * TTT_EVERY / K
+            else:
+                ttt32 += solve_s
+        fp32["ttt_checkpoint"] = {"events_reached": reached,
+                                  "seconds": ttt32 if reached == len(qs) else None,
+                                  "seconds_counting_unreached_as_full_solves": ttt32}
         del traced
-        log("batched form: FP32 one event at a time done")
-    for prec in ("fp16", "bf16"):
-        bs = sbt.DeviceBatchSolver(qs, "dsb", prec, sbt.solve_params(agents=M, steps=K, seed=0))
-        tb = timed_runs(bs.run, torch, reps=2)
-        # the batch kernel's own duration, on its stream, from the library's step events
-        b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        b.record()
-        e.record()
-        torch.cuda.synchronize()
-        bs._dr.step_begin, bs._dr.step_end = b.cuda_event, e.cuda_event
-        bs.run()
-        torch.cuda.synchronize()
-        bs._dr.step_begin = bs._dr.step_end = None
-        launch_s = b.elapsed_time(e) * 1e-3
-        flops = float(K) * M * (2.0 * sum_nnz + 8.0 * sum_n)
-        achieved = flops / launch_s / 1e12
-        out[prec] = {"seconds": tb, "spin_updates_per_s": sum_n * M * K / tb,
-                     "work_items": bs.n_items,
-                     "roofline": {"bound": "alu", "achieved": achieved,
-                                  "peak": MI355X_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                                  "frac": achieved / MI355X_FP32_VECTOR_TFLOPS,
-                                  "peak_without_packed_fp32": MI355X_FP32_UNPACKED_TFLOPS,
-                                  "frac_without_packed_fp32": achieved / MI355X_FP32_UNPACKED_TFLOPS,
-                                  "traffic": measured_traffic(f"sb_batch_batching_{prec}.md"),
-                                  "lds": measured_lds(f"sb_batch_batching_{prec}.md"),
-                                  "kernel": "sb_batch", "launch_ms": launch_s * 1e3}}
-        if with_fp32:
-            bt = sbt.DeviceBatchSolver(qs, "dsb", prec, sbt.solve_params(
-                agents=M, steps=K, seed=0, energy_every=TTT_EVERY), want_trace=True)
-            tt = timed_runs(bt.run, torch, reps=1)
-            tr = bt.result()["trace"]
-            ok = np.all(tr <= target[:, None], axis=0)
-            out[prec]["ttt_checkpoint_all_events"] = (
-                None if not ok.any() else tt * (int(np.argmax(ok)) + 1) * TTT_EVERY / K)
-            del bt
-            gap = (bs.result()["energy"] - e32) / np.abs(e32)
-            out[prec].update({"speedup_vs_fp32": t / tb,
-                              "rel_energy_gap_vs_fp32": {"mean": float(gap.mean()),
-                                                         "max": float(gap.max()),
-                                                         "min": float(gap.min())},
-                              "events_within_0.5pct_of_fp32": int(np.sum(gap <= 0.005))})
-        log(f"batched form: {prec} batch done")
-    # hits to every event's best spins on the GPU: construction + one batch
-    out["end_to_end_fp16_s"] = None if gpu_build_s is None else gpu_build_s + out["fp16"]["seconds"]
+        out["fp32_one_event_at_a_time"] = fp32
+        for prec in ("bf16", "fp16"):
+            out[prec]["speedup_vs_fp32"] = t / out[prec]["seconds"]
+            a, b = out[prec]["ttt_checkpoint"]["seconds"], fp32["ttt_checkpoint"]["seconds"]
+            out[prec]["ttt_speedup_vs_fp32"] = (b / a) if (a and b) else None
+        log("batching: FP32 one event at a time done")
+    if build_info.get("gpu_all_events_s") is not None:
+        out["end_to_end_bf16_s"] = build_info["gpu_all_events_s"] + out["bf16"]["seconds"]
     return out
 
 
@@ -434,7 +515,7 @@ def _sized_run(run_one, target_s):
     return k, time.perf_counter() - t0
 
 
-def _oracle_form_rate(qs, mode, agents, target_s, threads_used):
+def _oracle_form_rate(qs, mode, agents, target_s, threads_used, events=None):
     """C oracle (all host threads) on the QUBOs `qs`: spin-updates/s from the
     difference of a 2-step run and a longer one (x4 until the difference
     reaches half of target_s), so the per-run copies of the state and the
@@ -451,7 +532,7 @@ def _oracle_form_rate(qs, mode, agents, target_s, threads_used):
         t0 = time.perf_counter()
         for e, isg in enumerate(isgs):
             threads_used[0] = sb_c.run(isg.J, isg.h, isg.c0, mode, agents, k, seed=SOLVER_SEED,
-                                       event=e)[2]
+                                       event=events[e] if events else e)[2]
         return time.perf_counter() - t0
 
     t_lo = run(2)
@@ -465,18 +546,14 @@ def _oracle_form_rate(qs, mode, agents, target_s, threads_used):
 
 
 def cpu_forms_baseline(sbt, tg, target_s=4.0):
-    """The C oracle on every host thread for the precision, batching and
-    stress workloads (a bounded number of steps each; per-step cost is
-    constant, so the rate carries over to the full step counts)."""
+    """The C oracle on every host thread for the precision and stress
+    workloads (a bounded number of steps each; per-step cost is constant, so
+    the rate carries over to the full step counts)."""
     used = [0]
     ref = load_golden("oracle_best_precision.json")
     out = {"precision": _oracle_form_rate(
         [sbt.build_qubo(tg.generate(tg.precision_spec(), ref["event_seed"]).hits_struct())],
         "dsb", 1024, target_s, used)}
-    qs = [sbt.build_qubo_gpu(tg.generate(sp_, seed).hits_struct())[0]
-          for sp_, seed in tg.batching_specs()]
-    out["batching"] = _oracle_form_rate(qs, "dsb", 128, target_s, used)
-    del qs
     ev = tg.generate(tg.stress_spec(), 300)
     bp = sbt.build_params_default()
     bp.z0_max = tg.STRESS_Z0_MAX
@@ -523,69 +600,13 @@ def cpu_baseline(q, target_s=8.0):
                           f"({dt1:.1f} s)"}}
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10, help="timed bench steps")
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-ttt", action="store_true")
-    ap.add_argument("--no-forms", action="store_true",
-                    help="skip the precision (1000 particles), batched (512 events) and stress "
-                         "(5000 particles) forms")
-    ap.add_argument("--only", choices=["precision", "batched", "stress"],
-                    help="run only this form and print it (for profiling one kernel)")
-    ap.add_argument("--batch-skip-fp32", action="store_true",
-                    help="batched form without the FP32 one-event-at-a-time comparison "
-                         "(for counter collection)")
-    ap.add_argument("--batch-host-build", action="store_true",
-                    help="batched form on host-built QUBOs, without the GPU builder's "
-                         "launches (for counter collection)")
-    ap.add_argument("--stress-steps", type=int, default=10000,
-                    help="SB steps of the stress form (10000 is the workload's)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 3}))
-        return
-    if args.gpus != 1:
-        print("bench.py measures one GPU; the solver shards over agents with no per-step "
-              "communication, so --gpus N > 1 is not run", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import paper_2402_14718_amd as sbt
-    import trackgen as tg
-
-    if not torch.cuda.is_available():
-        print("bench.py: no HIP device", file=sys.stderr)
-        sys.exit(1)
-    if args.only:
-        form = {"precision": lambda: precision_form(sbt, tg, torch, np),
-                "batched": lambda: batched_form(sbt, tg, torch, np, not args.batch_skip_fp32,
-                                                not args.batch_host_build),
-                "stress": lambda: stress_form(sbt, tg, torch, np, args.stress_steps)}[args.only]
-        print(json.dumps({f"{args.only}_form": form()}), flush=True)
-        return
-    log("building the event QUBO on the host")
-    ev = tg.generate(tg.plain_spec(), EVENT_SEED)
-    q = sbt.build_qubo(ev.hits_struct())
-    log(f"N={q.n} nnz={q.nnz} agents={AGENTS} sb_steps={SB_STEPS}")
-
-    solvers = []
-    for mode in ("bsb", "dsb"):
-        p = sbt.solve_params(agents=AGENTS, steps=SB_STEPS, seed=SOLVER_SEED, kernel=args.kernel)
-        solvers.append(sbt.DeviceSolver(q, mode, p))
+def plain_form(sbt, tg, torch, q, kernel_choice, warmup, steps, with_ttt=True):
+    """The plain workload (200 particles, N ~ 1.5e3): one complete FP32 solve
+    in each SB form, bSB and dSB, 256 agents x 5000 steps, on the resident
+    kernel, with its ALU roofline and time-to-target against the oracle."""
+    solvers = [sbt.DeviceSolver(q, mode, sbt.solve_params(agents=AGENTS, steps=SB_STEPS,
+                                                          seed=SOLVER_SEED, kernel=kernel_choice))
+               for mode in ("bsb", "dsb")]
     kernel = solvers[0].kernel
     stream = torch.cuda.current_stream()
 
@@ -595,16 +616,14 @@ def main():
         e.record(stream)
         return b, e
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         for s in solvers:
             s.run()
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps), kernel={kernel}")
-
-    pairs = [[event_pair() for _ in solvers] for _ in range(args.steps)]
+    pairs = [[event_pair() for _ in solvers] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         for s, (b, e) in zip(solvers, pairs[k]):
             s._dr.step_begin = b.cuda_event
             s._dr.step_end = e.cuda_event
@@ -614,13 +633,8 @@ def main():
     step_ms = [b.elapsed_time(e) for row in pairs for (b, e) in row]
     for s in solvers:
         s._dr.step_begin = s._dr.step_end = None
-    log(f"timed {args.steps} steps in {elapsed:.3f} s")
-
-    updates = 2.0 * q.n * AGENTS * SB_STEPS * args.steps
-    value = updates / elapsed
     launches_per_solve = 1 if kernel == "resident" else SB_STEPS
-    phase_s = float(np.mean(step_ms)) * 1e-3
-    launch_s = phase_s / launches_per_solve
+    launch_s = float(np.mean(step_ms)) * 1e-3 / launches_per_solve
     flops = step_flops(q.n, q.nnz, AGENTS, SB_STEPS) / launches_per_solve
     bytes_ = step_bytes(q.n, q.nnz, AGENTS, SB_STEPS) / launches_per_solve
     if kernel == "resident":
@@ -635,31 +649,22 @@ def main():
                 "state_bytes_if_streamed_GBs": bytes_ / launch_s / 1e9}
     else:
         achieved = bytes_ / launch_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / MI355X_HBM_GBS, "traffic": None, "kernel": "sb_stream",
+        roof = {"bound": "cache-resident", "achieved_GBs": achieved, "kernel": "sb_stream",
                 "launch_ms": launch_s * 1e3}
-
-    result = {
-        "metric": "SB spin-updates/s + time-to-best-energy, BF16/FP8 batched vs plain FP32 SB",
-        "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "plain: 10-layer barrel, 200 particles + 10% noise, event seed 100; "
-                               "bSB and dSB, 256 agents x 5000 steps, CSR FP32",
-                   "n": q.n, "nnz": q.nnz, "agents": AGENTS, "sb_steps": SB_STEPS,
-                   "forms": ["bsb", "dsb"], "kernel": kernel},
-        "roofline": roof,
-    }
-
-    if not args.no_ttt:
+    out = {"workload": "plain: 10-layer barrel, 200 particles + 10% noise, event seed 100; "
+                       "bSB and dSB, 256 agents x 5000 steps, CSR FP32",
+           "n": q.n, "nnz": q.nnz, "kernel": kernel, "seconds_bsb_plus_dsb": elapsed / steps,
+           "spin_updates_per_s": 2.0 * q.n * AGENTS * SB_STEPS * steps / elapsed,
+           "roofline": roof}
+    del solvers
+    if with_ttt:
         ref = load_golden("oracle_best_plain.json")
         ttt = {"definitions": TTT_DEFINITIONS}
         for mode in ("bsb", "dsb"):
             e_star = ref["modes"][mode]["best"]
             mk = lambda K, every=0, mode=mode: sbt.DeviceSolver(
                 q, mode, sbt.solve_params(agents=AGENTS, steps=K, seed=SOLVER_SEED,
-                                          kernel=args.kernel, energy_every=every),
+                                          kernel=kernel_choice, energy_every=every),
                 want_trace=every > 0)
             ck = ttt_checkpoint(mk(SB_STEPS, TTT_EVERY), SB_STEPS, e_star + 0.005 * abs(e_star),
                                 torch)
@@ -683,24 +688,139 @@ def main():
         ttt["sa_cpu"] = {"target": target, "shots": 50, "cores": os.cpu_count(),
                          "ttt99": best,
                          "note": "single-flip Metropolis annealing on the host, all cores"}
-        result["time_to_target"] = ttt
-        log("time-to-target done")
+        out["time_to_target"] = ttt
+    return out
+
+
+def batching_cpu_baseline(qs, target_s=12.0):
+    """The C FP64 oracle on every host thread, on a bounded sample of the
+    batching workload: every 8th event (64 of 512, all sizes), 128 agents,
+    as many steps as fill about target_s (per-step cost is constant, so the
+    rate carries over to the 3000-step solve), as spin-updates/s."""
+    used = [0]
+    r = _oracle_form_rate(qs[::8], "dsb", BATCH_M, target_s, used, events=list(range(0, len(qs), 8)))
+    return {"value": r["spin_updates_per_s"], "unit": "spin-updates/s", "cores": used[0],
+            "kind": "oracle",
+            "sample": f"C FP64 oracle (oracle/sb_omp.c, OpenMP over agents), dSB, every 8th "
+                      f"batching event (64 events, sum N {sum(q.n for q in qs[::8])}), "
+                      f"{BATCH_M} agents x ({r['steps']}) steps, {r['seconds']:.1f} s on "
+                      f"{used[0]} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed bench steps (batched solves)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true",
+                    help="skip the FP32 one-event-at-a-time comparison of the batching workload")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the plain (200 particles), precision (1000 particles) and stress "
+                         "(5000 particles) workloads and the c0 scan")
+    ap.add_argument("--only", choices=["plain", "precision", "batched", "stress"],
+                    help="run only this workload and print it (for profiling one kernel)")
+    ap.add_argument("--batch-host-build", action="store_true",
+                    help="batching workload on host-built QUBOs, without the GPU builder's "
+                         "launches (for counter collection)")
+    ap.add_argument("--stress-steps", type=int, default=10000,
+                    help="SB steps of the stress form (10000 is the workload's)")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 4, "copies": 3}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU; the solver shards over agents with no per-step "
+              "communication, so --gpus N > 1 is not run", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2402_14718_amd as sbt
+    import trackgen as tg
+
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        sys.exit(1)
+
+    def plain_q():
+        return sbt.build_qubo(tg.generate(tg.plain_spec(), EVENT_SEED).hits_struct())
+
+    if args.only:
+        if args.only == "batched":
+            qs, info = batching_qubos(sbt, tg, not args.batch_host_build)
+            form = lambda: batching_form(sbt, tg, torch, np, qs, info,
+                                         load_golden("oracle_best_batching.json"), args.warmup,
+                                         args.steps, with_fp32=not args.no_fp32)
+        else:
+            form = {"plain": lambda: plain_form(sbt, tg, torch, plain_q(), args.kernel,
+                                                args.warmup, args.steps, with_ttt=False),
+                    "precision": lambda: precision_form(sbt, tg, torch, np),
+                    "stress": lambda: stress_form(sbt, tg, torch, np, args.stress_steps)}[args.only]
+        print(json.dumps({f"{args.only}_form": form()}), flush=True)
+        return
+
+    log("building the 512 batching QUBOs")
+    qs, info = batching_qubos(sbt, tg, not args.batch_host_build)
+    gold = load_golden("oracle_best_batching.json")
+    log(f"batching: sum N = {sum(q.n for q in qs)}, {len(qs)} events")
+    bf = batching_form(sbt, tg, torch, np, qs, info, gold, args.warmup, args.steps,
+                       with_fp32=not args.no_fp32)
+    head = bf["bf16"]
+    result = {
+        "metric": "SB spin-updates/s + time-to-best-energy, BF16/FP8 batched vs plain FP32 SB",
+        "value": head["spin_updates_per_s"], "unit": "spin-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["seconds"] * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 couplings, f32 state+accumulate, f64 energies", "data": "synthetic",
+        "config": {"workload": "batching: 512 synthetic barrel events (20-1000 particles + 10% "
+                               "noise), one persistent batched dSB solve, 128 agents x 3000 steps "
+                               "per event, BF16 couplings; compared with plain FP32 solving one "
+                               "event at a time",
+                   "events": bf["events"], "sum_n": bf["sum_n"], "sum_nnz": bf["sum_nnz"],
+                   "max_n": bf["max_n"], "agents": BATCH_M, "sb_steps": BATCH_K,
+                   "precision": "bf16", "kernel": "sb_batch", "work_items": head["work_items"]},
+        "roofline": head["roofline"],
+        "time_to_target": {
+            "definition": "time from the first kernel until every event's best-so-far FP64 "
+                          "O(T) (checkpoints every 50 steps, inside the timed solve) is at or "
+                          "below E* + 0.005 |E*|, E* the FP64 oracle's best for that event "
+                          "with the same agents, steps and seed; null if an event never gets "
+                          "there",
+            "bf16_batch": head["ttt_checkpoint"], "fp16_batch": bf["fp16"]["ttt_checkpoint"],
+            "fp32_one_event_at_a_time": (bf.get("fp32_one_event_at_a_time") or {}).get(
+                "ttt_checkpoint"),
+            "bf16_speedup_vs_fp32": head.get("ttt_speedup_vs_fp32")},
+        "batching_form": bf,
+    }
+    log(f"headline: {result['value']:.3e} spin-updates/s, {result['ms_per_step']:.1f} ms per batch")
 
     if not args.no_forms:
+        q = plain_q()
+        result["plain_form"] = plain_form(sbt, tg, torch, q, args.kernel, 2, 10)
+        log("plain form done")
         result["precision_form"] = precision_form(sbt, tg, torch, np)
         log("precision form done")
-        result["batched_form"] = batched_form(sbt, tg, torch, np)
-        log("batched form done")
         result["stress_form"] = stress_form(sbt, tg, torch, np, args.stress_steps)
         log("stress form done")
         result["c0_scan"] = c0_scan_form(sbt, q, torch)
         log("c0 scan done")
 
     if not args.no_cpu_baseline:
-        log("timing the oracle on the host (bounded sample)")
-        result["cpu_baseline"] = cpu_baseline(q)
+        log("timing the C oracle on the host (bounded sample of the batching workload)")
+        result["cpu_baseline"] = batching_cpu_baseline(qs)
         if not args.no_forms:
-            log("timing the C oracle on the other workloads (bounded samples)")
+            log("timing the oracle on the other workloads (bounded samples)")
+            result["cpu_baseline"]["plain"] = cpu_baseline(plain_q())
             result["cpu_baseline"]["forms"] = cpu_forms_baseline(sbt, tg)
     print(json.dumps(result), flush=True)
 

@@ -369,11 +369,61 @@ typedef struct {
     double *agent_trace;     /* device [E * (steps / energy_every) * agents] or   */
                              /*   NULL: O(T) of every agent at every checkpoint   */
                              /*   (event-major, then checkpoint, then agent)      */
+    int64_t *ckpt_clock;     /* device [E * (steps / energy_every + 1) * agents]  */
+                             /*   or NULL: device wall-clock ticks (see           */
+                             /*   sbt_wall_clock_hz) when each agent's work item  */
+                             /*   starts (slot 0) and when its checkpoint c       */
+                             /*   energy is known (slot c + 1); for measuring     */
+                             /*   time-to-target inside the one batch launch      */
 } sbt_dev_batch_result;
 
-/* Device workspace bytes for a batch of these sizes (0 on invalid input). */
+/* How a batch is scheduled: which events run on which step-kernel shape
+ * and how many agents a work item holds.  Scheduling only: every agent
+ * performs the same step arithmetic in the same order under any tuning, so
+ * positions and assignments are bit-identical; the FP64 energies are summed
+ * in an order that follows the schedule and agree to rounding.
+ * Shapes: 1024 threads per workgroup, one workgroup per CU (any n up to
+ * 9216), and 512 threads, two workgroups per CU (n up to 4608), each with 9
+ * position slots per thread.  The 1024-thread items run first, then the
+ * 512-thread items, each as one persistent launch over its own queue. */
+typedef struct {
+    int32_t split_n;     /* events with n <= split_n (and n <= 4608) run on the */
+                         /*   512-thread shape; 0 = every event on 1024 threads */
+    int32_t tail_words;  /* LDS words per workgroup for couplings past the     */
+                         /*   register capacity of their slot, 0..8192          */
+    double fill;         /* an item holds A agents, A the largest power of two */
+                         /*   with n A <= fill x (slots of its shape), A <=    */
+                         /*   agents and A <= threads; fill in (0, 1]          */
+    int32_t from_cache;  /* out of sbt_batch_tuning_lookup: 1 = tuned entry    */
+    int32_t reserved;    /* must be 0                                          */
+} sbt_batch_tuning;
+
+/* split_n = 0, tail_words = 8192, fill = 1 (what the untuned entry points
+ * use). */
+void sbt_batch_tuning_default(sbt_batch_tuning *t);
+
+/* The tuning cache key of a batch: mode, precision, agents and a histogram
+ * of event sizes (counts of n <= 64, <= 128, ..., <= 16384).  key receives a
+ * NUL-terminated string of at most key_len bytes. */
+int sbt_batch_tuning_key(const int32_t *n, int32_t n_events, sbt_mode mode, sbt_precision prec,
+                         int32_t agents, char *key, size_t key_len);
+
+/* The tuned schedule for a batch from the project's tuning cache (a JSON
+ * file written by the tuner, paper_2402_14718_amd/autotune.py; path from
+ * the environment variable SBT_BATCH_TUNING_CACHE, else tuning/
+ * batch_tuning.json beside the library; read once per process): the entry
+ * with this batch's key, else the entry of the same mode, precision and
+ * agents whose normalised size histogram is nearest (L1 distance <= 0.25),
+ * else the defaults (out->from_cache tells which). */
+int sbt_batch_tuning_lookup(const int32_t *n, int32_t n_events, sbt_mode mode,
+                            sbt_precision prec, int32_t agents, sbt_batch_tuning *out);
+
+/* Device workspace bytes for a batch of these sizes (0 on invalid input),
+ * with the default tuning / with tuning t (NULL = default). */
 size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz, int32_t n_events,
                                  const sbt_solve_params *p);
+size_t sbt_batch_workspace_bytes_tuned(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                                       const sbt_solve_params *p, const sbt_batch_tuning *t);
 
 /* Upload the batch's schedule (event descriptors and the ordered work
  * items) into `workspace` on `stream`.  Call once per (batch shape,
@@ -388,6 +438,11 @@ size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz, int32_t n
 int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
                    const double *c0_scale, int32_t same_start, const sbt_solve_params *p,
                    void *workspace, size_t workspace_bytes, void *stream);
+/* The same with tuning t (NULL = default); run the batch with the same t. */
+int sbt_batch_plan_tuned(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                         const double *c0_scale, int32_t same_start, const sbt_solve_params *p,
+                         const sbt_batch_tuning *t, void *workspace, size_t workspace_bytes,
+                         void *stream);
 
 /* Solve every event of a planned batch: per-event Ising preparation and
  * spin ordering, all steps of all agents of all events in one persistent
@@ -396,6 +451,15 @@ int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
 int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_precision prec,
                   const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
                   const sbt_dev_batch_result *out, void *stream);
+/* The same with tuning t (NULL = default), which must be the plan's. */
+int sbt_batch_run_tuned(const sbt_dev_batch *batch, sbt_mode mode, sbt_precision prec,
+                        const sbt_solve_params *p, const sbt_batch_tuning *t, void *workspace,
+                        size_t workspace_bytes, const sbt_dev_batch_result *out, void *stream);
+
+/* Tick rate of the device wall clock that sbt_dev_batch_result.ckpt_clock
+ * reads (a constant-rate counter, independent of the shader clock), for
+ * the current device. */
+int sbt_wall_clock_hz(double *hz);
 
 /* Host-memory results of sbt_solve_batch. */
 typedef struct {
@@ -409,7 +473,8 @@ typedef struct {
                              /*   NULL: as sbt_dev_batch_result.agent_trace        */
 } sbt_batch_result;
 
-/* Host convenience: validate and upload the QUBOs, plan, run, download. */
+/* Host convenience: validate and upload the QUBOs, plan, run, download,
+ * with the tuned schedule from sbt_batch_tuning_lookup. */
 int sbt_solve_batch(const sbt_qubo *const *qs, int32_t n_events, sbt_mode mode,
                     sbt_precision prec, const sbt_solve_params *p, sbt_batch_result *out);
 

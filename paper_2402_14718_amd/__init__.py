@@ -362,6 +362,13 @@ def solve_batch(qubos, mode: str, precision: str = "fp16", agents: int = 128,
             "elapsed_s": r.elapsed_s}
 
 
+def wall_clock_hz() -> float:
+    """sbt_wall_clock_hz: tick rate of the device wall clock."""
+    hz = C.c_double()
+    check(load().sbt_wall_clock_hz(C.byref(hz)))
+    return float(hz.value)
+
+
 def c0_scan(q: Qubo, mode: str, factors, precision: str = "fp16", agents: int = 128,
             steps: int = 3000, dt: float = 1.0, a0: float = 1.0, c0: float = 0.0,
             seed: int = 0, event: int = 0) -> dict:
@@ -380,13 +387,47 @@ def c0_scan(q: Qubo, mode: str, factors, precision: str = "fp16", agents: int = 
             "factor": float(f[best.value])}
 
 
+def batch_tuning(split_n: int = 0, tail_words: int = 8192, fill: float = 1.0):
+    """An explicit sbt_batch_tuning."""
+    t = _lib.SbtBatchTuning()
+    load().sbt_batch_tuning_default(C.byref(t))
+    t.split_n, t.tail_words, t.fill = int(split_n), int(tail_words), float(fill)
+    return t
+
+
+def tuning_dict(t: _lib.SbtBatchTuning) -> dict:
+    return {"split_n": int(t.split_n), "tail_words": int(t.tail_words), "fill": float(t.fill),
+            "from_cache": bool(t.from_cache)}
+
+
+def batch_tuning_key(sizes, mode: str, precision: str, agents: int) -> str:
+    """sbt_batch_tuning_key of a batch of events with these n."""
+    n = np.ascontiguousarray(sizes, dtype=np.int32)
+    buf = C.create_string_buffer(256)
+    check(load().sbt_batch_tuning_key(n.ctypes.data_as(C.POINTER(C.c_int32)), n.shape[0],
+                                      MODES[mode], PRECISIONS[precision], agents, buf, 256))
+    return buf.value.decode()
+
+
+def batch_tuning_lookup(sizes, mode: str, precision: str, agents: int) -> _lib.SbtBatchTuning:
+    """sbt_batch_tuning_lookup: the cached tuning of a batch, or the defaults."""
+    n = np.ascontiguousarray(sizes, dtype=np.int32)
+    t = _lib.SbtBatchTuning()
+    check(load().sbt_batch_tuning_lookup(n.ctypes.data_as(C.POINTER(C.c_int32)), n.shape[0],
+                                         MODES[mode], PRECISIONS[precision], agents, C.byref(t)))
+    return t
+
+
 class DeviceBatchSolver:
     """sbt_batch_plan once, then sbt_batch_run per call, every buffer held by
-    torch on a HIP device (events concatenated)."""
+    torch on a HIP device (events concatenated).  `tuning`: None = the
+    library's cached tuning for this batch (sbt_batch_tuning_lookup),
+    "default" = the untuned schedule, or an sbt_batch_tuning."""
 
     def __init__(self, qubos, mode: str, precision: str, params: _lib.SbtSolveParams,
                  device="cuda", want_agent_energy: bool = False, want_trace: bool = False,
-                 want_agent_state: bool = False, c0_scale=None, same_start: bool = False):
+                 want_agent_state: bool = False, c0_scale=None, same_start: bool = False,
+                 want_clock: bool = False, tuning=None):
         import torch
         self.torch = torch
         self.mode, self.precision, self.params = mode, precision, params
@@ -402,7 +443,13 @@ class DeviceBatchSolver:
         lib = load()
         np_ = n.ctypes.data_as(C.POINTER(C.c_int32))
         nz_ = nnz.ctypes.data_as(C.POINTER(C.c_int64))
-        self.ws_bytes = int(lib.sbt_batch_workspace_bytes(np_, nz_, E, C.byref(params)))
+        if tuning is None:
+            tuning = batch_tuning_lookup(n, mode, precision, params.agents)
+        elif isinstance(tuning, str) and tuning == "default":
+            tuning = batch_tuning()
+        self.tuning = tuning
+        self.ws_bytes = int(lib.sbt_batch_workspace_bytes_tuned(np_, nz_, E, C.byref(params),
+                                                                C.byref(tuning)))
         if self.ws_bytes == 0:
             raise SbtError(_lib.SBT_EINVAL, lib.sbt_last_error().decode())
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
@@ -418,6 +465,8 @@ class DeviceBatchSolver:
                       if want_trace and n_ck > 0 else None)
         self.agent_trace = (torch.empty(E * n_ck * M, dtype=torch.float64, device=dev)
                             if want_trace and n_ck > 0 else None)
+        self.ckpt_clock = (torch.zeros(E * (n_ck + 1) * M, dtype=torch.int64, device=dev)
+                           if want_clock else None)
         st = torch.cuda.current_stream()
         self._c0_scale = (None if c0_scale is None
                           else np.ascontiguousarray(c0_scale, dtype=np.float64))
@@ -425,9 +474,9 @@ class DeviceBatchSolver:
             raise ValueError("c0_scale must have one entry per event")
         cs = (None if self._c0_scale is None
               else self._c0_scale.ctypes.data_as(C.POINTER(C.c_double)))
-        rc = lib.sbt_batch_plan(np_, nz_, E, cs, 1 if same_start else 0, C.byref(params),
-                                C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
-                                C.c_void_p(st.cuda_stream))
+        rc = lib.sbt_batch_plan_tuned(np_, nz_, E, cs, 1 if same_start else 0, C.byref(params),
+                                      C.byref(tuning), C.c_void_p(self.workspace.data_ptr()),
+                                      self.ws_bytes, C.c_void_p(st.cuda_stream))
         if rc < 0:
             check(rc)
         self.n_items = rc
@@ -441,14 +490,19 @@ class DeviceBatchSolver:
                                           self.best_T.data_ptr(), ptr(self.agent_energy),
                                           self.offset.data_ptr(), ptr(self.trace), None, None,
                                           ptr(self.agent_T), ptr(self.agent_x),
-                                          ptr(self.agent_trace))
+                                          ptr(self.agent_trace), ptr(self.ckpt_clock))
 
     def run(self, stream=None) -> None:
         st = stream if stream is not None else self.torch.cuda.current_stream()
-        check(load().sbt_batch_run(C.byref(self._db), MODES[self.mode],
-                                   PRECISIONS[self.precision], C.byref(self.params),
-                                   C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
-                                   C.byref(self._dr), C.c_void_p(st.cuda_stream)))
+        check(load().sbt_batch_run_tuned(C.byref(self._db), MODES[self.mode],
+                                         PRECISIONS[self.precision], C.byref(self.params),
+                                         C.byref(self.tuning),
+                                         C.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                                         C.byref(self._dr), C.c_void_p(st.cuda_stream)))
+
+    def plan_info(self) -> dict:
+        """The tuning this batch runs with and its work-item count."""
+        return dict(tuning_dict(self.tuning), work_items=self.n_items)
 
     def result(self) -> dict:
         self.torch.cuda.synchronize()
@@ -463,6 +517,8 @@ class DeviceBatchSolver:
                           else self.trace.cpu().numpy().reshape(self.E, self.n_ckpt)),
                 "agent_trace": (None if self.agent_trace is None else
                                 self.agent_trace.cpu().numpy().reshape(self.E, self.n_ckpt, M)),
+                "ckpt_clock": (None if self.ckpt_clock is None else
+                               self.ckpt_clock.cpu().numpy().reshape(self.E, self.n_ckpt + 1, M)),
                 "agent_T": (None if self.agent_T is None else
                             [v.reshape(-1, M) for v in _split(self.agent_T.cpu().numpy(),
                                                               [s * M for s in self.sizes])]),
@@ -473,6 +529,7 @@ class DeviceBatchSolver:
 
 __all__ = ["Qubo", "DeviceSolver", "DeviceBatchSolver", "build_qubo", "energy", "solve",
            "phi_order", "permute_qubo", "build_qubo_gpu", "c0_scan", "anneal_cpu",
-           "solve_batch", "solve_params", "workspace_bytes", "select_kernel",
+           "solve_batch", "solve_params", "wall_clock_hz", "batch_tuning",
+           "batch_tuning_key", "batch_tuning_lookup", "tuning_dict", "workspace_bytes", "select_kernel",
            "build_params_default", "version", "load", "SbtError", "HIT_DTYPE", "MODES",
            "KERNELS", "PRECISIONS"]

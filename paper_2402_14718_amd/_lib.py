@@ -94,7 +94,13 @@ class SbtDevBatchResult(C.Structure):
     _fields_ = [("best_energy", C.c_void_p), ("best_agent", C.c_void_p), ("best_T", C.c_void_p),
                 ("agent_energy", C.c_void_p), ("offset", C.c_void_p), ("trace", C.c_void_p),
                 ("step_begin", C.c_void_p), ("step_end", C.c_void_p), ("agent_T", C.c_void_p),
-                ("agent_x", C.c_void_p), ("agent_trace", C.c_void_p)]
+                ("agent_x", C.c_void_p), ("agent_trace", C.c_void_p),
+                ("ckpt_clock", C.c_void_p)]
+
+
+class SbtBatchTuning(C.Structure):
+    _fields_ = [("split_n", C.c_int32), ("tail_words", C.c_int32), ("fill", C.c_double),
+                ("from_cache", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SbtBatchResult(C.Structure):
@@ -138,12 +144,29 @@ EXPORTS = [
                                         C.c_void_p]),
     ("sbt_batch_workspace_bytes", C.c_size_t, [C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                                C.c_int32, C.POINTER(SbtSolveParams)]),
+    ("sbt_batch_workspace_bytes_tuned", C.c_size_t,
+     [C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int32, C.POINTER(SbtSolveParams),
+      C.POINTER(SbtBatchTuning)]),
+    ("sbt_batch_tuning_default", None, [C.POINTER(SbtBatchTuning)]),
+    ("sbt_batch_tuning_key", C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.c_int, C.c_int,
+                                       C.c_int32, C.c_char_p, C.c_size_t]),
+    ("sbt_batch_tuning_lookup", C.c_int, [C.POINTER(C.c_int32), C.c_int32, C.c_int, C.c_int,
+                                          C.c_int32, C.POINTER(SbtBatchTuning)]),
+    ("sbt_batch_plan_tuned", C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int32,
+                                       C.POINTER(C.c_double), C.c_int32,
+                                       C.POINTER(SbtSolveParams), C.POINTER(SbtBatchTuning),
+                                       C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("sbt_batch_run_tuned", C.c_int, [C.POINTER(SbtDevBatch), C.c_int, C.c_int,
+                                      C.POINTER(SbtSolveParams), C.POINTER(SbtBatchTuning),
+                                      C.c_void_p, C.c_size_t, C.POINTER(SbtDevBatchResult),
+                                      C.c_void_p]),
     ("sbt_batch_plan", C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_int32,
                                  C.POINTER(C.c_double), C.c_int32, C.POINTER(SbtSolveParams),
                                  C.c_void_p, C.c_size_t, C.c_void_p]),
     ("sbt_batch_run", C.c_int, [C.POINTER(SbtDevBatch), C.c_int, C.c_int,
                                 C.POINTER(SbtSolveParams), C.c_void_p, C.c_size_t,
                                 C.POINTER(SbtDevBatchResult), C.c_void_p]),
+    ("sbt_wall_clock_hz", C.c_int, [C.POINTER(C.c_double)]),
     ("sbt_solve_batch", C.c_int, [C.POINTER(C.POINTER(SbtQubo)), C.c_int32, C.c_int, C.c_int,
                                   C.POINTER(SbtSolveParams), C.POINTER(SbtBatchResult)]),
     ("sbt_c0_scan", C.c_int, [C.POINTER(SbtQubo), C.c_int, C.c_int, C.POINTER(SbtSolveParams),

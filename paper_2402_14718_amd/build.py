@@ -24,15 +24,19 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["status.cpp", "validate.cpp", "build_qubo.cpp", "order.cpp", "anneal.cpp"]
+HOST_SOURCES = ["status.cpp", "validate.cpp", "build_qubo.cpp", "order.cpp", "anneal.cpp",
+                "batch_tuning.cpp"]
 RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
 HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_resident_reg_bsb.hip",
                "sb_resident_reg_dsb.hip", "sb_resident_reg_asb.hip", "sb_batch.hip",
                "sb_stream.hip", "build_qubo_gpu.hip", "solve_noalloc.hip"]
 # one source built several times: (source, object tag, extra flags) -- the
-# batched step kernel once per (mode, coupling format), in parallel
-HIP_VARIANTS = [("sb_batch_mode.hip", f"{m}_{j}", [f"-DSBT_BATCH_MODE={mi}", f"-DSBT_BATCH_JP={ji}"])
-                for mi, m in enumerate(("bsb", "dsb", "asb")) for ji, j in enumerate(("fp16", "bf16"))]
+# batched step kernel once per (mode, coupling format, workgroup shape), in
+# parallel
+HIP_VARIANTS = [("sb_batch_mode.hip", f"{m}_{j}_{tpb}",
+                 [f"-DSBT_BATCH_MODE={mi}", f"-DSBT_BATCH_JP={ji}", f"-DSBT_BATCH_TPB={tpb}"])
+                for mi, m in enumerate(("bsb", "dsb", "asb")) for ji, j in enumerate(("fp16", "bf16"))
+                for tpb in (1024, 512)]
 # the GPU QUBO builder evaluates the host builder's cut expressions: no
 # floating-point contraction, like the host file
 HIP_EXTRA_FLAGS = {"build_qubo_gpu.hip": ["-ffp-contract=off"]}
@@ -78,7 +82,7 @@ def build(verbose: bool = False) -> str:
     objs = [obj for _, obj in jobs]
     tmp = LIB_PATH + ".tmp"
     _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp,
-          f"-L{ROCM}/lib", "-lamdhip64", "-pthread", f"-Wl,-rpath,{ROCM}/lib"], verbose)
+          f"-L{ROCM}/lib", "-lamdhip64", "-ldl", "-pthread", f"-Wl,-rpath,{ROCM}/lib"], verbose)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

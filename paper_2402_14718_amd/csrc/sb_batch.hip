@@ -1,7 +1,7 @@
 // Batched SB over many events (gfx950): per-event preparation, the work
-// counter, best-agent selection, and the dispatch to the step kernel of
-// each mode and coupling format (sb_batch_step.hpp, instantiated once per
-// pair by sb_batch_mode.hip).
+// counters, best-agent selection, and the dispatch to the step kernel of
+// each mode, coupling format and workgroup shape (sb_batch_step.hpp,
+// instantiated once per triple by sb_batch_mode.hip).
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
@@ -86,7 +86,9 @@ __global__ __launch_bounds__(256) void batch_prep(BatchArgs B, int jprec) {
     }
 }
 
-__global__ void batch_reset(int *counter) { *counter = 0; }
+__global__ void batch_reset(int *counters, int n) {
+    if (static_cast<int>(threadIdx.x) < n) counters[threadIdx.x] = 0;
+}
 
 // Per event: best agent (minimum energy, lowest index on ties), its T,
 // and the best-so-far trace over checkpoints.
@@ -146,16 +148,28 @@ hipError_t launch_batch_prep(int jprec, const BatchArgs &B, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream_t st) {
-    batch_reset<<<1, 1, 0, st>>>(B.counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_batch_reset(int *counters, int n, hipStream_t st) {
+    batch_reset<<<1, 64, 0, st>>>(counters, n);
+    return hipGetLastError();
+}
+
+template <int TPB>
+static hipError_t steps_of_shape(int mode, int jprec, const BatchArgs &B, hipStream_t st) {
     const bool f16 = jprec == kJFp16;
     if (mode == kDSB)
-        return f16 ? launch_batch_steps_tu<kDSB, kJFp16>(B, st) : launch_batch_steps_tu<kDSB, kJBf16>(B, st);
+        return f16 ? launch_batch_steps_tu<kDSB, kJFp16, TPB>(B, st)
+                   : launch_batch_steps_tu<kDSB, kJBf16, TPB>(B, st);
     if (mode == kASB)
-        return f16 ? launch_batch_steps_tu<kASB, kJFp16>(B, st) : launch_batch_steps_tu<kASB, kJBf16>(B, st);
-    return f16 ? launch_batch_steps_tu<kBSB, kJFp16>(B, st) : launch_batch_steps_tu<kBSB, kJBf16>(B, st);
+        return f16 ? launch_batch_steps_tu<kASB, kJFp16, TPB>(B, st)
+                   : launch_batch_steps_tu<kASB, kJBf16, TPB>(B, st);
+    return f16 ? launch_batch_steps_tu<kBSB, kJFp16, TPB>(B, st)
+               : launch_batch_steps_tu<kBSB, kJBf16, TPB>(B, st);
+}
+
+hipError_t launch_batch_steps(int mode, int jprec, int tpb, const BatchArgs &B, hipStream_t st) {
+    if (tpb == kBatchTPBSmall) return steps_of_shape<kBatchTPBSmall>(mode, jprec, B, st);
+    if (tpb == kBatchTPB) return steps_of_shape<kBatchTPB>(mode, jprec, B, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_select(const BatchArgs &B, hipStream_t st) {

@@ -6,15 +6,18 @@
 //
 // Work items are (event, group of A agents) with A a power of two chosen so
 // that n_event * A fills one workgroup's slots; items are ordered by
-// decreasing cost and handed out by an atomic counter to a persistent grid
-// of one 1024-thread workgroup per CU.  Inside an item the structure is the
+// decreasing cost and handed out by an atomic counter to a persistent grid.
+// Two workgroup shapes exist (the tuner decides which events use which):
+// 1024 threads, one workgroup per CU, and 512 threads, two per CU (each
+// workgroup's barrier stalls overlap the other's work); both hold 9 slots
+// per thread within 128 VGPRs.  Inside an item the structure is the
 // register-row resident kernel: positions of the A agents in LDS
 // (spin-major, agent-minor: index i*A + a), momenta and couplings in
 // VGPRs.  Couplings are stored in 16 bits (FP16 or BF16, the reduced
 // precision form) next to a full LDS byte address; accumulation is FP32 and
 // energies FP64.
 //
-// Slot s of thread t is position j = s*1024 + t of the item, spin rank
+// Slot s of thread t is position j = s*TPB + t of the item, spin rank
 // q = j / A in decreasing-row-length order, agent a = j % A (so a thread's
 // slots all belong to agent t % A).  Register capacity per slot follows the
 // row-length profile by rank: slot 0 holds the longest rows.
@@ -37,7 +40,6 @@ namespace sbt {
 
 namespace {
 
-constexpr int kB = kBatchTPB;     // threads per workgroup
 constexpr int kS = kBatchSPT;     // slots per thread
 // couplings held in registers per slot (rank profile); rows beyond a
 // slot's capacity continue from global memory
@@ -116,22 +118,29 @@ __device__ __forceinline__ void for_slots(F &&f) {
     }
 }
 
-template <int MODE, int JP>
-__global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
+// At least four waves per SIMD for either shape (128 VGPRs): 1024 threads
+// are four waves per SIMD by themselves, 512 threads need the hint so that
+// two workgroups fit a CU.
+template <int MODE, int JP, int TPB>
+__global__ __launch_bounds__(TPB, 4) void sb_batch(BatchArgs B) {
+    constexpr int kB = TPB;                     // threads per workgroup
+    constexpr int kSlots = kB * kS;             // largest n * A of an item
+    constexpr int kStride = kSlots + 64;        // position buffer: slots, one pad word per lane
     extern __shared__ __align__(16) unsigned char smem[];
-    float *xs = reinterpret_cast<float *>(smem);                     // [2][kBatchStride]
-    double *red = reinterpret_cast<double *>(xs + 2 * kBatchStride); // [16][64]
-    int *item_s = reinterpret_cast<int *>(red + 16 * 64);
+    float *xs = reinterpret_cast<float *>(smem);                     // [2][kStride]
+    double *red = reinterpret_cast<double *>(xs + 2 * kStride);     // [waves][64]
+    int *item_s = reinterpret_cast<int *>(red + (kB / 64) * 64);
     // couplings past a slot's register capacity, packed like the held ones
-    uint32_t *tails = reinterpret_cast<uint32_t *>(item_s + 4);  // [kBatchTailCap]
+    uint32_t *tails = reinterpret_cast<uint32_t *>(item_s + 4);  // [B.tail_cap]
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
 
     for (;;) {
         if (t == 0) *item_s = atomicAdd(B.counter, 1);
         __syncthreads();
-        const int item = *item_s;
+        const int local = *item_s;
         __syncthreads();
-        if (item >= B.n_items) return;
+        if (local >= B.n_items) return;
+        const int item = B.item_begin + local;
         const int e = B.item_event[item];
         const int agent0 = B.item_agent0[item];
         const BatchEvent E = B.ev[e];
@@ -139,6 +148,14 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
         const int a = t & (A - 1);
         const int agent = agent0 + a;
         const bool agent_ok = agent < B.M;
+        // when each agent's work starts and reaches each checkpoint (the
+        // device's constant-rate wall clock), for time-to-target
+        auto stamp = [&](int slot) __attribute__((always_inline)) {
+            if (B.ckpt_clock && t < A && agent0 + t < B.M)
+                B.ckpt_clock[(static_cast<size_t>(e) * (B.n_ckpt + 1) + slot) * B.M + agent0 + t] =
+                    wall_clock64();
+        };
+        stamp(0);
 
         float xr[kS], yr[kS], hr[kS];
         // LDS address of the first position buffer (the dynamic LDS base; the
@@ -150,7 +167,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
         uint32_t wr[kS];
         auto spin_of = [&](int S) __attribute__((always_inline)) -> int {
             const uint32_t w = opaque(wr[S]) - lds0;
-            return w < static_cast<uint32_t>(4 * kBatchSlots) ? static_cast<int>(w >> (lgA + 2)) : -1;
+            return w < static_cast<uint32_t>(4 * kSlots) ? static_cast<int>(w >> (lgA + 2)) : -1;
         };
         uint32_t cp0[kCap[0]], cp1[kCap[1]], cp2[kCap[2]], cp3[kCap[3]], cp4[kCap[4]],
             cp5[kCap[5]], cp6[kCap[6]], cp7[kCap[7]], cp8[kCap[8]];
@@ -181,7 +198,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             // a lane without a spin in an active slot updates a zero
             // oscillator into its own pad word, so steps need no branches
             wr[S] = lds0 + 4u * (i >= 0 ? static_cast<uint32_t>(i * A + a)
-                                        : static_cast<uint32_t>(kBatchSlots + lane));
+                                        : static_cast<uint32_t>(kSlots + lane));
             xr[S] = yr[S] = hr[S] = 0.0f;
 #pragma unroll
             for (int c = 0; c < CAP; ++c) cp[c] = 0;
@@ -226,7 +243,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
         int t_total = 0, big_total = 0;
         const int t_base = block_exclusive_scan(tsum, reinterpret_cast<int *>(red), t_total);
         (void)block_exclusive_scan(tbig, reinterpret_cast<int *>(red), big_total);
-        const bool lds_tails = t_total <= kBatchTailCap && big_total == 0;
+        const bool lds_tails = t_total <= B.tail_cap && big_total == 0;
         if (lds_tails && tsum > 0) {
             int o = t_base;
             for_slots([&](auto sc) __attribute__((always_inline)) {
@@ -302,8 +319,8 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             constexpr bool SH = decltype(shc)::value;
             auto step = [&](auto bufc, int k) __attribute__((always_inline)) {
                 constexpr int BUF = decltype(bufc)::value;
-                constexpr uint32_t XO = BUF * kBatchStride * 4;        // buffer read
-                constexpr uint32_t XN = (BUF ^ 1) * kBatchStride * 4;  // buffer written
+                constexpr uint32_t XO = BUF * kStride * 4;        // buffer read
+                constexpr uint32_t XN = (BUF ^ 1) * kStride * 4;  // buffer written
                 const unsigned char *xc = smem + XO;
                 const float g = B.sched[k];
                 float acc[kS];
@@ -412,9 +429,10 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
                 }
                 if (k < kend) step(std::integral_constant<int, 0>{}, k++);
                 if (B.ckpt_every > 0 && k % B.ckpt_every == 0) {
-                    const double en = agent_energy(xs + (k & 1) * kBatchStride);
+                    const double en = agent_energy(xs + (k & 1) * kStride);
                     if (t < A && agent0 + t < B.M)
                         B.etrace[(static_cast<size_t>(e) * B.n_ckpt + ck) * B.M + agent0 + t] = en;
+                    stamp(ck + 1);
                     ++ck;
                 }
             }
@@ -444,7 +462,7 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
             case 8: with_c0(std::integral_constant<int, 8>{}); break;
             default: with_c0(std::integral_constant<int, kS>{}); break;
         }
-        const float *xfin = xs + (B.K & 1) * kBatchStride;
+        const float *xfin = xs + (B.K & 1) * kStride;
         const double en = agent_energy(xfin);
         if (t < A && agent0 + t < B.M) B.energy[static_cast<size_t>(e) * B.M + agent0 + t] = en;
         for_slots([&](auto sc) __attribute__((always_inline)) {
@@ -460,22 +478,21 @@ __global__ __launch_bounds__(kB) void sb_batch(BatchArgs B) {
     }
 }
 
-// The step kernel of one mode and coupling format (the work counter must
-// already be zero).
-template <int MODE, int JP>
+// The step kernel of one mode, coupling format and workgroup shape (the
+// launch's work counter must already be zero).
+template <int MODE, int JP, int TPB>
 hipError_t launch_batch_steps_tu(const BatchArgs &B, hipStream_t st) {
-    const size_t lds = sizeof(float) * 2 * kBatchStride + sizeof(double) * 16 * 64 + 16 +
-                       sizeof(uint32_t) * kBatchTailCap;
+    const size_t lds = batch_lds_bytes(TPB, B.tail_cap);
     // the packed 16-bit neighbour addresses assume the dynamic LDS starts at
     // address 0, which holds when the kernel has no static LDS
     static const bool base_zero = [] {
         hipFuncAttributes fa{};
-        return hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(sb_batch<MODE, JP>)) ==
+        return hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(sb_batch<MODE, JP, TPB>)) ==
                    hipSuccess &&
                fa.sharedSizeBytes == 0;
     }();
     if (!base_zero) return hipErrorInvalidConfiguration;
-    return launch_with_lds(sb_batch<MODE, JP>, dim3(B.grid), dim3(kB), lds, st, B);
+    return launch_with_lds(sb_batch<MODE, JP, TPB>, dim3(B.grid), dim3(TPB), lds, st, B);
 }
 
 }  // namespace sbt

@@ -112,14 +112,23 @@ struct StreamArgs {
 
 // ---------------------------------------------------------------- batch
 
-constexpr int kBatchTPB = 1024;                     // threads per workgroup
-constexpr int kBatchSPT = 9;                        // slots per thread
+constexpr int kBatchTPB = 1024;                     // threads per workgroup, large shape
+constexpr int kBatchTPBSmall = 512;                 // small shape (two workgroups per CU)
+constexpr int kBatchSPT = 9;                        // slots per thread (both shapes)
 constexpr int kBatchSlots = kBatchTPB * kBatchSPT;  // largest n * agents per item
-constexpr int kBatchTailCap = 8192;                 // batch: couplings past the slots' register
-                                                    //   capacity staged in LDS (32 KB)
-constexpr int kBatchStride = kBatchSlots + 64;      // LDS position buffer: slots, then
-                                                    //   one pad word per lane of a wave
+constexpr int kBatchSlotsSmall = kBatchTPBSmall * kBatchSPT;
+constexpr int kBatchTailCap = 8192;                 // default LDS words for couplings past the
+                                                    //   slots' register capacity (32 KB)
 enum : int { kJFp16 = 0, kJBf16 = 1, kJFp32 = 2, kJFp8 = 3 };  // coupling formats
+
+// LDS bytes of one batch workgroup of `tpb` threads with `tail_words` of
+// staged couplings: two position buffers (slots plus one pad word per lane
+// of a wave), the per-wave reduction area, the item word, the tails.
+constexpr size_t batch_lds_bytes(int tpb, int tail_words) {
+    return sizeof(float) * 2 * (static_cast<size_t>(tpb) * kBatchSPT + 64) +
+           sizeof(double) * static_cast<size_t>(tpb / 64) * 64 + 16 +
+           sizeof(uint32_t) * static_cast<size_t>(tail_words);
+}
 
 struct BatchEvent {
     int n, nnz;
@@ -132,7 +141,9 @@ struct BatchEvent {
 };
 
 struct BatchArgs {
-    int E, M, K, n_items, grid, ckpt_every, n_ckpt;
+    int E, M, K, ckpt_every, n_ckpt;
+    int n_items, item_begin;     // this launch's items: [item_begin, item_begin + n_items)
+    int grid, tail_cap;          // persistent workgroups; LDS words for staged couplings
     uint32_t seed_lo, seed_hi;
     float dt, dta0;
     double c0_fixed;             // > 0: fixed c0 for every event
@@ -149,7 +160,7 @@ struct BatchArgs {
     double *offset;              // [E] Ising offset C
     int *perm;                   // [sum n] spin order per event
     const float *sched;          // [K]
-    int *counter;                // work queue
+    int *counter;                // this launch's work queue counter
     double *etrace;              // [E * n_ckpt * M]
     double *energy;              // [E * M] final O(T)
     double *trace;               // [E * n_ckpt] best so far, or null
@@ -158,14 +169,19 @@ struct BatchArgs {
     int8_t *T;                   // [sum n * M] final T per agent
     float *x_out;                // [sum n * M] final positions, or null
     int8_t *best_T;              // [sum n]
+    long long *ckpt_clock;       // [E * (n_ckpt + 1) * M] device wall clock at each
+                                 //   agent's item start and checkpoints, or null
 };
 
 hipError_t launch_batch_prep(int jprec, const BatchArgs &B, hipStream_t st);
-hipError_t launch_batch_steps(int mode, int jprec, const BatchArgs &B, hipStream_t st);
-// the step kernel of one mode and coupling format, instantiated in its own
-// translation unit (sb_batch_mode.hip, built once per pair)
-template <int MODE, int JP>
+// resets the launch counters (kernels, so the reset can be graph-captured)
+hipError_t launch_batch_reset(int *counters, int n, hipStream_t st);
+hipError_t launch_batch_steps(int mode, int jprec, int tpb, const BatchArgs &B, hipStream_t st);
+// the step kernel of one mode, coupling format and shape, instantiated in
+// its own translation unit (sb_batch_mode.hip, built once per triple)
+template <int MODE, int JP, int TPB>
 hipError_t launch_batch_steps_tu(const BatchArgs &B, hipStream_t st);
+
 hipError_t launch_batch_select(const BatchArgs &B, hipStream_t st);
 
 hipError_t launch_prep(int n, const double *a, const int *row_ptr, const int *col, const double *b,

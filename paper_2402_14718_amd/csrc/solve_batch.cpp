@@ -22,24 +22,42 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Schedule {
     std::vector<sbt::BatchEvent> ev;
+    // items of the 1024-thread launch first, then those of the 512-thread
+    // launch, each group in decreasing-cost order
     std::vector<int32_t> item_event, item_agent0;
+    int n_large = 0, n_small = 0;  // items per launch
     int64_t sum_n = 0, sum_nnz = 0;
 };
 
-// Agents per work item: the largest power of two with n * A within one
-// workgroup's slots (and A <= agents, A <= threads per workgroup).
-int lg_agents_for(int32_t n, int32_t M) {
+int tpb_of(bool small) { return small ? sbt::kBatchTPBSmall : sbt::kBatchTPB; }
+
+// Agents per work item: the largest power of two A with n * A within
+// `fill` of the shape's slots (and A <= agents, A <= its threads); at least
+// one agent.
+int lg_agents_for(int32_t n, int32_t M, int tpb, double fill) {
+    const double cap = fill * tpb * sbt::kBatchSPT;
     int lg = 0;
-    while ((2 << lg) <= M && (2 << lg) <= sbt::kBatchTPB &&
-           static_cast<int64_t>(n) * (2 << lg) <= sbt::kBatchSlots)
-        ++lg;
+    while ((2 << lg) <= M && (2 << lg) <= tpb && static_cast<double>(n) * (2 << lg) <= cap) ++lg;
     return lg;
 }
 
+int check_tuning(const sbt_batch_tuning &t, const char *who) {
+    if (t.split_n < 0) return fail(SBT_EINVAL, "%s: tuning split_n must be >= 0", who);
+    if (t.tail_words < 0 || t.tail_words > sbt::kBatchTailCap)
+        return fail(SBT_EINVAL, "%s: tuning tail_words must be in [0, %d]", who, sbt::kBatchTailCap);
+    if (!(t.fill > 0.0) || !(t.fill <= 1.0))
+        return fail(SBT_EINVAL, "%s: tuning fill must be in (0, 1]", who);
+    if (t.reserved != 0) return fail(SBT_EINVAL, "%s: tuning reserved must be 0", who);
+    return SBT_OK;
+}
+
 int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const double *c0_scale,
-                  int32_t same_start, const sbt_solve_params &p, Schedule &S, const char *who) {
+                  int32_t same_start, const sbt_solve_params &p, const sbt_batch_tuning &tu,
+                  Schedule &S, const char *who) {
     if (E < 1) return fail(SBT_EINVAL, "%s: n_events must be >= 1", who);
     if (!n || !nnz) return fail(SBT_EINVAL, "%s: n or nnz is NULL", who);
+    int rc = check_tuning(tu, who);
+    if (rc) return rc;
     if (c0_scale)
         for (int32_t e = 0; e < E; ++e)
             if (!(c0_scale[e] > 0.0) || !std::isfinite(c0_scale[e]))
@@ -49,7 +67,7 @@ int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const double 
         int64_t cost;
         int32_t e, a0;
     };
-    std::vector<Item> items;
+    std::vector<Item> items[2];  // [0]: 1024-thread shape, [1]: 512-thread shape
     int64_t row_off = 0, nz_off = 0;
     for (int32_t e = 0; e < E; ++e) {
         if (n[e] < 1) return fail(SBT_EINVAL, "%s: event %d has n = %d", who, e, n[e]);
@@ -57,34 +75,39 @@ int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const double 
             return fail(SBT_EUNSUPPORTED, "%s: event %d has %d variables (batched limit %d)", who,
                         e, n[e], sbt::kBatchSlots);
         if (nnz[e] < 0) return fail(SBT_EINVAL, "%s: event %d has nnz < 0", who, e);
+        const bool small = n[e] <= tu.split_n && n[e] <= sbt::kBatchSlotsSmall;
         sbt::BatchEvent &d = S.ev[e];
         d.n = n[e];
         d.nnz = static_cast<int>(nnz[e]);
         d.row_off = static_cast<int>(row_off);
         d.rp_off = static_cast<int>(row_off + e);
         d.nz_off = static_cast<int>(nz_off);
-        d.lg_agents = lg_agents_for(n[e], p.agents);
+        d.lg_agents = lg_agents_for(n[e], p.agents, tpb_of(small), tu.fill);
         d.event_id = same_start ? p.event : p.event + e;
         d.c0_scale = c0_scale ? static_cast<float>(c0_scale[e]) : 1.0f;
         const int A = 1 << d.lg_agents;
         for (int a0 = 0; a0 < p.agents; a0 += A) {
             const int used = std::min(A, p.agents - a0);
-            items.push_back({(static_cast<int64_t>(n[e]) + nnz[e]) * used, e, a0});
+            items[small ? 1 : 0].push_back({(static_cast<int64_t>(n[e]) + nnz[e]) * used, e, a0});
         }
         row_off += n[e];
         nz_off += nnz[e];
         if (row_off + e + 1 > INT32_MAX / 2 || nz_off > INT32_MAX / 2)
             return fail(SBT_EINVAL, "%s: batch too large for 32-bit offsets", who);
     }
-    // longest items first (ties: event, then agent order)
-    std::stable_sort(items.begin(), items.end(),
-                     [](const Item &l, const Item &r) { return l.cost > r.cost; });
-    S.item_event.resize(items.size());
-    S.item_agent0.resize(items.size());
-    for (size_t k = 0; k < items.size(); ++k) {
-        S.item_event[k] = items[k].e;
-        S.item_agent0[k] = items[k].a0;
+    S.item_event.clear();
+    S.item_agent0.clear();
+    for (auto &v : items) {
+        // longest items first (ties: event, then agent order)
+        std::stable_sort(v.begin(), v.end(),
+                         [](const Item &l, const Item &r) { return l.cost > r.cost; });
+        for (const Item &it : v) {
+            S.item_event.push_back(it.e);
+            S.item_agent0.push_back(it.a0);
+        }
     }
+    S.n_large = static_cast<int>(items[0].size());
+    S.n_small = static_cast<int>(items[1].size());
     S.sum_n = row_off;
     S.sum_nnz = nz_off;
     return SBT_OK;
@@ -115,7 +138,7 @@ BatchLayout make_layout(const Schedule &S, const sbt_solve_params &p) {
     L.offset = take(sizeof(double) * E);
     L.perm = take(sizeof(int32_t) * static_cast<size_t>(S.sum_n));
     L.sched = take(sizeof(float) * static_cast<size_t>(p.steps));
-    L.counter = take(sizeof(int32_t));
+    L.counter = take(2 * sizeof(int32_t));  // one per launch
     L.etrace = take(sizeof(double) * E * static_cast<size_t>(L.n_ckpt) * M);
     L.energy = take(sizeof(double) * E * M);
     L.T = take(static_cast<size_t>(S.sum_n) * M);
@@ -148,8 +171,30 @@ int cu_count() {
 
 }  // namespace
 
-extern "C" size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz, int32_t n_events,
-                                            const sbt_solve_params *p) {
+extern "C" void sbt_batch_tuning_default(sbt_batch_tuning *t) {
+    if (!t) return;
+    std::memset(t, 0, sizeof *t);
+    t->split_n = 0;
+    t->tail_words = sbt::kBatchTailCap;
+    t->fill = 1.0;
+}
+
+namespace {
+
+sbt_batch_tuning tuning_or_default(const sbt_batch_tuning *t) {
+    sbt_batch_tuning d;
+    sbt_batch_tuning_default(&d);
+    if (!t) return d;
+    sbt_batch_tuning r = *t;
+    r.from_cache = 0;
+    return r;
+}
+
+}  // namespace
+
+extern "C" size_t sbt_batch_workspace_bytes_tuned(const int32_t *n, const int64_t *nnz,
+                                                  int32_t n_events, const sbt_solve_params *p,
+                                                  const sbt_batch_tuning *t) {
     sbt::clear_error();
     const char *who = "sbt_batch_workspace_bytes";
     if (!p) {
@@ -158,21 +203,26 @@ extern "C" size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz
     }
     if (check_batch_params(*p, who)) return 0;
     Schedule S;
-    if (make_schedule(n, nnz, n_events, nullptr, 0, *p, S, who)) return 0;
+    if (make_schedule(n, nnz, n_events, nullptr, 0, *p, tuning_or_default(t), S, who)) return 0;
     return make_layout(S, *p).total;
 }
 
-extern "C" int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
-                              const double *c0_scale, int32_t same_start,
-                              const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
-                              void *stream) {
+extern "C" size_t sbt_batch_workspace_bytes(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                                            const sbt_solve_params *p) {
+    return sbt_batch_workspace_bytes_tuned(n, nnz, n_events, p, nullptr);
+}
+
+extern "C" int sbt_batch_plan_tuned(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                                    const double *c0_scale, int32_t same_start,
+                                    const sbt_solve_params *p, const sbt_batch_tuning *t,
+                                    void *workspace, size_t workspace_bytes, void *stream) {
     const char *who = "sbt_batch_plan";
     sbt::clear_error();
     if (!p) return fail(SBT_EINVAL, "%s: params is NULL", who);
     int rc = check_batch_params(*p, who);
     if (rc) return rc;
     Schedule S;
-    rc = make_schedule(n, nnz, n_events, c0_scale, same_start, *p, S, who);
+    rc = make_schedule(n, nnz, n_events, c0_scale, same_start, *p, tuning_or_default(t), S, who);
     if (rc) return rc;
     const BatchLayout L = make_layout(S, *p);
     if (!workspace || workspace_bytes < L.total)
@@ -190,9 +240,18 @@ extern "C" int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_ev
     return static_cast<int>(S.item_event.size());
 }
 
-extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_precision prec,
-                             const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
-                             const sbt_dev_batch_result *out, void *stream) {
+extern "C" int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
+                              const double *c0_scale, int32_t same_start,
+                              const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
+                              void *stream) {
+    return sbt_batch_plan_tuned(n, nnz, n_events, c0_scale, same_start, p, nullptr, workspace,
+                                workspace_bytes, stream);
+}
+
+extern "C" int sbt_batch_run_tuned(const sbt_dev_batch *batch, sbt_mode mode, sbt_precision prec,
+                                   const sbt_solve_params *p, const sbt_batch_tuning *t,
+                                   void *workspace, size_t workspace_bytes,
+                                   const sbt_dev_batch_result *out, void *stream) {
     const char *who = "sbt_batch_run";
     sbt::clear_error();
     if (!batch || !p || !out) return fail(SBT_EINVAL, "%s: NULL argument", who);
@@ -202,8 +261,9 @@ extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_prec
         return fail(SBT_EUNSUPPORTED, "%s: batches hold 16-bit couplings (FP16 or BF16)", who);
     int rc = check_batch_params(*p, who);
     if (rc) return rc;
+    const sbt_batch_tuning tu = tuning_or_default(t);
     Schedule S;
-    rc = make_schedule(batch->n, batch->nnz, batch->n_events, nullptr, 0, *p, S, who);
+    rc = make_schedule(batch->n, batch->nnz, batch->n_events, nullptr, 0, *p, tu, S, who);
     if (rc) return rc;
     const BatchLayout L = make_layout(S, *p);
     if (!workspace || workspace_bytes < L.total)
@@ -222,8 +282,7 @@ extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_prec
     B.E = batch->n_events;
     B.M = p->agents;
     B.K = p->steps;
-    B.n_items = static_cast<int>(S.item_event.size());
-    B.grid = std::min(B.n_items, cu_count());
+    B.tail_cap = tu.tail_words;
     B.ckpt_every = p->energy_every;
     B.n_ckpt = L.n_ckpt;
     B.seed_lo = static_cast<uint32_t>(p->seed & 0xffffffffu);
@@ -244,7 +303,6 @@ extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_prec
     B.offset = out->offset ? out->offset : reinterpret_cast<double *>(ws + L.offset);
     B.perm = reinterpret_cast<int *>(ws + L.perm);
     B.sched = reinterpret_cast<const float *>(ws + L.sched);
-    B.counter = reinterpret_cast<int *>(ws + L.counter);
     B.etrace = reinterpret_cast<double *>(ws + L.etrace);
     B.energy = out->agent_energy ? out->agent_energy : reinterpret_cast<double *>(ws + L.energy);
     B.trace = out->trace;
@@ -253,25 +311,51 @@ extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_prec
     B.T = out->agent_T ? out->agent_T : reinterpret_cast<int8_t *>(ws + L.T);
     B.x_out = out->agent_x;
     B.best_T = out->best_T;
+    B.ckpt_clock = reinterpret_cast<long long *>(out->ckpt_clock);
+    int *counters = reinterpret_cast<int *>(ws + L.counter);
 
     SBT_HIP(sbt::launch_schedule(p->steps, p->a0, reinterpret_cast<float *>(ws + L.sched), st));
     const int jprec = prec == SBT_PREC_FP16 ? sbt::kJFp16 : sbt::kJBf16;
-    rc = 0;
-    {
-        hipError_t e = sbt::launch_batch_prep(jprec, B, st);
-        if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch prep: %s", who, hipGetErrorString(e));
-        if (out->step_begin) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_begin), st));
-        e = sbt::launch_batch_steps(static_cast<int>(mode), jprec, B, st);  // SBT_BSB/DSB = 0/1
+    const int cus = cu_count();
+    hipError_t e = sbt::launch_batch_prep(jprec, B, st);
+    if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch prep: %s", who, hipGetErrorString(e));
+    SBT_HIP(sbt::launch_batch_reset(counters, 2, st));
+    if (out->step_begin) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_begin), st));
+    // the 1024-thread items (one workgroup per CU), then the 512-thread items
+    // (two per CU), each launch a persistent grid over its own queue
+    if (S.n_large > 0) {
+        sbt::BatchArgs L0 = B;
+        L0.item_begin = 0;
+        L0.n_items = S.n_large;
+        L0.counter = counters;
+        L0.grid = std::min(S.n_large, cus);
+        e = sbt::launch_batch_steps(static_cast<int>(mode), jprec, sbt::kBatchTPB, L0, st);
         if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch kernel: %s", who, hipGetErrorString(e));
-        if (out->step_end) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_end), st));
-        e = sbt::launch_batch_select(B, st);
-        if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch select: %s", who, hipGetErrorString(e));
     }
+    if (S.n_small > 0) {
+        sbt::BatchArgs L1 = B;
+        L1.item_begin = S.n_large;
+        L1.n_items = S.n_small;
+        L1.counter = counters + 1;
+        L1.grid = std::min(S.n_small, 2 * cus);
+        e = sbt::launch_batch_steps(static_cast<int>(mode), jprec, sbt::kBatchTPBSmall, L1, st);
+        if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch kernel: %s", who, hipGetErrorString(e));
+    }
+    if (out->step_end) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_end), st));
+    e = sbt::launch_batch_select(B, st);
+    if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch select: %s", who, hipGetErrorString(e));
     if (out->agent_trace)
         SBT_HIP(hipMemcpyAsync(out->agent_trace, B.etrace,
                                sizeof(double) * S.ev.size() * L.n_ckpt * p->agents,
                                hipMemcpyDeviceToDevice, st));
     return SBT_OK;
+}
+
+extern "C" int sbt_batch_run(const sbt_dev_batch *batch, sbt_mode mode, sbt_precision prec,
+                             const sbt_solve_params *p, void *workspace, size_t workspace_bytes,
+                             const sbt_dev_batch_result *out, void *stream) {
+    return sbt_batch_run_tuned(batch, mode, prec, p, nullptr, workspace, workspace_bytes, out,
+                               stream);
 }
 
 // ----------------------------------------------------------- host batch
@@ -332,12 +416,16 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     }
     int rc0 = check_batch_params(p, who);
     if (rc0) return rc0;
+    // the tuned schedule for this batch's shape, if the tuning cache has one
+    sbt_batch_tuning tu;
+    rc0 = sbt_batch_tuning_lookup(n.data(), E, mode, prec, p.agents, &tu);
+    if (rc0) return rc0;
     {
         Schedule S;
-        rc0 = make_schedule(n.data(), nnz.data(), E, c0_scale, same_start, p, S, who);
+        rc0 = make_schedule(n.data(), nnz.data(), E, c0_scale, same_start, p, tu, S, who);
         if (rc0) return rc0;
     }
-    const size_t ws_bytes = sbt_batch_workspace_bytes(n.data(), nnz.data(), E, &p);
+    const size_t ws_bytes = sbt_batch_workspace_bytes_tuned(n.data(), nnz.data(), E, &p, &tu);
     if (ws_bytes == 0) return SBT_EINVAL;
     const int n_ck = p.energy_every > 0 ? p.steps / p.energy_every : 0;
     if ((out->trace || out->agent_trace) && n_ck == 0)
@@ -373,7 +461,8 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
         }
     } eg{e0, e1};
     SBT_HIP(hipEventRecord(e0, st));
-    int rc = sbt_batch_plan(n.data(), nnz.data(), E, c0_scale, same_start, &p, dws.p, ws_bytes, st);
+    int rc = sbt_batch_plan_tuned(n.data(), nnz.data(), E, c0_scale, same_start, &p, &tu, dws.p,
+                                  ws_bytes, st);
     if (rc < 0) return rc;
     sbt_dev_batch dbch{E, n.data(), nnz.data(), static_cast<const double *>(da.p),
                        static_cast<const int32_t *>(drp.p), static_cast<const int32_t *>(dcol.p),
@@ -385,7 +474,7 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     dr.agent_energy = static_cast<double *>(dae.p);
     dr.trace = static_cast<double *>(dtr.p);
     dr.agent_trace = static_cast<double *>(dat.p);
-    rc = sbt_batch_run(&dbch, mode, prec, &p, dws.p, ws_bytes, &dr, st);
+    rc = sbt_batch_run_tuned(&dbch, mode, prec, &p, &tu, dws.p, ws_bytes, &dr, st);
     if (rc) return rc;
     SBT_HIP(hipEventRecord(e1, st));
     SBT_HIP(hipMemcpyAsync(out->energy, dbe.p, sizeof(double) * E, hipMemcpyDeviceToHost, st));
@@ -402,6 +491,18 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     float ms = 0.0f;
     SBT_HIP(hipEventElapsedTime(&ms, e0, e1));
     out->elapsed_s = 1e-3 * ms;
+    return SBT_OK;
+}
+
+extern "C" int sbt_wall_clock_hz(double *hz) {
+    const char *who = "sbt_wall_clock_hz";
+    sbt::clear_error();
+    if (!hz) return fail(SBT_EINVAL, "%s: hz is NULL", who);
+    int dev = 0, khz = 0;
+    SBT_HIP(hipGetDevice(&dev));
+    SBT_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(SBT_EDEVICE, "%s: the device reports no wall clock rate", who);
+    *hz = 1e3 * khz;
     return SBT_OK;
 }
 
