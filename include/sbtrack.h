@@ -342,13 +342,28 @@ int sbt_solve_dev_noalloc(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode m
 /* Events concatenated in device memory. */
 typedef struct {
     int32_t n_events;
-    const int32_t *n;        /* host [E]: variables of each event (1..9216)       */
+    const int32_t *n;        /* host [E]: variables of each event (>= 1; above   */
+                             /*   9216 as gangs of row bands, at most 9216 x the  */
+                             /*   device's CU count)                              */
     const int64_t *nnz;      /* host [E]: stored couplings of each event          */
     const double *a;         /* device [sum n]                                     */
     const int32_t *row_ptr;  /* device [sum (n + 1)]: each event's own CSR row    */
                              /*   pointers, starting at 0                          */
     const int32_t *col;      /* device [sum nnz]: columns local to the event      */
     const double *b;         /* device [sum nnz]: symmetric, ascending columns    */
+    const double *target;    /* device [E] or NULL.  Target mode (time-to-target: */
+                             /*   stop at the goal, as a solve run for time-to-   */
+                             /*   solution would): event e's work stops at the    */
+                             /*   first checkpoint (energy_every > 0 required)    */
+                             /*   where one of its agents reaches O(T) <=         */
+                             /*   target[e] (an event run as gangs of row bands:  */
+                             /*   each agent's gang stops on its own energy); its */
+                             /*   agents keep the state reached (results are of  */
+                             /*   that state), the checkpoints not reached read   */
+                             /*   NaN in agent_trace.  The items of one event     */
+                             /*   stop through a shared flag, so at which         */
+                             /*   checkpoint each stops depends on timing: a      */
+                             /*   target-mode solve is not bit-reproducible       */
 } sbt_dev_batch;
 
 typedef struct {
@@ -394,6 +409,12 @@ typedef struct {
     double fill;         /* an item holds A agents, A the largest power of two */
                          /*   with n A <= fill x (slots of its shape), A <=    */
                          /*   agents and A <= threads; fill in (0, 1]          */
+    int32_t band_rows;   /* events with n above this (0 = 9216, the largest    */
+                         /*   that one workgroup holds; at most 9216) run as    */
+                         /*   gangs of row bands: one gang per agent, bands of  */
+                         /*   at most band_rows consecutive spins on as many    */
+                         /*   workgroups at once, positions exchanged through   */
+                         /*   HBM with one barrier per step                     */
     int32_t from_cache;  /* out of sbt_batch_tuning_lookup: 1 = tuned entry    */
     int32_t reserved;    /* must be 0                                          */
 } sbt_batch_tuning;
@@ -433,8 +454,9 @@ size_t sbt_batch_workspace_bytes_tuned(const int32_t *n, const int64_t *nnz, int
  *               fixed or automatic value of that event); each > 0
  *   same_start  nonzero: every event draws its start with counter word
  *               p->event (a scan of one QUBO); zero: event e uses p->event + e
- * Returns the number of work items, or a negative status; SBT_EUNSUPPORTED
- * for an event with more than 9216 variables. */
+ * Returns the number of work items (row-band items of gangs included), or a
+ * negative status; SBT_EUNSUPPORTED for an event needing more row bands
+ * than the device has CUs (the bands of a gang must run at once). */
 int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
                    const double *c0_scale, int32_t same_start, const sbt_solve_params *p,
                    void *workspace, size_t workspace_bytes, void *stream);

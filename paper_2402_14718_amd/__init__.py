@@ -387,17 +387,19 @@ def c0_scan(q: Qubo, mode: str, factors, precision: str = "fp16", agents: int = 
             "factor": float(f[best.value])}
 
 
-def batch_tuning(split_n: int = 0, tail_words: int = 8192, fill: float = 1.0):
+def batch_tuning(split_n: int = 0, tail_words: int = 8192, fill: float = 1.0,
+                 band_rows: int = 0):
     """An explicit sbt_batch_tuning."""
     t = _lib.SbtBatchTuning()
     load().sbt_batch_tuning_default(C.byref(t))
     t.split_n, t.tail_words, t.fill = int(split_n), int(tail_words), float(fill)
+    t.band_rows = int(band_rows)
     return t
 
 
 def tuning_dict(t: _lib.SbtBatchTuning) -> dict:
     return {"split_n": int(t.split_n), "tail_words": int(t.tail_words), "fill": float(t.fill),
-            "from_cache": bool(t.from_cache)}
+            "band_rows": int(t.band_rows), "from_cache": bool(t.from_cache)}
 
 
 def batch_tuning_key(sizes, mode: str, precision: str, agents: int) -> str:
@@ -427,7 +429,7 @@ class DeviceBatchSolver:
     def __init__(self, qubos, mode: str, precision: str, params: _lib.SbtSolveParams,
                  device="cuda", want_agent_energy: bool = False, want_trace: bool = False,
                  want_agent_state: bool = False, c0_scale=None, same_start: bool = False,
-                 want_clock: bool = False, tuning=None):
+                 want_clock: bool = False, tuning=None, target=None):
         import torch
         self.torch = torch
         self.mode, self.precision, self.params = mode, precision, params
@@ -480,8 +482,12 @@ class DeviceBatchSolver:
         if rc < 0:
             check(rc)
         self.n_items = rc
+        # target mode: per-event energies at which the event's work stops
+        self.target = (None if target is None else
+                       t(np.asarray(target, dtype=np.float64).reshape(E), torch.float64))
         self._db = _lib.SbtDevBatch(E, np_, nz_, self.a.data_ptr(), self.rp.data_ptr(),
-                                    self.col.data_ptr(), self.b.data_ptr())
+                                    self.col.data_ptr(), self.b.data_ptr(),
+                                    None if self.target is None else self.target.data_ptr())
         tot = int(n.sum()) * M
         self.agent_T = torch.empty(tot, dtype=torch.int8, device=dev) if want_agent_state else None
         self.agent_x = torch.empty(tot, dtype=torch.float32, device=dev) if want_agent_state else None

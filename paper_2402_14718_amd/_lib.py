@@ -87,7 +87,8 @@ SBT_PREC_FP8 = 3
 
 class SbtDevBatch(C.Structure):
     _fields_ = [("n_events", C.c_int32), ("n", C.POINTER(C.c_int32)), ("nnz", C.POINTER(C.c_int64)),
-                ("a", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("b", C.c_void_p)]
+                ("a", C.c_void_p), ("row_ptr", C.c_void_p), ("col", C.c_void_p), ("b", C.c_void_p),
+                ("target", C.c_void_p)]
 
 
 class SbtDevBatchResult(C.Structure):
@@ -100,7 +101,7 @@ class SbtDevBatchResult(C.Structure):
 
 class SbtBatchTuning(C.Structure):
     _fields_ = [("split_n", C.c_int32), ("tail_words", C.c_int32), ("fill", C.c_double),
-                ("from_cache", C.c_int32), ("reserved", C.c_int32)]
+                ("band_rows", C.c_int32), ("from_cache", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SbtBatchResult(C.Structure):

@@ -10,7 +10,8 @@
 //
 // File (written by the tuner; only these fields are read):
 //   {"format": "sbtrack batch tuning 1", "entries": [
-//     {"key": "...", "split_n": 4608, "tail_words": 8192, "fill": 1.0, ...}, ...]}
+//     {"key": "...", "split_n": 4608, "tail_words": 8192, "fill": 1.0,
+//      "band_rows": 0 (optional), ...}, ...]}
 #include <dlfcn.h>
 
 #include <cmath>
@@ -112,6 +113,8 @@ const std::vector<Entry> &entries() {
             E.t.split_n = static_cast<int32_t>(split);
             E.t.tail_words = static_cast<int32_t>(tail);
             E.t.fill = fill;
+            const double band = field(s, q1, end, "band_rows");
+            E.t.band_rows = std::isfinite(band) ? static_cast<int32_t>(band) : 0;
             E.t.from_cache = 1;
             const size_t h = E.key.find(" h=");
             if (h == std::string::npos) continue;

@@ -313,6 +313,7 @@ __global__ __launch_bounds__(TPB, 4) void sb_batch(BatchArgs B) {
         // meets the same barriers.
         // SH: slots past 0 gather min(capacity, 2) couplings (the entries
         // beyond are zero padding in such a wave)
+        int k_done = B.K;  // steps taken (fewer when a target stops the event)
         auto run = [&](auto nac, auto c0c, auto shc) __attribute__((always_inline)) {
             constexpr int NA = decltype(nac)::value;
             constexpr int C0 = decltype(c0c)::value;
@@ -430,12 +431,37 @@ __global__ __launch_bounds__(TPB, 4) void sb_batch(BatchArgs B) {
                 if (k < kend) step(std::integral_constant<int, 0>{}, k++);
                 if (B.ckpt_every > 0 && k % B.ckpt_every == 0) {
                     const double en = agent_energy(xs + (k & 1) * kStride);
-                    if (t < A && agent0 + t < B.M)
+                    const bool mine = t < A && agent0 + t < B.M;
+                    if (mine)
                         B.etrace[(static_cast<size_t>(e) * B.n_ckpt + ck) * B.M + agent0 + t] = en;
                     stamp(ck + 1);
                     ++ck;
+                    // target mode: the event's work stops at the first
+                    // checkpoint where one of its agents (of this item or,
+                    // through the event's flag, of another) reaches the target
+                    if (B.target) {
+                        // (an OR over the workgroup through the item word: the
+                        // kernel keeps no static LDS, see the launch)
+                        if (t == 0) *item_s = 0;
+                        __syncthreads();
+                        if (mine && en <= B.target[e]) *item_s = 1;
+                        __syncthreads();
+                        if (t == 0) {
+                            const int hit = *item_s;
+                            if (hit)
+                                __hip_atomic_store(B.done + e, 1, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                            *item_s = hit || __hip_atomic_load(B.done + e, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        __syncthreads();
+                        const bool stop = *item_s != 0;
+                        __syncthreads();
+                        if (stop) break;
+                    }
                 }
             }
+            k_done = k;
         };
         auto with_sh = [&](auto nac, auto c0c) __attribute__((always_inline)) {
             if (short_rest)
@@ -462,7 +488,14 @@ __global__ __launch_bounds__(TPB, 4) void sb_batch(BatchArgs B) {
             case 8: with_c0(std::integral_constant<int, 8>{}); break;
             default: with_c0(std::integral_constant<int, kS>{}); break;
         }
-        const float *xfin = xs + (B.K & 1) * kStride;
+        // checkpoints a target stop skipped read NaN (no state was reached)
+        if (t < A && agent0 + t < B.M)
+            for (int c = ck; c < B.n_ckpt; ++c) {
+                B.etrace[(static_cast<size_t>(e) * B.n_ckpt + c) * B.M + agent0 + t] = NAN;
+                if (B.ckpt_clock)
+                    B.ckpt_clock[(static_cast<size_t>(e) * (B.n_ckpt + 1) + c + 1) * B.M + agent0 + t] = 0;
+            }
+        const float *xfin = xs + (k_done & 1) * kStride;
         const double en = agent_energy(xfin);
         if (t < A && agent0 + t < B.M) B.energy[static_cast<size_t>(e) * B.M + agent0 + t] = en;
         for_slots([&](auto sc) __attribute__((always_inline)) {

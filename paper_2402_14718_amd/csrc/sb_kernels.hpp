@@ -171,6 +171,29 @@ struct BatchArgs {
     int8_t *best_T;              // [sum n]
     long long *ckpt_clock;       // [E * (n_ckpt + 1) * M] device wall clock at each
                                  //   agent's item start and checkpoints, or null
+    const double *target;        // [E] or null: stop an event's work at the first
+                                 //   checkpoint where an agent reaches O(T) <= target
+    int *done;                   // [E] events whose target was reached (target mode)
+    // events run as gangs of row bands (sb_batch_gang.hip)
+    int gang_items;              // (gang, band) items, gang-major
+    const int *gitem_gang;       // [gang_items]
+    const int *gitem_band;       // [gang_items]
+    const struct GangDesc *gangs;
+    float *xg;                   // per gang: two position buffers of n floats
+    int *arrive;                 // per gang: bands arrived at its barriers
+    double *gpart;               // per gang: [bands][n_ckpt + 1] partial energies
+    long long *gclock;           // per gang: [bands][n_ckpt + 1] wall-clock stamps
+    int *gang_fault;             // set when a bounded gang wait ran out
+    int *gang_counter;           // work queue of the gang launch
+};
+
+// One gang: the `bands` row bands of one (event, agent), each of at most
+// `rows` consecutive spins, run by as many workgroups at once; positions
+// cross bands through the gang's global buffers, one barrier per step.
+struct GangDesc {
+    int e, agent, bands, rows;
+    long long x_off;             // offset of the gang's two position buffers in xg
+    int part_off;                // offset of its [bands][n_ckpt + 1] in gpart / gclock
 };
 
 hipError_t launch_batch_prep(int jprec, const BatchArgs &B, hipStream_t st);
@@ -183,6 +206,12 @@ template <int MODE, int JP, int TPB>
 hipError_t launch_batch_steps_tu(const BatchArgs &B, hipStream_t st);
 
 hipError_t launch_batch_select(const BatchArgs &B, hipStream_t st);
+// the gang launch (persistent grid of `B.grid` 1024-thread workgroups) and
+// the reduction of its partial energies and stamps; n_gangs gangs
+hipError_t launch_batch_gang(int mode, int jprec, const BatchArgs &B, hipStream_t st);
+hipError_t launch_batch_gang_reduce(const BatchArgs &B, int n_gangs, hipStream_t st);
+// zeroes n ints (a kernel, so it can be graph-captured)
+hipError_t launch_zero_ints(int *p, int n, hipStream_t st);
 
 hipError_t launch_prep(int n, const double *a, const int *row_ptr, const int *col, const double *b,
                        float *J, float *h, double *part, double *scal, double c0_fixed,

@@ -27,6 +27,12 @@ struct Schedule {
     std::vector<int32_t> item_event, item_agent0;
     int n_large = 0, n_small = 0;  // items per launch
     int64_t sum_n = 0, sum_nnz = 0;
+    // events above the band limit: one gang of row bands per agent
+    std::vector<sbt::GangDesc> gangs;
+    std::vector<int32_t> gitem_gang, gitem_band;
+    int64_t xg_floats = 0, part_entries = 0;
+    int max_bands = 0;
+    int items() const { return static_cast<int>(item_event.size() + gitem_gang.size()); }
 };
 
 int tpb_of(bool small) { return small ? sbt::kBatchTPBSmall : sbt::kBatchTPB; }
@@ -47,6 +53,8 @@ int check_tuning(const sbt_batch_tuning &t, const char *who) {
         return fail(SBT_EINVAL, "%s: tuning tail_words must be in [0, %d]", who, sbt::kBatchTailCap);
     if (!(t.fill > 0.0) || !(t.fill <= 1.0))
         return fail(SBT_EINVAL, "%s: tuning fill must be in (0, 1]", who);
+    if (t.band_rows < 0 || t.band_rows > sbt::kBatchSlots)
+        return fail(SBT_EINVAL, "%s: tuning band_rows must be in [0, %d]", who, sbt::kBatchSlots);
     if (t.reserved != 0) return fail(SBT_EINVAL, "%s: tuning reserved must be 0", who);
     return SBT_OK;
 }
@@ -68,12 +76,15 @@ int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const double 
         int32_t e, a0;
     };
     std::vector<Item> items[2];  // [0]: 1024-thread shape, [1]: 512-thread shape
+    const int band_limit = tu.band_rows > 0 ? tu.band_rows : sbt::kBatchSlots;
+    const int n_ckpt = p.energy_every > 0 ? p.steps / p.energy_every : 0;
+    S.gangs.clear();
+    S.xg_floats = S.part_entries = 0;
+    S.max_bands = 0;
+    std::vector<int64_t> gang_cost;
     int64_t row_off = 0, nz_off = 0;
     for (int32_t e = 0; e < E; ++e) {
         if (n[e] < 1) return fail(SBT_EINVAL, "%s: event %d has n = %d", who, e, n[e]);
-        if (n[e] > sbt::kBatchSlots)
-            return fail(SBT_EUNSUPPORTED, "%s: event %d has %d variables (batched limit %d)", who,
-                        e, n[e], sbt::kBatchSlots);
         if (nnz[e] < 0) return fail(SBT_EINVAL, "%s: event %d has nnz < 0", who, e);
         const bool small = n[e] <= tu.split_n && n[e] <= sbt::kBatchSlotsSmall;
         sbt::BatchEvent &d = S.ev[e];
@@ -85,10 +96,32 @@ int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const double 
         d.lg_agents = lg_agents_for(n[e], p.agents, tpb_of(small), tu.fill);
         d.event_id = same_start ? p.event : p.event + e;
         d.c0_scale = c0_scale ? static_cast<float>(c0_scale[e]) : 1.0f;
-        const int A = 1 << d.lg_agents;
-        for (int a0 = 0; a0 < p.agents; a0 += A) {
-            const int used = std::min(A, p.agents - a0);
-            items[small ? 1 : 0].push_back({(static_cast<int64_t>(n[e]) + nnz[e]) * used, e, a0});
+        if (n[e] > band_limit) {
+            // row bands of balanced size, one gang per agent
+            const int bands = (n[e] + band_limit - 1) / band_limit;
+            const int rows = (n[e] + bands - 1) / bands;
+            S.max_bands = std::max(S.max_bands, bands);
+            for (int a = 0; a < p.agents; ++a) {
+                sbt::GangDesc gd{};
+                gd.e = e;
+                gd.agent = a;
+                gd.bands = bands;
+                gd.rows = rows;
+                gd.x_off = S.xg_floats;
+                gd.part_off = static_cast<int>(S.part_entries);
+                S.gangs.push_back(gd);
+                gang_cost.push_back(static_cast<int64_t>(n[e]) + nnz[e]);
+                S.xg_floats += 2 * static_cast<int64_t>(n[e]);
+                S.part_entries += static_cast<int64_t>(bands) * (n_ckpt + 1);
+            }
+            if (S.part_entries > INT32_MAX / 2)
+                return fail(SBT_EINVAL, "%s: too many row bands for 32-bit offsets", who);
+        } else {
+            const int A = 1 << d.lg_agents;
+            for (int a0 = 0; a0 < p.agents; a0 += A) {
+                const int used = std::min(A, p.agents - a0);
+                items[small ? 1 : 0].push_back({(static_cast<int64_t>(n[e]) + nnz[e]) * used, e, a0});
+            }
         }
         row_off += n[e];
         nz_off += nnz[e];
@@ -108,6 +141,22 @@ int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const double 
     }
     S.n_large = static_cast<int>(items[0].size());
     S.n_small = static_cast<int>(items[1].size());
+    // gangs: largest events first, then agent order; items gang after gang
+    std::vector<int> order(S.gangs.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int l, int r) { return gang_cost[l] > gang_cost[r]; });
+    std::vector<sbt::GangDesc> sorted;
+    sorted.reserve(order.size());
+    for (int g : order) sorted.push_back(S.gangs[g]);
+    S.gangs.swap(sorted);
+    S.gitem_gang.clear();
+    S.gitem_band.clear();
+    for (size_t g = 0; g < S.gangs.size(); ++g)
+        for (int b = 0; b < S.gangs[g].bands; ++b) {
+            S.gitem_gang.push_back(static_cast<int32_t>(g));
+            S.gitem_band.push_back(b);
+        }
     S.sum_n = row_off;
     S.sum_nnz = nz_off;
     return SBT_OK;
@@ -115,6 +164,7 @@ int make_schedule(const int32_t *n, const int64_t *nnz, int32_t E, const double 
 
 struct BatchLayout {
     size_t ev, item_e, item_a, J16, h, c0, offset, perm, sched, counter, etrace, energy, T;
+    size_t gangs, gitem_g, gitem_b, xg, gints, gpart, gclock, done;
     size_t total;
     int n_ckpt;
 };
@@ -142,6 +192,15 @@ BatchLayout make_layout(const Schedule &S, const sbt_solve_params &p) {
     L.etrace = take(sizeof(double) * E * static_cast<size_t>(L.n_ckpt) * M);
     L.energy = take(sizeof(double) * E * M);
     L.T = take(static_cast<size_t>(S.sum_n) * M);
+    const size_t G = S.gangs.size(), GI = S.gitem_gang.size();
+    L.gangs = take(sizeof(sbt::GangDesc) * G);
+    L.gitem_g = take(sizeof(int32_t) * GI);
+    L.gitem_b = take(sizeof(int32_t) * GI);
+    L.xg = take(sizeof(float) * static_cast<size_t>(S.xg_floats));
+    L.gints = take(sizeof(int32_t) * (G + 2));  // arrivals per gang, fault flag, queue
+    L.gpart = take(sizeof(double) * static_cast<size_t>(S.part_entries));
+    L.gclock = take(sizeof(int64_t) * static_cast<size_t>(S.part_entries));
+    L.done = take(sizeof(int32_t) * E);  // events whose target was reached
     L.total = off;
     return L;
 }
@@ -236,8 +295,19 @@ extern "C" int sbt_batch_plan_tuned(const int32_t *n, const int64_t *nnz, int32_
                            hipMemcpyHostToDevice, st));
     SBT_HIP(hipMemcpyAsync(ws + L.item_a, S.item_agent0.data(),
                            sizeof(int32_t) * S.item_agent0.size(), hipMemcpyHostToDevice, st));
+    if (!S.gangs.empty()) {
+        if (S.max_bands > cu_count())
+            return fail(SBT_EUNSUPPORTED, "%s: an event needs %d row bands at once, more than the "
+                        "device's %d CUs", who, S.max_bands, cu_count());
+        SBT_HIP(hipMemcpyAsync(ws + L.gangs, S.gangs.data(), sizeof(sbt::GangDesc) * S.gangs.size(),
+                               hipMemcpyHostToDevice, st));
+        SBT_HIP(hipMemcpyAsync(ws + L.gitem_g, S.gitem_gang.data(),
+                               sizeof(int32_t) * S.gitem_gang.size(), hipMemcpyHostToDevice, st));
+        SBT_HIP(hipMemcpyAsync(ws + L.gitem_b, S.gitem_band.data(),
+                               sizeof(int32_t) * S.gitem_band.size(), hipMemcpyHostToDevice, st));
+    }
     SBT_HIP(hipStreamSynchronize(st));
-    return static_cast<int>(S.item_event.size());
+    return S.items();
 }
 
 extern "C" int sbt_batch_plan(const int32_t *n, const int64_t *nnz, int32_t n_events,
@@ -313,6 +383,12 @@ extern "C" int sbt_batch_run_tuned(const sbt_dev_batch *batch, sbt_mode mode, sb
     B.best_T = out->best_T;
     B.ckpt_clock = reinterpret_cast<long long *>(out->ckpt_clock);
     int *counters = reinterpret_cast<int *>(ws + L.counter);
+    if (batch->target) {
+        if (L.n_ckpt == 0)
+            return fail(SBT_EINVAL, "%s: a target needs checkpoints (energy_every > 0)", who);
+        B.target = batch->target;
+        B.done = reinterpret_cast<int *>(ws + L.done);
+    }
 
     SBT_HIP(sbt::launch_schedule(p->steps, p->a0, reinterpret_cast<float *>(ws + L.sched), st));
     const int jprec = prec == SBT_PREC_FP16 ? sbt::kJFp16 : sbt::kJBf16;
@@ -320,7 +396,34 @@ extern "C" int sbt_batch_run_tuned(const sbt_dev_batch *batch, sbt_mode mode, sb
     hipError_t e = sbt::launch_batch_prep(jprec, B, st);
     if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch prep: %s", who, hipGetErrorString(e));
     SBT_HIP(sbt::launch_batch_reset(counters, 2, st));
+    if (B.done) SBT_HIP(sbt::launch_zero_ints(B.done, batch->n_events, st));
+    const int n_gangs = static_cast<int>(S.gangs.size());
+    if (n_gangs > 0) {
+        if (S.max_bands > cus)
+            return fail(SBT_EUNSUPPORTED, "%s: an event needs %d row bands at once, more than the "
+                        "device's %d CUs", who, S.max_bands, cus);
+        int *gints = reinterpret_cast<int *>(ws + L.gints);
+        SBT_HIP(sbt::launch_zero_ints(gints, n_gangs + 2, st));
+        B.gang_items = static_cast<int>(S.gitem_gang.size());
+        B.gitem_gang = reinterpret_cast<const int *>(ws + L.gitem_g);
+        B.gitem_band = reinterpret_cast<const int *>(ws + L.gitem_b);
+        B.gangs = reinterpret_cast<const sbt::GangDesc *>(ws + L.gangs);
+        B.xg = reinterpret_cast<float *>(ws + L.xg);
+        B.arrive = gints;
+        B.gang_fault = gints + n_gangs;
+        B.gang_counter = gints + n_gangs + 1;
+        B.gpart = reinterpret_cast<double *>(ws + L.gpart);
+        B.gclock = reinterpret_cast<long long *>(ws + L.gclock);
+    }
     if (out->step_begin) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_begin), st));
+    // gangs of row bands first (the largest events), on a persistent grid at
+    // least as large as any gang
+    if (n_gangs > 0) {
+        sbt::BatchArgs LG = B;
+        LG.grid = std::min(B.gang_items, cus);
+        e = sbt::launch_batch_gang(static_cast<int>(mode), jprec, LG, st);
+        if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: gang kernel: %s", who, hipGetErrorString(e));
+    }
     // the 1024-thread items (one workgroup per CU), then the 512-thread items
     // (two per CU), each launch a persistent grid over its own queue
     if (S.n_large > 0) {
@@ -342,6 +445,10 @@ extern "C" int sbt_batch_run_tuned(const sbt_dev_batch *batch, sbt_mode mode, sb
         if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch kernel: %s", who, hipGetErrorString(e));
     }
     if (out->step_end) SBT_HIP(hipEventRecord(static_cast<hipEvent_t>(out->step_end), st));
+    if (n_gangs > 0) {
+        e = sbt::launch_batch_gang_reduce(B, n_gangs, st);
+        if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: gang reduce: %s", who, hipGetErrorString(e));
+    }
     e = sbt::launch_batch_select(B, st);
     if (e != hipSuccess) return fail(SBT_EDEVICE, "%s: batch select: %s", who, hipGetErrorString(e));
     if (out->agent_trace)
@@ -491,6 +598,9 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     float ms = 0.0f;
     SBT_HIP(hipEventElapsedTime(&ms, e0, e1));
     out->elapsed_s = 1e-3 * ms;
+    for (int32_t e = 0; e < E; ++e)
+        if (std::isnan(out->energy[e]))
+            return fail(SBT_EDEVICE, "%s: event %d: a gang of row bands timed out at a barrier", who, e);
     return SBT_OK;
 }
 

@@ -156,13 +156,18 @@ def test_batch_deterministic_and_host_entry_point():
 
 
 def test_batch_rejects_unsupported():
+    """More row bands than CUs for one gang (the bands must run at once)
+    and couplings other than FP16 / BF16 are refused.  (Events above 9216
+    variables themselves are solved as gangs; test_gpu_gang.py.)"""
     rng = np.random.default_rng(1)
-    n = 9300
-    big = sbt.Qubo(n, rng.uniform(0, 0.7, n), np.zeros(n + 1, np.int64), np.zeros(0, np.int32),
-                   np.zeros(0), np.zeros((n, 3), np.int64))
+    n = 600
+    q = sbt.Qubo(n, rng.uniform(0, 0.7, n), np.zeros(n + 1, np.int64), np.zeros(0, np.int32),
+                 np.zeros(0), np.zeros((n, 3), np.int64))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
     with pytest.raises(sbt.SbtError) as e:
-        sbt.solve_batch([big], "dsb", "fp16", agents=4, steps=2)
-    assert e.value.code == -4
+        sbt.DeviceBatchSolver([q], "dsb", "fp16", sbt.solve_params(agents=4, steps=2),
+                              tuning=sbt.batch_tuning(band_rows=max(1, n // (cus + 1))))
+    assert e.value.code == -4 and "row bands" in str(e.value)
     evs, qs = _events(SMALL[:1])
     with pytest.raises(sbt.SbtError) as e:
         sbt.solve_batch(qs, "dsb", "fp32", agents=4, steps=2)

@@ -28,7 +28,7 @@ def test_key_is_mode_precision_agents_and_size_histogram():
 def test_defaults_and_validation():
     t = sbt.batch_tuning()
     assert sbt.tuning_dict(t) == {"split_n": 0, "tail_words": 8192, "fill": 1.0,
-                                  "from_cache": False}
+                                  "band_rows": 0, "from_cache": False}
     n = np.array([300, 5000, 60], np.int32)
     nnz = np.array([900, 15000, 100], np.int64)
     p = sbt.solve_params(agents=128, steps=100)
@@ -45,7 +45,7 @@ def test_defaults_and_validation():
     assert w(sbt.batch_tuning(fill=0.5)) >= base
     assert w(sbt.batch_tuning(split_n=4608)) >= base
     for bad in (dict(fill=0.0), dict(fill=1.5), dict(tail_words=9000), dict(tail_words=-1),
-                dict(split_n=-3)):
+                dict(split_n=-3), dict(band_rows=-1), dict(band_rows=9217)):
         assert w(sbt.batch_tuning(**bad)) == 0
         assert "tuning" in lib.sbt_last_error().decode()
     t = sbt.batch_tuning()
@@ -72,7 +72,7 @@ def test_lookup_exact_nearest_and_default(tmp_path):
         {"key": key_a, "split_n": 2304, "tail_words": 4096, "fill": 0.5, "seconds": 1.0},
         {"key": key_b, "split_n": 0, "tail_words": 8192, "fill": 1.0, "seconds": 2.0},
         {"key": "dsb fp16 M128 h=0,0,0,0,0,0,0,0,1", "split_n": 64, "tail_words": 0,
-         "fill": 0.25}]}
+         "fill": 0.25, "band_rows": 3000}]}
     path = tmp_path / "cache.json"
     path.write_text(json.dumps(cache, indent=1))
     cases = [("exact", sizes_a, "dsb", "bf16", 128),
@@ -86,12 +86,15 @@ def test_lookup_exact_nearest_and_default(tmp_path):
                        capture_output=True, text=True, env=env, timeout=120)
     assert r.returncode == 0, r.stderr
     got = json.loads(r.stdout.strip().splitlines()[-1])
-    assert got["exact"] == {"split_n": 2304, "tail_words": 4096, "fill": 0.5, "from_cache": True}
+    assert got["exact"] == {"split_n": 2304, "tail_words": 4096, "fill": 0.5, "band_rows": 0,
+                            "from_cache": True}
     assert got["near"] == got["exact"]
-    default = {"split_n": 0, "tail_words": 8192, "fill": 1.0, "from_cache": False}
+    default = {"split_n": 0, "tail_words": 8192, "fill": 1.0, "band_rows": 0,
+               "from_cache": False}
     assert got["far"] == default and got["other_mode"] == default
     assert got["other_agents"] == default
-    assert got["fp16"] == {"split_n": 64, "tail_words": 0, "fill": 0.25, "from_cache": True}
+    assert got["fp16"] == {"split_n": 64, "tail_words": 0, "fill": 0.25, "band_rows": 3000,
+                           "from_cache": True}
 
 
 def test_committed_cache_is_well_formed():
