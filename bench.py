@@ -122,7 +122,7 @@ def ttt99(make, target, M, torch, energies_of=lambda s: s.result()["agent_energy
 def precision_form(sbt, tg, torch, np):
     """1000 particles (N ~ 8.5e3), dSB, 1024 agents x 5000 steps: plain FP32
     against the 16-bit-coupling forms (one-event batch), with the energy gap
-    to the FP64 oracle (best of the first 32 agents) and both
+    to the FP64 oracle (its best over the same 1024 agents) and both
     time-to-target definitions."""
     ref = load_golden("oracle_best_precision.json")
     ev = tg.generate(tg.precision_spec(), ref["event_seed"])
@@ -131,7 +131,7 @@ def precision_form(sbt, tg, torch, np):
     e_star = ref["modes"]["dsb"]["best"]
     out = {"workload": "precision: 10-layer barrel, 1000 particles + 10% noise, event seed 200; "
                        "dSB, 1024 agents x 5000 steps", "n": q.n, "nnz": q.nnz,
-           "oracle_best_32_agents": e_star}
+           "oracle_best_1024_agents": e_star}
     prm = lambda k, every=0: sbt.solve_params(agents=M, steps=k, seed=0, energy_every=every)
     forms = {
         "fp32": (lambda k, every=0: sbt.DeviceSolver(q, "dsb", prm(k, every),
@@ -400,7 +400,8 @@ def stream_bytes_dsb(n, nnz, agents):
 def stress_form(sbt, tg, torch, np, K=10000):
     """5000 particles (N ~ 2.1e5), bSB, 512 agents x 10000 steps on the
     streaming kernel: FP8 couplings (the workload's storage) and FP32, spins
-    in azimuth order, FP64 energies of every agent on the GPU."""
+    in azimuth order, FP64 energies of every agent on the GPU; the tiled
+    streaming step's launch time beside them."""
     ev = tg.generate(tg.stress_spec(), 300)
     hits = ev.hits_struct()
     bp = sbt.build_params_default()
@@ -452,6 +453,25 @@ def stress_form(sbt, tg, torch, np, K=10000):
                                   "bytes_per_launch": byts}}
         del s
         torch.cuda.empty_cache()
+    # the tiled streaming step (row tiles, column unions staged in LDS) on
+    # the same event, for comparison (FP32, a shorter run: per-launch cost is
+    # constant)
+    k_cmp = min(K, 200)
+    s = sbt.DeviceSolver(q, "bsb", sbt.solve_params(agents=M, steps=k_cmp, seed=0,
+                                                     kernel="stream_tile"))
+    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.record()
+    e.record()
+    torch.cuda.synchronize()
+    s._dr.step_begin, s._dr.step_end = b.cuda_event, e.cuda_event
+    s.run()
+    torch.cuda.synchronize()
+    launch_s = b.elapsed_time(e) * 1e-3 / k_cmp
+    byts = stream_bytes(q.n, q.nnz, M, 4)
+    out["fp32_tiled"] = {"kernel": "sb_stream_tile", "steps": k_cmp, "launch_ms": launch_s * 1e3,
+                         "hbm_frac": byts / launch_s / 1e9 / MI355X_HBM_GBS}
+    del s
+    torch.cuda.empty_cache()
     out["fp8_rel_gap_vs_fp32"] = (out["fp8"]["best"] - out["fp32"]["best"]) / abs(out["fp32"]["best"])
     return out
 

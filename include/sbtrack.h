@@ -183,20 +183,35 @@ typedef enum {
     SBT_KERNEL_AUTO = 0,
     SBT_KERNEL_RESIDENT = 1, /* one launch for all steps; a workgroup owns
                                 whole agents, positions live in LDS        */
-    SBT_KERNEL_STREAM = 2    /* one launch per step; state streams through
+    SBT_KERNEL_STREAM = 2,   /* one launch per step; state streams through
                                 HBM, lanes are agents                       */
+    SBT_KERNEL_STREAM_TILE = 3 /* bSB / aSB: the streaming step with rows in
+                                tiles of 8 whose neighbours' positions (the
+                                tile's column union, up to 256 columns x 64
+                                agents) are staged in LDS each step; the
+                                same arithmetic, bit-identical results.
+                                Only on request (AUTO never picks it): it
+                                moves fewer bytes but measured slower     */
 } sbt_kernel;
 
 /* Storage precision of the couplings J.  The paper fixes no number format
  * (section "Simulated Bifurcation" states the dynamics only); the narrow
  * forms are this library's: only J is stored narrower, accumulation is FP32
  * and energies are FP64 of the exact QUBO throughout.
- * FP8 is OCP e4m3 with one FP32 scale per row, max_j |J_ij| / 448. */
+ * FP8 is OCP e4m3 with one FP32 scale per row, max_j |J_ij| / 448;
+ * FP8_BLOCK the same with one FP32 scale per block of 8 consecutive stored
+ * couplings of a row (the last block of a row may be shorter);
+ * BF16X2 stores each FP32 coupling as a BF16 pair hi = bf16(J),
+ * lo = bf16(J - hi), used as hi + lo (16 significant bits).
+ * FP16 and BF16 are the batch functions' forms; FP8, FP8_BLOCK and BF16X2
+ * run on the streaming kernel. */
 typedef enum {
     SBT_PREC_FP32 = 0,
     SBT_PREC_FP16 = 1,
     SBT_PREC_BF16 = 2,
-    SBT_PREC_FP8 = 3
+    SBT_PREC_FP8 = 3,
+    SBT_PREC_FP8_BLOCK = 4,
+    SBT_PREC_BF16X2 = 5
 } sbt_precision;
 
 /* Solver parameters (section "Simulated Bifurcation" and Results: a0 = dt = 1,
@@ -217,8 +232,9 @@ typedef struct {
     int32_t tpb;          /* resident kernel threads per workgroup (64, 256,  */
                           /* 512, 1024); 0 = chosen from the shape           */
     int32_t precision;    /* sbt_precision of J for sbt_solve/sbt_solve_dev: */
-                          /* FP32 (any kernel) or FP8 (stream kernel only);  */
-                          /* the batch functions take theirs as an argument  */
+                          /* FP32 (any kernel) or FP8, FP8_BLOCK, BF16X2     */
+                          /* (stream kernel only); the batch functions take  */
+                          /* theirs as an argument                           */
     int32_t reserved;     /* must be 0                                       */
 } sbt_solve_params;
 

@@ -23,6 +23,12 @@ FP32 and energies FP64.  This module writes out the 16-bit and FP8 forms:
   row), code_ij = e4m3(min(max(fl32(J_ij / s_i), -448), 448)) and the
   coupling used is J'_ij = fl32(s_i * e4m3_value(code_ij)).  J enters in
   FP32 (the kernels' coupling type).
+* per-block scaling: the same with one scale per block of 8 consecutive
+  stored couplings of a row, in CSR order (the last block of a row may be
+  shorter).
+* BF16 pair ("hi + lo"): hi = bf16(J32), lo = bf16(J32 - hi) (the
+  difference is exact in binary32), coupling used hi + lo (exact in
+  binary32: 16 significant bits).
 """
 from __future__ import annotations
 
@@ -141,3 +147,42 @@ def fp8_rows(J: sp.csr_matrix):
         vals[lo:hi] = (s * e4m3_value(codes[lo:hi]).astype(np.float32)).astype(np.float32)
     Jq = sp.csr_matrix((vals.astype(np.float64), J.indices.copy(), J.indptr.copy()), shape=J.shape)
     return Jq, codes, scale
+
+
+def fp8_blocks(J: sp.csr_matrix, block: int = 8):
+    """Per-block FP8 form: blocks of `block` consecutive stored couplings of
+    each row.  Returns (J' as CSR FP64 of FP32 values, codes per stored
+    entry, FP32 scale per block in row-major block order)."""
+    J = sp.csr_matrix(J)
+    J.sort_indices()
+    J32 = J.data.astype(np.float32)
+    codes = np.zeros(J32.shape[0], dtype=np.uint8)
+    vals = np.zeros(J32.shape[0], dtype=np.float32)
+    scales = []
+    for i in range(J.shape[0]):
+        for lo in range(J.indptr[i], J.indptr[i + 1], block):
+            hi = min(lo + block, J.indptr[i + 1])
+            mx = np.float32(np.max(np.abs(J32[lo:hi])))
+            s = np.float32(mx / np.float32(E4M3_MAX)) if mx > 0 else np.float32(1.0)
+            scales.append(s)
+            q = np.clip((J32[lo:hi] / s).astype(np.float32), -E4M3_MAX, E4M3_MAX)
+            codes[lo:hi] = e4m3_encode(q)
+            vals[lo:hi] = (s * e4m3_value(codes[lo:hi]).astype(np.float32)).astype(np.float32)
+    Jq = sp.csr_matrix((vals.astype(np.float64), J.indices.copy(), J.indptr.copy()), shape=J.shape)
+    return Jq, codes, np.array(scales, dtype=np.float32)
+
+
+def bf16x2_value(v) -> np.ndarray:
+    """hi + lo with hi = bf16(fl32(v)), lo = bf16(fl32(v) - hi), as FP64."""
+    v32 = np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+    hi = bf16_value(v32)
+    rest = v32 - hi                       # exact: fewer than 24 significant bits
+    assert np.array_equal(rest.astype(np.float32).astype(np.float64), rest)
+    return hi + bf16_value(rest)          # exact in binary32
+
+
+def bf16x2_couplings(J: sp.csr_matrix) -> sp.csr_matrix:
+    """The BF16-pair coupling form: every stored J_ij as hi + lo."""
+    J = sp.csr_matrix(J, dtype=np.float64, copy=True)
+    J.data = bf16x2_value(J.data)
+    return J

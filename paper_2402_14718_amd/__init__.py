@@ -22,9 +22,11 @@ from ._lib import (SBT_BSB, SBT_DSB, SBT_KERNEL_AUTO, SBT_KERNEL_RESIDENT, SBT_K
                    SbtError, check, load)
 
 MODES = {"bsb": SBT_BSB, "dsb": SBT_DSB, "asb": _lib.SBT_ASB}
-KERNELS = {"auto": SBT_KERNEL_AUTO, "resident": SBT_KERNEL_RESIDENT, "stream": SBT_KERNEL_STREAM}
+KERNELS = {"auto": SBT_KERNEL_AUTO, "resident": SBT_KERNEL_RESIDENT, "stream": SBT_KERNEL_STREAM,
+           "stream_tile": _lib.SBT_KERNEL_STREAM_TILE}
 PRECISIONS = {"fp32": _lib.SBT_PREC_FP32, "fp16": _lib.SBT_PREC_FP16, "bf16": _lib.SBT_PREC_BF16,
-              "fp8": _lib.SBT_PREC_FP8}
+              "fp8": _lib.SBT_PREC_FP8, "fp8_block": _lib.SBT_PREC_FP8_BLOCK,
+              "bf16x2": _lib.SBT_PREC_BF16X2}
 KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
 
 HIT_DTYPE = np.dtype([("hit_id", "<i8"), ("layer", "<i4"), ("pad", "<i4"),

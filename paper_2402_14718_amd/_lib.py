@@ -24,6 +24,7 @@ SBT_ASB = 2
 SBT_KERNEL_AUTO = 0
 SBT_KERNEL_RESIDENT = 1
 SBT_KERNEL_STREAM = 2
+SBT_KERNEL_STREAM_TILE = 3
 
 
 class SbtHit(C.Structure):
@@ -83,6 +84,8 @@ SBT_PREC_FP32 = 0
 SBT_PREC_FP16 = 1
 SBT_PREC_BF16 = 2
 SBT_PREC_FP8 = 3
+SBT_PREC_FP8_BLOCK = 4
+SBT_PREC_BF16X2 = 5
 
 
 class SbtDevBatch(C.Structure):

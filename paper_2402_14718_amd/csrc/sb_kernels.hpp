@@ -105,10 +105,30 @@ struct StreamArgs {
     const double *scal;
     float *y;
     const float *sched;          // [K] a0 - a_k
-    const uint8_t *J8;           // [padded nnz] FP8 e4m3 couplings (FP8 form)
+    const uint8_t *J8;           // [padded nnz] FP8 e4m3 couplings (FP8 forms)
     const float *rowscale;       // [n] per-row FP32 scale of J8
+    const float *blkscale;       // [padded nnz / kStreamChunk] per-block scale of J8
+    const uint32_t *J2;          // [padded nnz] BF16 hi << 16 | BF16 lo
     int sign_stride;             // stream_sign_stride(M)
 };
+
+// Row tiles of the streaming bSB / aSB step (sb_stream_tile.hip): tiles of
+// kTileRows consecutive rows; each tile's distinct columns, at most
+// kTileCols of them, staged in LDS per step (64 agents x 4 B per column).
+constexpr int kTileRows = 8;
+constexpr int kTileCols = 256;
+
+struct TileArgs {
+    int *tile_cols;              // [ntile * kTileCols] distinct columns, ascending
+    int *tile_u;                 // [ntile] how many of them are staged
+    uint16_t *ploc;              // [padded nnz] index of the column in its tile's
+                                 //   list, or 0xFFFF: read from global memory
+};
+
+hipError_t launch_tile_union(int n, const int *prow, const int *pcol, const TileArgs &T,
+                             hipStream_t st);
+hipError_t launch_stream_tile(int mode, int jprec, const StreamArgs &A, const TileArgs &T, int k,
+                              const float *xin, float *xout, hipStream_t st);
 
 // ---------------------------------------------------------------- batch
 
@@ -119,7 +139,10 @@ constexpr int kBatchSlots = kBatchTPB * kBatchSPT;  // largest n * agents per it
 constexpr int kBatchSlotsSmall = kBatchTPBSmall * kBatchSPT;
 constexpr int kBatchTailCap = 8192;                 // default LDS words for couplings past the
                                                     //   slots' register capacity (32 KB)
-enum : int { kJFp16 = 0, kJBf16 = 1, kJFp32 = 2, kJFp8 = 3 };  // coupling formats
+// coupling formats: 16-bit (batch), FP32, FP8 e4m3 with a per-row scale,
+// FP8 e4m3 with a per-block scale (blocks of kStreamChunk couplings of a
+// row), BF16 hi + lo pairs (streaming kernels)
+enum : int { kJFp16 = 0, kJBf16 = 1, kJFp32 = 2, kJFp8 = 3, kJFp8Blk = 4, kJBf16x2 = 5 };
 
 // LDS bytes of one batch workgroup of `tpb` threads with `tail_words` of
 // staged couplings: two position buffers (slots plus one pad word per lane
@@ -230,6 +253,13 @@ hipError_t launch_resident_reg_asb(const ResidentArgs &A, const ResidentShape &S
 hipError_t launch_stream2(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
                           float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st);
 hipError_t launch_sign_planes(int n, int M, const float *x, uint64_t *S, hipStream_t st);
+// FP8 with one scale per block of kStreamChunk padded couplings; BF16 hi +
+// lo pairs (both over the padded rows)
+// (over the padded rows: prow[n] entries of capacity pnnz)
+hipError_t launch_quantize_fp8_blocks(int n, const int *prow, int64_t pnnz, const float *J,
+                                      uint8_t *J8, float *blkscale, hipStream_t st);
+hipError_t launch_split_bf16x2(int n, const int *prow, int64_t pnnz, const float *J, uint32_t *J2,
+                               hipStream_t st);
 hipError_t launch_quantize_fp8(int n, const int *row_ptr, const float *J, uint8_t *J8, float *scale,
                                hipStream_t st);
 // Padded copy (col, J) -> (pcol, pJ) with row pointers prow; pcol and pJ hold

@@ -19,8 +19,11 @@
 // XCDs round robin) sweeps one contiguous range of rows: neighbouring rows
 // share gathered lines, which then stay in that XCD's L2.
 //
-// Couplings are FP32, or FP8 (OCP e4m3) with one FP32 scale per row (the
-// reduced-precision form): J_ij = scale_i * e4m3(code_ij).
+// Couplings are FP32; FP8 (OCP e4m3) with one FP32 scale per row,
+// J_ij = scale_i * e4m3(code_ij), or per block of eight consecutive stored
+// couplings of a row (the padded chunk, so one scale per chunk load); or a
+// BF16 hi + lo pair per coupling, J_ij = hi + lo (the reduced-precision
+// forms).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -67,10 +70,17 @@ __device__ __forceinline__ float e4m3_to_f32(uint32_t word) {
     return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(word), SEL);
 }
 
+// The BF16 pair of a coupling as FP32: hi + lo (exact in FP32: lo is the
+// rounded remainder of hi, at most 16 significant bits below it).
+__device__ __forceinline__ float bf16x2_value(uint32_t w) {
+    return __uint_as_float(w & 0xFFFF0000u) + __uint_as_float(w << 16);
+}
+
 // Couplings p .. p + kChunk - 1 (p a multiple of kChunk).
 template <int JP>
 __device__ __forceinline__ void load_chunk(const StreamArgs &A, int p, float scale, float (&w)[kChunk]) {
-    if constexpr (JP == kJFp8) {
+    if constexpr (JP == kJFp8 || JP == kJFp8Blk) {
+        if constexpr (JP == kJFp8Blk) scale = A.blkscale[p / kChunk];
         const uint2 codes = *reinterpret_cast<const uint2 *>(A.J8 + p);
         w[0] = scale * e4m3_to_f32<0>(codes.x);
         w[1] = scale * e4m3_to_f32<1>(codes.x);
@@ -80,6 +90,12 @@ __device__ __forceinline__ void load_chunk(const StreamArgs &A, int p, float sca
         w[5] = scale * e4m3_to_f32<1>(codes.y);
         w[6] = scale * e4m3_to_f32<2>(codes.y);
         w[7] = scale * e4m3_to_f32<3>(codes.y);
+    } else if constexpr (JP == kJBf16x2) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(A.J2 + p);
+        const uint4 b = *reinterpret_cast<const uint4 *>(A.J2 + p + 4);
+        const uint32_t v[kChunk] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int u = 0; u < kChunk; ++u) w[u] = bf16x2_value(v[u]);
     } else {
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) w[u] = A.J[p + u];
@@ -174,6 +190,43 @@ __global__ __launch_bounds__(256) void quantize_fp8_rows(int n, const int *__res
         const float q = fminf(fmaxf(J[p] / s, -448.0f), 448.0f);
         J8[p] = static_cast<uint8_t>(__builtin_amdgcn_cvt_pk_fp8_f32(q, q, 0, false) & 0xFF);
     }
+}
+
+// FP8 with one FP32 scale per block of kChunk padded couplings:
+// scale_b = max |J| over the block / 448 (1 for an all-zero block),
+// code = e4m3(J / scale_b) as for the per-row form.
+__global__ __launch_bounds__(256) void quantize_fp8_blocks(int64_t nblk, const int *__restrict__ prow_end,
+                                                           const float *__restrict__ J,
+                                                           uint8_t *__restrict__ J8,
+                                                           float *__restrict__ blkscale) {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (b >= nblk || b * kChunk >= *prow_end) return;  // blocks of the padded rows only
+    float mx = 0.0f;
+    for (int u = 0; u < kChunk; ++u) mx = fmaxf(mx, __builtin_fabsf(J[b * kChunk + u]));
+    const float s = mx > 0.0f ? mx / 448.0f : 1.0f;
+    blkscale[b] = s;
+    for (int u = 0; u < kChunk; ++u) {
+        const float q = fminf(fmaxf(J[b * kChunk + u] / s, -448.0f), 448.0f);
+        J8[b * kChunk + u] = static_cast<uint8_t>(__builtin_amdgcn_cvt_pk_fp8_f32(q, q, 0, false) & 0xFF);
+    }
+}
+
+// BF16 to nearest, ties to even, of an FP32 value (its upper 16 bits).
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// hi = bf16(J), lo = bf16(J - hi) (the difference is exact in FP32).
+__global__ __launch_bounds__(256) void split_bf16x2(int64_t pnnz, const int *__restrict__ prow_end,
+                                                    const float *__restrict__ J,
+                                                    uint32_t *__restrict__ J2) {
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (q >= pnnz || q >= *prow_end) return;  // entries of the padded rows only
+    const float j = J[q];
+    const uint32_t hi = bf16_bits(j);
+    const uint32_t lo = bf16_bits(j - __uint_as_float(hi << 16));
+    J2[q] = hi << 16 | lo;
 }
 
 template <int MODE, int JP, int APL, bool NT>
@@ -325,6 +378,23 @@ hipError_t launch_stream_pack(int n, const int *row_ptr, const int *col, const f
     return hipGetLastError();
 }
 
+hipError_t launch_quantize_fp8_blocks(int n, const int *prow, int64_t pnnz, const float *J,
+                                      uint8_t *J8, float *blkscale, hipStream_t st) {
+    const int64_t nblk = pnnz / kChunk;
+    if (nblk > 0)
+        quantize_fp8_blocks<<<static_cast<unsigned>((nblk + 255) / 256), 256, 0, st>>>(
+            nblk, prow + n, J, J8, blkscale);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_bf16x2(int n, const int *prow, int64_t pnnz, const float *J, uint32_t *J2,
+                               hipStream_t st) {
+    if (pnnz > 0)
+        split_bf16x2<<<static_cast<unsigned>((pnnz + 255) / 256), 256, 0, st>>>(pnnz, prow + n, J,
+                                                                              J2);
+    return hipGetLastError();
+}
+
 hipError_t launch_quantize_fp8(int n, const int *row_ptr, const float *J, uint8_t *J8, float *scale,
                                hipStream_t st) {
     quantize_fp8_rows<<<(n + 255) / 256, 256, 0, st>>>(n, row_ptr, J, J8, scale);
@@ -359,21 +429,31 @@ hipError_t launch_stream_gather(int jprec, const StreamArgs &A, int k, const flo
         const int grid = (total + 7) / 8 * 8;
         if (jprec == kJFp8)
             sb_stream_v4<MODE, kJFp8, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
+        else if (jprec == kJFp8Blk)
+            sb_stream_v4<MODE, kJFp8Blk, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
+        else if (jprec == kJBf16x2)
+            sb_stream_v4<MODE, kJBf16x2, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
         else
             sb_stream_v4<MODE, kJFp32, NT><<<grid, 256, 0, st>>>(A, k, xin, xout);
         return hipGetLastError();
     }
-    return jprec == kJFp8 ? launch_stream_apl<MODE, kJFp8, NT>(A, k, xin, xout, nullptr, nullptr, st)
-                          : launch_stream_apl<MODE, kJFp32, NT>(A, k, xin, xout, nullptr, nullptr, st);
+    switch (jprec) {
+        case kJFp8: return launch_stream_apl<MODE, kJFp8, NT>(A, k, xin, xout, nullptr, nullptr, st);
+        case kJFp8Blk: return launch_stream_apl<MODE, kJFp8Blk, NT>(A, k, xin, xout, nullptr, nullptr, st);
+        case kJBf16x2: return launch_stream_apl<MODE, kJBf16x2, NT>(A, k, xin, xout, nullptr, nullptr, st);
+        default: return launch_stream_apl<MODE, kJFp32, NT>(A, k, xin, xout, nullptr, nullptr, st);
+    }
 }
 
 template <bool NT>
 hipError_t launch_stream_nt(int mode, int jprec, const StreamArgs &A, int k, const float *xin,
                             float *xout, const uint64_t *Sin, uint64_t *Sout, hipStream_t st) {
-    if (mode == kDSB)
-        return jprec == kJFp8
-                   ? launch_stream_apl<kDSB, kJFp8, NT>(A, k, xin, xout, Sin, Sout, st)
-                   : launch_stream_apl<kDSB, kJFp32, NT>(A, k, xin, xout, Sin, Sout, st);
+    if (mode == kDSB) switch (jprec) {
+            case kJFp8: return launch_stream_apl<kDSB, kJFp8, NT>(A, k, xin, xout, Sin, Sout, st);
+            case kJFp8Blk: return launch_stream_apl<kDSB, kJFp8Blk, NT>(A, k, xin, xout, Sin, Sout, st);
+            case kJBf16x2: return launch_stream_apl<kDSB, kJBf16x2, NT>(A, k, xin, xout, Sin, Sout, st);
+            default: return launch_stream_apl<kDSB, kJFp32, NT>(A, k, xin, xout, Sin, Sout, st);
+        }
     return mode == kASB ? launch_stream_gather<kASB, NT>(jprec, A, k, xin, xout, st)
                         : launch_stream_gather<kBSB, NT>(jprec, A, k, xin, xout, st);
 }

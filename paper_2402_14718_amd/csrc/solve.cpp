@@ -23,7 +23,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t J = 0, h = 0, scal = 0, prep = 0, perm = 0, sched = 0, xa = 0, xb = 0, y = 0, epart = 0,
-           etrace = 0, S0 = 0, S1 = 0, J8 = 0, rowscale = 0, prow = 0, pcol = 0, pJ = 0;
+           etrace = 0, S0 = 0, S1 = 0, J8 = 0, rowscale = 0, prow = 0, pcol = 0, pJ = 0,
+           tile_cols = 0, tile_u = 0, ploc = 0, blkscale = 0, J2 = 0;
     size_t total = 0;
     int n_ckpt = 0;
 };
@@ -69,6 +70,17 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
         L.J8 = take(pnnz);
         L.rowscale = take(sizeof(float) * n);
     }
+    if (prec == SBT_PREC_FP8_BLOCK) {
+        L.J8 = take(pnnz);
+        L.blkscale = take(sizeof(float) * (pnnz / sbt::kStreamChunk));
+    }
+    if (prec == SBT_PREC_BF16X2) L.J2 = take(sizeof(uint32_t) * pnnz);
+    if (mode != SBT_DSB) {  // row tiles of the tiled streaming step
+        const size_t ntile = (static_cast<size_t>(n) + sbt::kTileRows - 1) / sbt::kTileRows;
+        L.tile_cols = take(sizeof(int32_t) * ntile * sbt::kTileCols);
+        L.tile_u = take(sizeof(int32_t) * ntile);
+        L.ploc = take(sizeof(uint16_t) * pnnz);
+    }
     L.total = off;
     return L;
 }
@@ -83,11 +95,11 @@ int check_params(const sbt_solve_params &p, const char *who) {
     if (p.steps < 1) return fail(SBT_EINVAL, "%s: steps must be >= 1", who);
     if (p.energy_every < 0) return fail(SBT_EINVAL, "%s: energy_every must be >= 0", who);
     if (p.event < 0) return fail(SBT_EINVAL, "%s: event must be >= 0", who);
-    if (p.kernel < SBT_KERNEL_AUTO || p.kernel > SBT_KERNEL_STREAM)
+    if (p.kernel < SBT_KERNEL_AUTO || p.kernel > SBT_KERNEL_STREAM_TILE)
         return fail(SBT_EINVAL, "%s: unknown kernel %d", who, p.kernel);
     if (p.tpb != 0 && p.tpb != 64 && p.tpb != 256 && p.tpb != 512 && p.tpb != 1024)
         return fail(SBT_EINVAL, "%s: tpb must be 0, 64, 256, 512 or 1024", who);
-    if (p.precision < SBT_PREC_FP32 || p.precision > SBT_PREC_FP8)
+    if (p.precision < SBT_PREC_FP32 || p.precision > SBT_PREC_BF16X2)
         return fail(SBT_EINVAL, "%s: unknown precision %d", who, p.precision);
     if (p.reserved != 0) return fail(SBT_EINVAL, "%s: reserved must be 0", who);
     return SBT_OK;
@@ -179,12 +191,24 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
     if (p.precision == SBT_PREC_FP16 || p.precision == SBT_PREC_BF16)
         return fail(SBT_EUNSUPPORTED,
                     "16-bit couplings are solved by the batch functions (sbt_solve_batch)");
-    if (p.precision == SBT_PREC_FP8) {
+    // AUTO streams without row tiles: the tiled step (neighbours staged in
+    // LDS) measured about 9x slower per step on the stress event, its
+    // staging phase keeping too few bytes in flight per CU
+    const int stream_kind = SBT_KERNEL_STREAM;
+    if (p.kernel == SBT_KERNEL_STREAM_TILE && mode == SBT_DSB)
+        return fail(SBT_EUNSUPPORTED, "the tiled streaming step is for bSB and aSB (dSB reads "
+                    "sign planes)");
+    if (p.precision == SBT_PREC_FP8 || p.precision == SBT_PREC_FP8_BLOCK ||
+        p.precision == SBT_PREC_BF16X2) {
         if (p.kernel == SBT_KERNEL_RESIDENT)
-            return fail(SBT_EUNSUPPORTED, "FP8 coupling storage runs on the streaming kernel only");
-        return SBT_KERNEL_STREAM;
+            return fail(SBT_EUNSUPPORTED, "FP8 and BF16-pair coupling storage run on the streaming "
+                        "kernel only");
+        if (p.kernel == SBT_KERNEL_STREAM_TILE && p.precision != SBT_PREC_FP8)
+            return fail(SBT_EUNSUPPORTED, "the tiled streaming step holds FP32 or per-row FP8 "
+                        "couplings");
+        return p.kernel == SBT_KERNEL_AUTO ? stream_kind : p.kernel;
     }
-    if (p.kernel == SBT_KERNEL_STREAM) return SBT_KERNEL_STREAM;
+    if (p.kernel == SBT_KERNEL_STREAM || p.kernel == SBT_KERNEL_STREAM_TILE) return p.kernel;
     if (p.kernel == SBT_KERNEL_RESIDENT) {
         if (S.tpb == 0)
             return fail(SBT_EUNSUPPORTED, "resident kernel: n = %d does not fit in LDS", n);
@@ -195,7 +219,7 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
     // 64-lane waves (measured: at 1024 agents and n = 8.5e3 streaming is
     // 2.6x faster)
     if (S.tpb != 0 && (S.rc > 0 || p.agents <= 128)) return SBT_KERNEL_RESIDENT;
-    return SBT_KERNEL_STREAM;
+    return stream_kind;
 }
 
 #define SBT_HIP(call)                                                                        \
@@ -351,13 +375,35 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         A.y = dy;
         A.sched = sched;
         A.sign_stride = sbt::stream_sign_stride(M);
-        const bool fp8 = p->precision == SBT_PREC_FP8;
-        if (fp8) {
+        int jprec = sbt::kJFp32;
+        const size_t pnnz = static_cast<size_t>(nnz) + (sbt::kStreamChunk - 1) * static_cast<size_t>(n);
+        if (p->precision == SBT_PREC_FP8) {
             SBT_HIP(sbt::launch_quantize_fp8(n, prow, pJ, J8, rowscale, st));
             A.J8 = J8;
             A.rowscale = rowscale;
+            jprec = sbt::kJFp8;
+        } else if (p->precision == SBT_PREC_FP8_BLOCK) {
+            // blocks are the padded rows' chunks of 8 (one scale per chunk load)
+            float *blk = reinterpret_cast<float *>(ws + L.blkscale);
+            SBT_HIP(sbt::launch_quantize_fp8_blocks(n, prow, static_cast<int64_t>(pnnz), pJ, J8, blk,
+                                                    st));
+            A.J8 = J8;
+            A.blkscale = blk;
+            jprec = sbt::kJFp8Blk;
+        } else if (p->precision == SBT_PREC_BF16X2) {
+            uint32_t *J2 = reinterpret_cast<uint32_t *>(ws + L.J2);
+            SBT_HIP(sbt::launch_split_bf16x2(n, prow, static_cast<int64_t>(pnnz), pJ, J2, st));
+            A.J2 = J2;
+            jprec = sbt::kJBf16x2;
         }
-        const int jprec = fp8 ? sbt::kJFp8 : sbt::kJFp32;
+        const bool tiled = kernel == SBT_KERNEL_STREAM_TILE;
+        sbt::TileArgs T{};
+        if (tiled) {
+            T.tile_cols = reinterpret_cast<int *>(ws + L.tile_cols);
+            T.tile_u = reinterpret_cast<int *>(ws + L.tile_u);
+            T.ploc = reinterpret_cast<uint16_t *>(ws + L.ploc);
+            SBT_HIP(sbt::launch_tile_union(n, prow, pcol, T, st));
+        }
         // dSB: x, y in place, signs ping-pong between S0 and S1;
         // bSB: positions ping-pong between xa and xb
         float *xin = xa, *xout = xb;
@@ -365,7 +411,10 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         if (mode == SBT_DSB) SBT_HIP(sbt::launch_sign_planes(n, M, xa, S0, st));
         int ck = 0;
         for (int k = 0; k < K; ++k) {
-            SBT_HIP(sbt::launch_stream2(static_cast<int>(mode), jprec, A, k, xin, xout, Sin, Sout, st));
+            if (tiled)
+                SBT_HIP(sbt::launch_stream_tile(static_cast<int>(mode), jprec, A, T, k, xin, xout, st));
+            else
+                SBT_HIP(sbt::launch_stream2(static_cast<int>(mode), jprec, A, k, xin, xout, Sin, Sout, st));
             std::swap(xin, xout);
             std::swap(Sin, Sout);
             if (p->energy_every > 0 && (k + 1) % p->energy_every == 0) {

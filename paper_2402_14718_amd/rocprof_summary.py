@@ -32,6 +32,7 @@ KERNEL_SOURCES = {
     "sb_stream": ["csrc/sb_stream.hip", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
     "sb_batch": ["csrc/sb_batch.hip", "csrc/sb_batch_step.hpp", "csrc/sb_batch_mode.hip",
                  "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
+    "sb_batch_gang": ["csrc/sb_batch_gang.hip", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
 }
 COPY_BYTES = 256 << 20
 
@@ -67,6 +68,21 @@ def pick(table, regex):
     raise KeyError(regex)
 
 
+def pick_all(table, regex):
+    """Every kernel whose name matches: [(name, {counter: [values]})]."""
+    out = [(name, v) for name, v in table.items() if re.search(regex, name)]
+    if not out:
+        raise KeyError(regex)
+    return out
+
+
+def per_solve(matches, counter):
+    """Sum over the matched kernels (one launch each per solve, e.g. the
+    batch kernel's two workgroup shapes) of the counter's mean per
+    dispatch."""
+    return sum(sum(v[counter]) / len(v[counter]) for _, v in matches if counter in v)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--title", required=True)
@@ -94,8 +110,10 @@ def main(argv=None):
     for r in rows[:12]:
         lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.2f} | "
                      f"{float(r['TotalDurationNs'])/1e3:.1f} | {float(r['Percentage']):.1f} |")
+    # per launch of the kernel; when the regex matches several kernels (one
+    # launch each per solve), the sum of their mean durations: per solve
     dom = [r for r in rows if re.search(a.kernel, r["Name"])]
-    avg_ns = sum(float(r["TotalDurationNs"]) for r in dom) / max(1, sum(int(r["Calls"]) for r in dom))
+    avg_ns = sum(float(r["TotalDurationNs"]) / max(1, int(r["Calls"])) for r in dom)
 
     cf = counters(a.copy_fetch)
     cw = counters(a.copy_write)
@@ -106,16 +124,16 @@ def main(argv=None):
     f_fac = COPY_BYTES / 1024.0 / fetch_copy_kib
     w_fac = COPY_BYTES / 1024.0 / write_copy_kib
 
-    kf = counters(a.fetch)
-    kw = counters(a.write)
-    name_f, vf = pick(kf, a.kernel)
-    name_w, vw = pick(kw, a.kernel)
-    fetch_kib = sum(vf["FETCH_SIZE"]) / len(vf["FETCH_SIZE"])
-    write_kib = sum(vw["WRITE_SIZE"]) / len(vw["WRITE_SIZE"])
+    mf = pick_all(counters(a.fetch), a.kernel)
+    mw = pick_all(counters(a.write), a.kernel)
+    fetch_kib = per_solve(mf, "FETCH_SIZE")
+    write_kib = per_solve(mw, "WRITE_SIZE")
     hbm_bytes = fetch_kib * 1024 * f_fac + write_kib * 1024 * w_fac
+    names = ", ".join(f"`{n}`" for n, _ in mf)
 
     lines += ["", "## HBM bytes of the dominant kernel (rocprofv3 --pmc, one pass each)", "",
-              f"Kernel: `{name_f}`", "",
+              f"Kernel: {names}" + (" (one launch of each per solve; figures summed)"
+                                    if len(mf) > 1 else ""), "",
               "| counter | KiB per dispatch | copy calibration (KiB read for 256 MiB) | factor | bytes per launch |",
               "|---|---|---|---|---|",
               f"| FETCH_SIZE | {fetch_kib:.1f} | {fetch_copy_kib:.1f} | {f_fac:.3f} | {fetch_kib*1024*f_fac:.4g} |",
@@ -126,8 +144,8 @@ def main(argv=None):
     if a.sq:
         sq = {}
         for d in a.sq:
-            _, vs = pick(counters(d), a.kernel)
-            sq.update({c: sum(v) / len(v) for c, v in vs.items()})
+            m = pick_all(counters(d), a.kernel)
+            sq.update({c: per_solve(m, c) for c in {c for _, vs in m for c in vs}})
         lines += ["## Instruction counters (SQ, summed over the chip, per dispatch)", "",
                   "| counter | value |", "|---|---|"]
         for c, v in sorted(sq.items()):

@@ -146,3 +146,89 @@ def test_asb_energies_and_every_kernel():
     with pytest.raises(sbt.SbtError) as e:
         sbt.solve(q, "asb", agents=8, steps=10, precision="fp8", kernel="resident")
     assert e.value.code == _lib.SBT_EUNSUPPORTED
+
+
+def _dense_rows_qubo(n=1500, dense=10, deg=700, seed=3):
+    """Random symmetric QUBO whose first `dense` rows couple to `deg` others:
+    their row tile holds more couplings than the tiled step sorts (4096)."""
+    rng = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(dense):
+        js = rng.choice(np.arange(dense, n), deg, replace=False)
+        rows += [i] * deg
+        cols += list(js)
+    for i in range(dense, n):
+        js = rng.choice(n, 3, replace=False)
+        rows += [i] * 3
+        cols += list(js)
+    B = sp.coo_matrix((rng.uniform(-1, 1, len(rows)), (rows, cols)), shape=(n, n)).tocsr()
+    B = sp.triu(B + B.T, k=1)
+    B = (B + B.T).tocsr()
+    B.sort_indices()
+    return sbt.Qubo(n, rng.uniform(0, 0.7, n), B.indptr.astype(np.int64),
+                    B.indices.astype(np.int32), B.data.astype(np.float64),
+                    np.zeros((n, 3), np.int64))
+
+
+@pytest.mark.parametrize("mode", ["bsb", "asb"])
+@pytest.mark.parametrize("prec", ["fp32", "fp8"])
+@pytest.mark.parametrize("M", [64, 96, 130, 600])
+def test_tiled_step_bit_identical_to_untiled(mode, prec, M):
+    """The tiled streaming step (row tiles, column unions in LDS) against the
+    untiled one: plain event (small unions), a QUBO with tiles past the
+    4096-coupling sort (all global) and past 256 columns (part global);
+    ragged agent counts (partial 64-agent blocks)."""
+    dt = 0.1 if mode == "asb" else 1.0
+    for q in (sbt.build_qubo(tg.generate(tg.plain_spec(), 104).hits_struct()), _dense_rows_qubo()):
+        kw = dict(agents=M, steps=40, seed=3, dt=dt, precision=prec, want_state=True)
+        a = sbt.solve(q, mode, kernel="stream", **kw)
+        t = sbt.solve(q, mode, kernel="stream_tile", **kw)
+        assert t["kernel"] == "stream_tile"
+        assert np.array_equal(a["x"], t["x"]) and np.array_equal(a["y"], t["y"])
+        assert np.array_equal(a["agent_energy"], t["agent_energy"])
+
+
+def test_tiled_step_refuses_dsb():
+    q = sbt.build_qubo(tg.generate(tg.plain_spec(60), 2).hits_struct())
+    with pytest.raises(sbt.SbtError) as e:
+        sbt.solve(q, "dsb", agents=64, steps=4, kernel="stream_tile")
+    assert e.value.code == -4
+
+
+FORMS = {"fp8_block": lambda J: oquant.fp8_blocks(J)[0], "bf16x2": oquant.bf16x2_couplings}
+
+
+@pytest.mark.parametrize("prec", ["fp8_block", "bf16x2"])
+@pytest.mark.parametrize("mode", ["bsb", "dsb"])
+@pytest.mark.parametrize("dt,K,M", [(1.0, 50, 70), (0.1, 20, 96), (0.1, 10, 600)])
+def test_block_fp8_and_bf16_pair_trajectories_within_1e5(prec, mode, dt, K, M):
+    """FP8 with a scale per block of eight couplings and BF16 hi + lo pairs
+    on the streaming kernel against the oracle run with the same rounded
+    couplings (oracle.quant): 1e-5 per agent, close calls exempt, >= 90%
+    of agents; FP64 energies of the returned spins exact."""
+    ev, q, b, isg = _event(tg.plain_spec(), 100)
+    Jq = FORMS[prec](isg.J)
+    r = sbt.solve(q, mode, agents=M, steps=K, dt=dt, seed=11, precision=prec, want_state=True)
+    assert r["kernel"] == "stream"
+    ref = osb.run(Jq, isg.h, isg.c0, mode, M, K, dt=dt, seed=11, margin_steps=K)
+    err = np.linalg.norm(r["x"] - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
+    close = ref.wall_margin < 1e-6
+    if mode == "dsb":
+        close |= ref.sign_margin < 1e-6
+    ok = err <= 1e-5
+    assert np.all(ok | close), (err.max(), np.nonzero(~ok & ~close))
+    assert np.mean(ok) >= 0.9
+    T = (r["x"] >= 0).astype(np.int8)
+    e_or = oenergy.qubo_energy(q.a, b, T)
+    assert np.all(np.abs(r["agent_energy"] - e_or) <= 1e-9 * np.maximum(1.0, np.abs(e_or)))
+
+
+def test_new_forms_refused_where_not_built():
+    q = sbt.build_qubo(tg.generate(tg.plain_spec(60), 2).hits_struct())
+    for prec in ("fp8_block", "bf16x2"):
+        with pytest.raises(sbt.SbtError) as e:
+            sbt.solve(q, "bsb", agents=8, steps=4, precision=prec, kernel="resident")
+        assert e.value.code == -4
+        with pytest.raises(sbt.SbtError) as e:
+            sbt.solve(q, "bsb", agents=64, steps=4, precision=prec, kernel="stream_tile")
+        assert e.value.code == -4

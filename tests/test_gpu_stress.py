@@ -48,12 +48,14 @@ def _two_hop(b, rows):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp8"])
-@pytest.mark.parametrize("mode", ["bsb", "dsb"])
-def test_two_steps_on_sampled_rows(stress, mode, prec):
+@pytest.mark.parametrize("mode,kernel", [("bsb", "stream"), ("bsb", "stream_tile"),
+                                         ("dsb", "stream")])
+def test_two_steps_on_sampled_rows(stress, mode, kernel, prec):
     q, b, isg = stress
     K = 2
-    r = sbt.solve(q, mode, agents=M, steps=K, seed=SEED, precision=prec, kernel="stream",
+    r = sbt.solve(q, mode, agents=M, steps=K, seed=SEED, precision=prec, kernel=kernel,
                   want_state=True)
+    assert r["kernel"] == kernel
     rng = np.random.default_rng(11)
     rows = np.sort(rng.choice(q.n, 32, replace=False))
     s1, s2 = _two_hop(b, rows)
@@ -82,9 +84,23 @@ def test_full_length_energies_and_best(stress):
     energies of sampled agents against the oracle on the whole QUBO."""
     q, b, _ = stress
     r = sbt.solve(q, "bsb", agents=M, steps=400, seed=0, precision="fp8", want_state=True)
+    assert r["kernel"] == "stream"
     T = (r["x"] >= 0).astype(np.int8)
     cols = np.array([0, 1, 63, 64, 255, 256, 511, r["best_agent"]])
     e_or = oenergy.qubo_energy(q.a, b, T[:, cols])
     assert np.allclose(r["agent_energy"][cols], e_or, rtol=1e-12, atol=1e-9)
     assert r["best_agent"] == int(np.argmin(r["agent_energy"]))
     assert np.array_equal(r["T"], T[:, r["best_agent"]])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp8"])
+def test_tiled_step_equals_untiled_on_the_stress_event(stress, prec):
+    """Tiles of the stress event have up to ~700 distinct columns, so the
+    tiled step reads some columns from LDS and the rest from global memory;
+    both paths give the untiled step's positions bit for bit."""
+    q, _, _ = stress
+    kw = dict(agents=M, steps=6, seed=SEED, precision=prec, want_state=True)
+    a = sbt.solve(q, "bsb", kernel="stream", **kw)
+    t = sbt.solve(q, "bsb", kernel="stream_tile", **kw)
+    assert np.array_equal(a["x"], t["x"]) and np.array_equal(a["y"], t["y"])
+    assert np.array_equal(a["agent_energy"], t["agent_energy"])

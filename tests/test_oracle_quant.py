@@ -177,3 +177,66 @@ def test_16bit_coupling_forms_keep_the_sparsity():
         Jq = f(J)
         assert np.array_equal(Jq.indptr, J.indptr) and np.array_equal(Jq.indices, J.indices)
         assert np.array_equal(Jq.data, g(J.data))
+
+
+# ------------------------------------------------ FP8 blocks, BF16 pairs
+
+def test_fp8_blocks_partition_rows_in_blocks_of_eight():
+    rng = np.random.default_rng(2)
+    lens = [0, 1, 7, 8, 9, 16, 23]
+    rows, cols, vals = [], [], []
+    n = 40
+    for i, L in enumerate(lens):
+        cs = np.sort(rng.choice(n, L, replace=False))
+        rows += [i] * L
+        cols += list(cs)
+        vals += list(rng.normal(0, 0.2, L) * np.exp2(rng.integers(-6, 3, L)))
+    J = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    Jq, codes, scales = quant.fp8_blocks(J)
+    assert scales.shape[0] == sum((L + 7) // 8 for L in lens)
+    k = 0
+    for i in range(len(lens)):
+        lo, hi = J.indptr[i], J.indptr[i + 1]
+        for b in range(lo, hi, 8):
+            e = min(b + 8, hi)
+            blk = J.data[b:e].astype(np.float32)
+            s = scales[k]
+            k += 1
+            assert s == np.float32(np.float32(np.abs(blk).max()) / np.float32(448.0))
+            # torch's own E4M3 cast of the scaled block, decoded and rescaled
+            ref = _torch_code(np.clip(blk / s, -448, 448).astype(np.float32))
+            assert np.array_equal(codes[b:e], ref)
+            assert np.array_equal(Jq.data[b:e], (s * _torch_value(ref).astype(np.float32)).astype(
+                np.float32).astype(np.float64))
+            assert np.abs(Jq.data[b:e]).max() == np.float32(s * np.float32(448.0))
+            # relative to its block's largest coupling, error <= 2^-4
+            assert np.all(np.abs(Jq.data[b:e] - blk) <= 2.0 ** -4 * np.abs(blk).max())
+
+
+def test_fp8_blocks_beat_rows_on_mixed_scales():
+    """A row whose first block of eight couplings is near 1 and second near
+    5e-6: per-row scaling puts the small ones among the FP8 subnormals,
+    per-block scaling gives them their own scale."""
+    vals = np.array([1.0 - 0.05 * k for k in range(8)] + [5e-6 * (1 + 0.1 * k) for k in range(8)])
+    J = sp.csr_matrix((vals, ([0] * 16, np.arange(1, 17))), shape=(17, 17))
+    small = slice(8, 16)
+    er = np.abs(quant.fp8_rows(J)[0].data[small] - vals[small]) / vals[small]
+    eb = np.abs(quant.fp8_blocks(J)[0].data[small] - vals[small]) / vals[small]
+    assert eb.max() <= 2.0 ** -4 and er.max() > 4 * eb.max()
+
+
+def test_bf16x2_matches_torch_pair_and_bounds():
+    rng = np.random.default_rng(4)
+    v = rng.normal(0, 0.3, 100_000) * np.exp2(rng.integers(-30, 4, 100_000))
+    v32 = torch.from_numpy(v.astype(np.float32))
+    hi = v32.to(torch.bfloat16).to(torch.float32)
+    lo = (v32 - hi).to(torch.bfloat16).to(torch.float32)
+    ref = (hi + lo).to(torch.float64).numpy()
+    got = quant.bf16x2_value(v)
+    assert np.array_equal(got, ref)
+    x32 = v.astype(np.float32).astype(np.float64)
+    # 16 significant bits: relative error <= 2^-16
+    assert np.all(np.abs(got - x32) <= 2.0 ** -16 * np.abs(x32))
+    assert np.array_equal(got.astype(np.float32).astype(np.float64), got)
+    J = sp.random(30, 30, density=0.2, random_state=1, format="csr")
+    assert np.array_equal(quant.bf16x2_couplings(J).data, quant.bf16x2_value(J.data))
