@@ -286,7 +286,8 @@ def batch_ttt(sbt, torch, qs, prec, targets):
     return out
 
 
-def batching_form(sbt, tg, torch, np, qs, build_info, gold, warmup, steps, with_fp32=True):
+def batching_form(sbt, tg, torch, np, qs, build_info, gold, warmup, steps, with_fp32=True,
+                  with_ttt=True):
     """512 events of 20-1000 particles, dSB, 128 agents x 3000 steps: one
     persistent batched kernel (BF16 / FP16 couplings, FP32 state and
     accumulation, FP64 energies) against plain FP32 solving the events one
@@ -323,7 +324,8 @@ def batching_form(sbt, tg, torch, np, qs, build_info, gold, warmup, steps, with_
                      "rel_gap_to_oracle_best": {"mean": float(gap.mean()), "max": float(gap.max()),
                                                 "min": float(gap.min())},
                      "events_within_0.5pct_of_oracle": int(np.sum(res["energy"] <= targets)),
-                     "ttt_checkpoint": batch_ttt(sbt, torch, qs, prec, targets)}
+                     "ttt_checkpoint": (batch_ttt(sbt, torch, qs, prec, targets)
+                                        if with_ttt else None)}
         del bs
         log(f"batching: {prec} batch {tb * 1e3:.1f} ms")
     if with_fp32:
@@ -373,7 +375,8 @@ def batching_form(sbt, tg, torch, np, qs, build_info, gold, warmup, steps, with_
         out["fp32_one_event_at_a_time"] = fp32
         for prec in ("bf16", "fp16"):
             out[prec]["speedup_vs_fp32"] = t / out[prec]["seconds"]
-            a, b = out[prec]["ttt_checkpoint"]["seconds"], fp32["ttt_checkpoint"]["seconds"]
+            a = (out[prec]["ttt_checkpoint"] or {}).get("seconds")
+            b = fp32["ttt_checkpoint"]["seconds"]
             out[prec]["ttt_speedup_vs_fp32"] = (b / a) if (a and b) else None
         log("batching: FP32 one event at a time done")
     if build_info.get("gpu_all_events_s") is not None:
@@ -744,6 +747,8 @@ def main():
                          "(5000 particles) workloads and the c0 scan")
     ap.add_argument("--only", choices=["plain", "precision", "batched", "stress"],
                     help="run only this workload and print it (for profiling one kernel)")
+    ap.add_argument("--no-ttt", action="store_true",
+                    help="skip the time-to-target solves (profiling: full-length solves only)")
     ap.add_argument("--batch-host-build", action="store_true",
                     help="batching workload on host-built QUBOs, without the GPU builder's "
                          "launches (for counter collection)")
@@ -784,7 +789,8 @@ def main():
             qs, info = batching_qubos(sbt, tg, not args.batch_host_build)
             form = lambda: batching_form(sbt, tg, torch, np, qs, info,
                                          load_golden("oracle_best_batching.json"), args.warmup,
-                                         args.steps, with_fp32=not args.no_fp32)
+                                         args.steps, with_fp32=not args.no_fp32,
+                                         with_ttt=not args.no_ttt)
         else:
             form = {"plain": lambda: plain_form(sbt, tg, torch, plain_q(), args.kernel,
                                                 args.warmup, args.steps, with_ttt=False),
@@ -798,7 +804,7 @@ def main():
     gold = load_golden("oracle_best_batching.json")
     log(f"batching: sum N = {sum(q.n for q in qs)}, {len(qs)} events")
     bf = batching_form(sbt, tg, torch, np, qs, info, gold, args.warmup, args.steps,
-                       with_fp32=not args.no_fp32)
+                       with_fp32=not args.no_fp32, with_ttt=not args.no_ttt)
     head = bf["bf16"]
     result = {
         "metric": "SB spin-updates/s + time-to-best-energy, BF16/FP8 batched vs plain FP32 SB",
@@ -830,7 +836,8 @@ def main():
 
     if not args.no_forms:
         q = plain_q()
-        result["plain_form"] = plain_form(sbt, tg, torch, q, args.kernel, 2, 10)
+        result["plain_form"] = plain_form(sbt, tg, torch, q, args.kernel, 2, 10,
+                                          with_ttt=not args.no_ttt)
         log("plain form done")
         result["precision_form"] = precision_form(sbt, tg, torch, np)
         log("precision form done")
