@@ -56,15 +56,20 @@ SMALL = [(tg.plain_spec(30), 1), (tg.tiny_spec(), 4), (tg.plain_spec(60), 2),
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 @pytest.mark.parametrize("mode", ["bsb", "dsb"])
-def test_batch_trajectories_match_oracle_with_rounded_couplings(prec, mode):
+@pytest.mark.parametrize("dt", [1.0, 0.02])
+def test_batch_trajectories_match_oracle_with_rounded_couplings(prec, mode, dt):
+    """50 steps at the paper's dt = 1 (walls reached early) and at dt = 0.02
+    (no wall within the 50 steps: every rounding of the interior arithmetic
+    shows)."""
     evs, qs = _events(SMALL)
     M, K, seed = 64, 50, 21
-    ds = sbt.DeviceBatchSolver(qs, mode, prec, sbt.solve_params(agents=M, steps=K, seed=seed),
+    ds = sbt.DeviceBatchSolver(qs, mode, prec, sbt.solve_params(agents=M, steps=K, seed=seed,
+                                                               dt=dt),
                                want_agent_energy=True, want_agent_state=True)
     ds.run()
     r = ds.result()
     for e, q in enumerate(qs):
-        b, isg, ref = _oracle_run(q, prec, mode, M, K, seed, e)
+        b, isg, ref = _oracle_run(q, prec, mode, M, K, seed, e, dt=dt)
         x = r["agent_x"][e]
         err = np.linalg.norm(x - ref.x, axis=0) / np.linalg.norm(ref.x, axis=0)
         close = ref.wall_margin < 1e-6
