@@ -186,12 +186,17 @@ typedef enum {
     SBT_KERNEL_STREAM = 2,   /* one launch per step; state streams through
                                 HBM, lanes are agents                       */
     SBT_KERNEL_STREAM_TILE = 3 /* bSB / aSB: the streaming step with rows in
-                                tiles of 8 whose neighbours' positions (the
-                                tile's column union, up to 256 columns x 64
-                                agents) are staged in LDS each step; the
-                                same arithmetic, bit-identical results.
-                                Only on request (AUTO never picks it): it
-                                moves fewer bytes but measured slower     */
+                                planned tiles -- runs of consecutive rows
+                                (within blocks of 32) whose column union
+                                fits 192 columns -- whose neighbours'
+                                positions (the union x 64 agents) are staged
+                                in LDS each step; a row longer than that is
+                                read from global memory.  The same
+                                arithmetic, bit-identical results; every
+                                streaming coupling form.  Planned once per
+                                solve on the GPU; the workspace grows by
+                                6 bytes per padded coupling.  Only on
+                                request (AUTO never picks it)            */
 } sbt_kernel;
 
 /* Storage precision of the couplings J.  The paper fixes no number format

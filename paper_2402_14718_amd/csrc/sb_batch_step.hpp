@@ -386,7 +386,7 @@ __global__ __launch_bounds__(TPB, 4) void sb_batch(BatchArgs B) {
                     for_slots([&](auto sc) __attribute__((always_inline)) {
                         constexpr int S = decltype(sc)::value;
                         if constexpr (S < NA) {
-                            const int len = static_cast<int>((S < 8 ? tp_lo >> (4 * S) : tp_hi) & 15u);
+                            const int len = static_cast<int>((S < 8 ? tp_lo >> (4 * (S & 7)) : tp_hi) & 15u);
                             for (int u = 0; u < len; ++u) {
                                 const uint32_t w = tails[o + u];
                                 acc[S] = __builtin_fmaf(packed_j<JP>(w), lds_at<XO>(w), acc[S]);

@@ -112,21 +112,32 @@ struct StreamArgs {
     int sign_stride;             // stream_sign_stride(M)
 };
 
-// Row tiles of the streaming bSB / aSB step (sb_stream_tile.hip): tiles of
-// kTileRows consecutive rows; each tile's distinct columns, at most
-// kTileCols of them, staged in LDS per step (64 agents x 4 B per column).
-constexpr int kTileRows = 8;
-constexpr int kTileCols = 256;
+// Row tiles of the streaming bSB / aSB step (sb_stream_tile.hip): super
+// tiles of kTileSuper consecutive rows, each cut into tiles of consecutive
+// rows whose column union has at most `ucap` (<= kTileColsMax) entries and
+// whose padded couplings number at most kTileNnz; per step a tile's union
+// positions (64 agents x 4 B per column) and its couplings are staged in LDS.
+constexpr int kTileSuper = 32;
+constexpr int kTileColsMax = 256;
+constexpr int kTileColsDefault = 192;
+constexpr int kTileNnz = 640;
+constexpr uint16_t kTileGlobal = 0xFFFF;  // ploc of a tile read from global memory
+__host__ __device__ constexpr size_t tile_lds_bytes(int ucap) {
+    return sizeof(float) * 64 * static_cast<size_t>(ucap) + (sizeof(float) + sizeof(uint16_t)) * kTileNnz;
+}
 
 struct TileArgs {
-    int *tile_cols;              // [ntile * kTileCols] distinct columns, ascending
-    int *tile_u;                 // [ntile] how many of them are staged
-    uint16_t *ploc;              // [padded nnz] index of the column in its tile's
-                                 //   list, or 0xFFFF: read from global memory
+    int ucap;                    // columns a tile stages, kStreamChunk .. kTileColsMax
+    int2 *tile_info;             // [nsuper * kTileSuper] (first row, union size) per tile
+    int *tile_n;                 // [nsuper] tiles of each super tile
+    int *tile_cols;              // [padded nnz] a tile's union, ascending, stored from its
+                                 //   first row's padded row pointer on
+    uint16_t *ploc;              // [padded nnz] index of the coupling's column in its
+                                 //   tile's union (kTileGlobal: tile read from global)
 };
 
-hipError_t launch_tile_union(int n, const int *prow, const int *pcol, const TileArgs &T,
-                             hipStream_t st);
+hipError_t launch_tile_plan(int n, const int *prow, const int *pcol, const TileArgs &T,
+                            hipStream_t st);
 hipError_t launch_stream_tile(int mode, int jprec, const StreamArgs &A, const TileArgs &T, int k,
                               const float *xin, float *xout, hipStream_t st);
 

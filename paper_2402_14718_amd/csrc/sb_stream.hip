@@ -30,6 +30,7 @@
 
 #include "sb_device.hpp"
 #include "sb_kernels.hpp"
+#include "sb_stream_chunk.hpp"
 
 namespace sbt {
 
@@ -46,61 +47,8 @@ constexpr bool kStreamVec4 = true;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <bool NT, class T>
-__device__ __forceinline__ T ld_stream(const T *p) {
-    if constexpr (NT)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
-
-template <bool NT, class T>
-__device__ __forceinline__ void st_stream(T v, T *p) {
-    if constexpr (NT)
-        __builtin_nontemporal_store(v, p);
-    else
-        *p = v;
-}
 constexpr int kChunk = kStreamChunk;
 constexpr int kPackThreads = 1024;
-
-// FP8 e4m3 (OCP) byte `sel` of a dword -> FP32 on the conversion unit.
-template <int SEL>
-__device__ __forceinline__ float e4m3_to_f32(uint32_t word) {
-    return __builtin_amdgcn_cvt_f32_fp8(static_cast<int>(word), SEL);
-}
-
-// The BF16 pair of a coupling as FP32: hi + lo (exact in FP32: lo is the
-// rounded remainder of hi, at most 16 significant bits below it).
-__device__ __forceinline__ float bf16x2_value(uint32_t w) {
-    return __uint_as_float(w & 0xFFFF0000u) + __uint_as_float(w << 16);
-}
-
-// Couplings p .. p + kChunk - 1 (p a multiple of kChunk).
-template <int JP>
-__device__ __forceinline__ void load_chunk(const StreamArgs &A, int p, float scale, float (&w)[kChunk]) {
-    if constexpr (JP == kJFp8 || JP == kJFp8Blk) {
-        if constexpr (JP == kJFp8Blk) scale = A.blkscale[p / kChunk];
-        const uint2 codes = *reinterpret_cast<const uint2 *>(A.J8 + p);
-        w[0] = scale * e4m3_to_f32<0>(codes.x);
-        w[1] = scale * e4m3_to_f32<1>(codes.x);
-        w[2] = scale * e4m3_to_f32<2>(codes.x);
-        w[3] = scale * e4m3_to_f32<3>(codes.x);
-        w[4] = scale * e4m3_to_f32<0>(codes.y);
-        w[5] = scale * e4m3_to_f32<1>(codes.y);
-        w[6] = scale * e4m3_to_f32<2>(codes.y);
-        w[7] = scale * e4m3_to_f32<3>(codes.y);
-    } else if constexpr (JP == kJBf16x2) {
-        const uint4 a = *reinterpret_cast<const uint4 *>(A.J2 + p);
-        const uint4 b = *reinterpret_cast<const uint4 *>(A.J2 + p + 4);
-        const uint32_t v[kChunk] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u) w[u] = bf16x2_value(v[u]);
-    } else {
-#pragma unroll
-        for (int u = 0; u < kChunk; ++u) w[u] = A.J[p + u];
-    }
-}
 
 // Workgroup id -> (row block, agent block), XCD-contiguous.
 __device__ __forceinline__ bool map_block(int nrb, int nab, int &rb, int &ab) {

@@ -24,7 +24,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t J = 0, h = 0, scal = 0, prep = 0, perm = 0, sched = 0, xa = 0, xb = 0, y = 0, epart = 0,
            etrace = 0, S0 = 0, S1 = 0, J8 = 0, rowscale = 0, prow = 0, pcol = 0, pJ = 0,
-           tile_cols = 0, tile_u = 0, ploc = 0, blkscale = 0, J2 = 0;
+           tile_info = 0, tile_n = 0, tile_cols = 0, ploc = 0, blkscale = 0, J2 = 0;
     size_t total = 0;
     int n_ckpt = 0;
 };
@@ -32,9 +32,10 @@ struct Layout {
 // x is updated in place under dSB (the streaming kernel's neighbours are
 // the sign planes S0/S1), so the second position buffer exists for bSB
 // only; FP8 couplings add one byte per padded nonzero and a scale per row.
-// prow/pcol/pJ: the streaming kernel's row-padded copy of the couplings.
+// prow/pcol/pJ: the streaming kernel's row-padded copy of the couplings;
+// the tiled step (requested explicitly) adds its tile plan.
 Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, sbt_mode mode,
-                   int32_t prec) {
+                   int32_t prec, bool tiled) {
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -75,10 +76,11 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
         L.blkscale = take(sizeof(float) * (pnnz / sbt::kStreamChunk));
     }
     if (prec == SBT_PREC_BF16X2) L.J2 = take(sizeof(uint32_t) * pnnz);
-    if (mode != SBT_DSB) {  // row tiles of the tiled streaming step
-        const size_t ntile = (static_cast<size_t>(n) + sbt::kTileRows - 1) / sbt::kTileRows;
-        L.tile_cols = take(sizeof(int32_t) * ntile * sbt::kTileCols);
-        L.tile_u = take(sizeof(int32_t) * ntile);
+    if (tiled && mode != SBT_DSB) {  // the tiled streaming step's plan
+        const size_t nsuper = (static_cast<size_t>(n) + sbt::kTileSuper - 1) / sbt::kTileSuper;
+        L.tile_info = take(2 * sizeof(int32_t) * nsuper * sbt::kTileSuper);
+        L.tile_n = take(sizeof(int32_t) * nsuper);
+        L.tile_cols = take(sizeof(int32_t) * pnnz);
         L.ploc = take(sizeof(uint16_t) * pnnz);
     }
     L.total = off;
@@ -191,9 +193,6 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
     if (p.precision == SBT_PREC_FP16 || p.precision == SBT_PREC_BF16)
         return fail(SBT_EUNSUPPORTED,
                     "16-bit couplings are solved by the batch functions (sbt_solve_batch)");
-    // AUTO streams without row tiles: the tiled step (neighbours staged in
-    // LDS) measured about 9x slower per step on the stress event, its
-    // staging phase keeping too few bytes in flight per CU
     const int stream_kind = SBT_KERNEL_STREAM;
     if (p.kernel == SBT_KERNEL_STREAM_TILE && mode == SBT_DSB)
         return fail(SBT_EUNSUPPORTED, "the tiled streaming step is for bSB and aSB (dSB reads "
@@ -203,9 +202,6 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
         if (p.kernel == SBT_KERNEL_RESIDENT)
             return fail(SBT_EUNSUPPORTED, "FP8 and BF16-pair coupling storage run on the streaming "
                         "kernel only");
-        if (p.kernel == SBT_KERNEL_STREAM_TILE && p.precision != SBT_PREC_FP8)
-            return fail(SBT_EUNSUPPORTED, "the tiled streaming step holds FP32 or per-row FP8 "
-                        "couplings");
         return p.kernel == SBT_KERNEL_AUTO ? stream_kind : p.kernel;
     }
     if (p.kernel == SBT_KERNEL_STREAM || p.kernel == SBT_KERNEL_STREAM_TILE) return p.kernel;
@@ -258,7 +254,8 @@ extern "C" size_t sbt_workspace_bytes(int32_t n, int64_t nnz, sbt_mode mode,
     }
     if (check_params(*p, "sbt_workspace_bytes") != SBT_OK) return 0;
     if (check_shape(n, nnz, p->agents, "sbt_workspace_bytes") != SBT_OK) return 0;
-    return make_layout(n, nnz, p->agents, p->steps, p->energy_every, mode, p->precision).total;
+    return make_layout(n, nnz, p->agents, p->steps, p->energy_every, mode, p->precision,
+                       p->kernel == SBT_KERNEL_STREAM_TILE).total;
 }
 
 extern "C" int sbt_select_kernel(int32_t n, int64_t nnz, int32_t max_row_nnz, sbt_mode mode,
@@ -293,7 +290,8 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         return fail(SBT_EINVAL, "%s: result pointer is NULL", who);
     const int32_t n = q->n, M = p->agents, K = p->steps;
     const int nnz = static_cast<int>(q->nnz);
-    const Layout L = make_layout(n, q->nnz, M, K, p->energy_every, mode, p->precision);
+    const Layout L = make_layout(n, q->nnz, M, K, p->energy_every, mode, p->precision,
+                                 p->kernel == SBT_KERNEL_STREAM_TILE);
     if (!workspace || workspace_bytes < L.total)
         return fail(SBT_EINVAL, "%s: workspace of %zu bytes is smaller than the %zu needed", who,
                     workspace_bytes, L.total);
@@ -399,10 +397,12 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         const bool tiled = kernel == SBT_KERNEL_STREAM_TILE;
         sbt::TileArgs T{};
         if (tiled) {
+            T.ucap = sbt::kTileColsDefault;
+            T.tile_info = reinterpret_cast<int2 *>(ws + L.tile_info);
+            T.tile_n = reinterpret_cast<int *>(ws + L.tile_n);
             T.tile_cols = reinterpret_cast<int *>(ws + L.tile_cols);
-            T.tile_u = reinterpret_cast<int *>(ws + L.tile_u);
             T.ploc = reinterpret_cast<uint16_t *>(ws + L.ploc);
-            SBT_HIP(sbt::launch_tile_union(n, prow, pcol, T, st));
+            SBT_HIP(sbt::launch_tile_plan(n, prow, pcol, T, st));
         }
         // dSB: x, y in place, signs ping-pong between S0 and S1;
         // bSB: positions ping-pong between xa and xb
@@ -493,7 +493,8 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
 
     std::vector<int32_t> rp32(n + 1);
     for (int32_t i = 0; i <= n; ++i) rp32[i] = static_cast<int32_t>(q->row_ptr[i]);
-    const size_t ws_bytes = make_layout(n, nnz, M, p.steps, p.energy_every, mode, p.precision).total;
+    const size_t ws_bytes = make_layout(n, nnz, M, p.steps, p.energy_every, mode, p.precision,
+                                        p.kernel == SBT_KERNEL_STREAM_TILE).total;
     const size_t nm = static_cast<size_t>(n) * M;
 
     DevBuf da, drp, dcol, db, dws, dT, dE, dbe, dbm, dsc, dx, dy, dtr, dat;

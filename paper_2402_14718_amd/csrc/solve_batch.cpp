@@ -573,7 +573,7 @@ static int solve_batch_impl(const sbt_qubo *const *qs, int32_t E, const double *
     if (rc < 0) return rc;
     sbt_dev_batch dbch{E, n.data(), nnz.data(), static_cast<const double *>(da.p),
                        static_cast<const int32_t *>(drp.p), static_cast<const int32_t *>(dcol.p),
-                       static_cast<const double *>(db.p)};
+                       static_cast<const double *>(db.p), nullptr};  // no target: full-length solves
     sbt_dev_batch_result dr{};
     dr.best_energy = static_cast<double *>(dbe.p);
     dr.best_agent = static_cast<int32_t *>(dba.p);

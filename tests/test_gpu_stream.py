@@ -150,7 +150,8 @@ def test_asb_energies_and_every_kernel():
 
 def _dense_rows_qubo(n=1500, dense=10, deg=700, seed=3):
     """Random symmetric QUBO whose first `dense` rows couple to `deg` others:
-    their row tile holds more couplings than the tiled step sorts (4096)."""
+    rows longer than a tile's column capacity (tiles of their own, read from
+    global memory) beside short rows."""
     rng = np.random.default_rng(seed)
     rows, cols = [], []
     for i in range(dense):
@@ -171,13 +172,14 @@ def _dense_rows_qubo(n=1500, dense=10, deg=700, seed=3):
 
 
 @pytest.mark.parametrize("mode", ["bsb", "asb"])
-@pytest.mark.parametrize("prec", ["fp32", "fp8"])
+@pytest.mark.parametrize("prec", ["fp32", "fp8", "fp8_block", "bf16x2"])
 @pytest.mark.parametrize("M", [64, 96, 130, 600])
 def test_tiled_step_bit_identical_to_untiled(mode, prec, M):
-    """The tiled streaming step (row tiles, column unions in LDS) against the
-    untiled one: plain event (small unions), a QUBO with tiles past the
-    4096-coupling sort (all global) and past 256 columns (part global);
-    ragged agent counts (partial 64-agent blocks)."""
+    """The tiled streaming step (planned row tiles, column unions in LDS)
+    against the untiled one: plain event (tiles of several rows), a QUBO
+    with rows longer than a tile holds (read from global memory) between
+    short ones; ragged agent counts (partial 64-agent blocks; 130 agents
+    stage one agent per load, the others four)."""
     dt = 0.1 if mode == "asb" else 1.0
     for q in (sbt.build_qubo(tg.generate(tg.plain_spec(), 104).hits_struct()), _dense_rows_qubo()):
         kw = dict(agents=M, steps=40, seed=3, dt=dt, precision=prec, want_state=True)
@@ -228,7 +230,4 @@ def test_new_forms_refused_where_not_built():
     for prec in ("fp8_block", "bf16x2"):
         with pytest.raises(sbt.SbtError) as e:
             sbt.solve(q, "bsb", agents=8, steps=4, precision=prec, kernel="resident")
-        assert e.value.code == -4
-        with pytest.raises(sbt.SbtError) as e:
-            sbt.solve(q, "bsb", agents=64, steps=4, precision=prec, kernel="stream_tile")
         assert e.value.code == -4

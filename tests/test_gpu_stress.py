@@ -95,9 +95,9 @@ def test_full_length_energies_and_best(stress):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp8"])
 def test_tiled_step_equals_untiled_on_the_stress_event(stress, prec):
-    """Tiles of the stress event have up to ~700 distinct columns, so the
-    tiled step reads some columns from LDS and the rest from global memory;
-    both paths give the untiled step's positions bit for bit."""
+    """The stress event's tile plan: runs of up to 32 rows whose column
+    unions fit the LDS capacity, and rows longer than it read from global
+    memory; the untiled step's positions bit for bit."""
     q, _, _ = stress
     kw = dict(agents=M, steps=6, seed=SEED, precision=prec, want_state=True)
     a = sbt.solve(q, "bsb", kernel="stream", **kw)
