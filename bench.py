@@ -443,12 +443,12 @@ def stress_form(sbt, tg, torch, np, K=10000):
         wall = time.perf_counter() - t0
         s._dr.step_begin = s._dr.step_end = None
         launch_s = b.elapsed_time(e) * 1e-3 / K
+        best32, _ = sbt.top_k(s.agent_energy, 32)  # FP64 energies of the best 32 agents, on the GPU
         r = s.result()
-        E = np.sort(r["agent_energy"])
         byts = stream_bytes(q.n, q.nnz, M, 1 if prec == "fp8" else 4)
         achieved = byts / launch_s / 1e9
         out[prec] = {"seconds": wall, "spin_updates_per_s": q.n * M * K / wall,
-                     "best": r["energy"], "mean_best_32": float(E[:32].mean()),
+                     "best": r["energy"], "mean_best_32": float(best32.mean()),
                      "roofline": {"bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_GBS,
                                   "unit": "GB/s", "frac": achieved / MI355X_HBM_GBS,
                                   "traffic": measured_traffic(f"sb_stream_stress_{prec}.md"),

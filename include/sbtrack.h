@@ -346,6 +346,19 @@ int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
 int sbt_solve_dev_noalloc(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mode mode,
                           const sbt_solve_params *p, const sbt_dev_result *out, void *stream);
 
+/* The k lowest agent energies (paper section "Results": the best of the
+ * shots, here the best k of them, as the stress workload reports its best
+ * 32), on the GPU.  energy: device [agents], FP64 O(T) per agent (e.g.
+ * sbt_dev_result.agent_energy); top_energy, top_agent: device [k], written
+ * in ascending (energy, agent) order -- ties go to the lower agent, as for
+ * best_agent, and NaN energies come after every number.  One workgroup,
+ * queued on `stream` (hipStream_t or NULL); allocates nothing.
+ * Errors: SBT_EINVAL for NULL pointers, agents < 1 or k outside
+ * 1..agents (checked before any device call); SBT_EDEVICE if the launch
+ * fails. */
+int sbt_top_k_dev(const double *energy, int32_t agents, int32_t k, double *top_energy,
+                  int32_t *top_agent, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches of events (HIP)
  *

@@ -311,6 +311,21 @@ class DeviceSolver:
 
 
 
+def top_k(energy, k: int, stream=None):
+    """The k lowest energies of a CUDA float64 vector and their indices,
+    ascending, ties to the lower index (sbt_top_k_dev, on the GPU)."""
+    import torch
+    if not (energy.is_cuda and energy.dtype == torch.float64 and energy.dim() == 1):
+        raise ValueError("top_k: energy must be a 1-D float64 CUDA tensor")
+    e = energy.contiguous()
+    vals = torch.empty(k, dtype=torch.float64, device=e.device)
+    idx = torch.empty(k, dtype=torch.int32, device=e.device)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    check(load().sbt_top_k_dev(C.c_void_p(e.data_ptr()), e.numel(), k, C.c_void_p(vals.data_ptr()),
+                               C.c_void_p(idx.data_ptr()), C.c_void_p(st.cuda_stream)))
+    return vals, idx
+
+
 def _concat_batch(qubos):
     n = np.array([q.n for q in qubos], dtype=np.int32)
     nnz = np.array([q.nnz for q in qubos], dtype=np.int64)

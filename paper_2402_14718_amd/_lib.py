@@ -146,6 +146,8 @@ EXPORTS = [
     ("sbt_solve_dev_noalloc", C.c_int, [C.POINTER(SbtDevQubo), C.c_int32, C.c_int,
                                         C.POINTER(SbtSolveParams), C.POINTER(SbtDevResult),
                                         C.c_void_p]),
+    ("sbt_top_k_dev", C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                C.c_void_p]),
     ("sbt_batch_workspace_bytes", C.c_size_t, [C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                                C.c_int32, C.POINTER(SbtSolveParams)]),
     ("sbt_batch_workspace_bytes_tuned", C.c_size_t,

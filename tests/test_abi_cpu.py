@@ -247,3 +247,14 @@ def test_noalloc_entry_point_refuses_oversized_shapes_before_any_device_call():
     p = sbt.solve_params(agents=0)
     rc = lib.sbt_solve_dev_noalloc(C.byref(dq), 12, _lib.SBT_BSB, C.byref(p), C.byref(dr), None)
     assert rc == _lib.SBT_EINVAL
+
+
+def test_top_k_refuses_bad_sizes_before_any_device_call():
+    """sbt_top_k_dev checks its sizes and pointers before launching (the
+    pointers here are never read)."""
+    lib = sbt.load()
+    fake = C.c_void_p(0x1000)
+    for agents, k in ((0, 1), (10, 0), (10, 11), (-3, 1)):
+        assert lib.sbt_top_k_dev(fake, agents, k, fake, fake, None) == _lib.SBT_EINVAL
+        assert "sbt_top_k_dev" in lib.sbt_last_error().decode()
+    assert lib.sbt_top_k_dev(None, 10, 2, fake, fake, None) == _lib.SBT_EINVAL

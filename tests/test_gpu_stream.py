@@ -231,3 +231,48 @@ def test_new_forms_refused_where_not_built():
         with pytest.raises(sbt.SbtError) as e:
             sbt.solve(q, "bsb", agents=8, steps=4, precision=prec, kernel="resident")
         assert e.value.code == -4
+
+
+def _tile_edge_qubo(seed=5):
+    """A QUBO built to hit the tile plan's limits: seven rows sharing one set
+    of 90 neighbours (96 padded couplings each, so the 640-coupling bound
+    closes a tile after six of them while the union is still small), rows
+    of exactly 192 padded couplings (a tile's whole column capacity), a row
+    of 200 (past it: read from global memory), sparse rows elsewhere, and
+    n = 1013 (a partial last block of 32 rows)."""
+    rng = np.random.default_rng(seed)
+    n = 1013
+    rows, cols = [], []
+
+    def link(i, js):
+        rows.extend([i] * len(js))
+        cols.extend(js)
+
+    shared = list(range(500, 590))
+    for i in range(7):
+        link(i, shared)
+    link(100, list(range(600, 792)))
+    link(102, list(range(601, 793)))
+    link(101, list(range(600, 797)))
+    for i in range(110, n):  # never touching the rows above
+        link(i, list(110 + rng.choice(n - 110, 3, replace=False)))
+    B = sp.coo_matrix((rng.uniform(-1, 1, len(rows)), (rows, cols)), shape=(n, n)).tocsr()
+    B = sp.triu(B + B.T, k=1)
+    B = (B + B.T).tocsr()
+    B.sort_indices()
+    return sbt.Qubo(n, rng.uniform(0, 0.7, n), B.indptr.astype(np.int64), B.indices.astype(np.int32),
+                    B.data.astype(np.float64), np.zeros((n, 3), np.int64))
+
+
+@pytest.mark.parametrize("M", [64, 130])
+@pytest.mark.parametrize("prec", ["fp32", "fp8_block"])
+def test_tiled_step_at_the_tile_limits(M, prec):
+    q = _tile_edge_qubo()
+    lens = np.diff(q.row_ptr)
+    plen = (lens + 7) // 8 * 8
+    assert np.all(plen[:7] == 96) and plen[100] == 192 and plen[102] == 192 and plen[101] == 200
+    kw = dict(agents=M, steps=30, seed=4, precision=prec, want_state=True)
+    a = sbt.solve(q, "bsb", kernel="stream", **kw)
+    t = sbt.solve(q, "bsb", kernel="stream_tile", **kw)
+    assert np.array_equal(a["x"], t["x"]) and np.array_equal(a["y"], t["y"])
+    assert np.array_equal(a["agent_energy"], t["agent_energy"])
