@@ -400,7 +400,7 @@ def stream_bytes_dsb(n, nnz, agents):
     return 16.0 * n * agents + 16.0 * n * words + 8.0 * nnz + 12.0 * n
 
 
-def stress_form(sbt, tg, torch, np, K=10000):
+def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=True):
     """5000 particles (N ~ 2.1e5), bSB, 512 agents x 10000 steps on the
     streaming kernel: FP8 couplings (the workload's storage) and FP32, spins
     in azimuth order, FP64 energies of every agent on the GPU; the tiled
@@ -429,7 +429,7 @@ def stress_form(sbt, tg, torch, np, K=10000):
            "n": q.n, "nnz": q.nnz, "host_build_s": t_build, "host_order_s": t_order,
            "gpu_build_s": t_gpu, "gpu_build_device_s": t_gpu_dev,
            "gpu_build_same_structure": same}
-    for prec in ("fp8", "fp32"):
+    for prec in precisions:
         s = sbt.DeviceSolver(q, "bsb", sbt.solve_params(agents=M, steps=K, seed=0,
                                                          kernel="stream", precision=prec))
         b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -452,30 +452,34 @@ def stress_form(sbt, tg, torch, np, K=10000):
                      "roofline": {"bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_GBS,
                                   "unit": "GB/s", "frac": achieved / MI355X_HBM_GBS,
                                   "traffic": measured_traffic(f"sb_stream_stress_{prec}.md"),
-                                  "kernel": "sb_stream_v4", "launch_ms": launch_s * 1e3,
+                                  "kernel": "sb_stream_quad", "launch_ms": launch_s * 1e3,
                                   "bytes_per_launch": byts}}
         del s
         torch.cuda.empty_cache()
-    # the tiled streaming step (row tiles, column unions staged in LDS) on
-    # the same event, for comparison (FP32, a shorter run: per-launch cost is
-    # constant)
-    k_cmp = min(K, 200)
-    s = sbt.DeviceSolver(q, "bsb", sbt.solve_params(agents=M, steps=k_cmp, seed=0,
-                                                     kernel="stream_tile"))
-    b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    b.record()
-    e.record()
-    torch.cuda.synchronize()
-    s._dr.step_begin, s._dr.step_end = b.cuda_event, e.cuda_event
-    s.run()
-    torch.cuda.synchronize()
-    launch_s = b.elapsed_time(e) * 1e-3 / k_cmp
-    byts = stream_bytes(q.n, q.nnz, M, 4)
-    out["fp32_tiled"] = {"kernel": "sb_stream_tile", "steps": k_cmp, "launch_ms": launch_s * 1e3,
-                         "hbm_frac": byts / launch_s / 1e9 / MI355X_HBM_GBS}
-    del s
-    torch.cuda.empty_cache()
-    out["fp8_rel_gap_vs_fp32"] = (out["fp8"]["best"] - out["fp32"]["best"]) / abs(out["fp32"]["best"])
+    # the tiled streaming step (planned row tiles, column unions staged in
+    # LDS) on the same event, and the one-row-per-wave step, for comparison
+    # (FP32, shorter runs: per-launch cost is constant)
+    if tiled:
+        k_cmp = min(K, 200)
+        for key, kern, name in (("fp32_tiled", "stream_tile", "sb_stream_tile"),
+                                ("fp32_rows", "stream_rows", "sb_stream_v4")):
+            s = sbt.DeviceSolver(q, "bsb", sbt.solve_params(agents=M, steps=k_cmp, seed=0,
+                                                             kernel=kern))
+            b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            b.record()
+            e.record()
+            torch.cuda.synchronize()
+            s._dr.step_begin, s._dr.step_end = b.cuda_event, e.cuda_event
+            s.run()
+            torch.cuda.synchronize()
+            launch_s = b.elapsed_time(e) * 1e-3 / k_cmp
+            byts = stream_bytes(q.n, q.nnz, M, 4)
+            out[key] = {"kernel": name, "steps": k_cmp, "launch_ms": launch_s * 1e3,
+                        "hbm_frac": byts / launch_s / 1e9 / MI355X_HBM_GBS}
+            del s
+            torch.cuda.empty_cache()
+    if "fp8" in out and "fp32" in out:
+        out["fp8_rel_gap_vs_fp32"] = (out["fp8"]["best"] - out["fp32"]["best"]) / abs(out["fp32"]["best"])
     return out
 
 
@@ -754,6 +758,9 @@ def main():
                          "launches (for counter collection)")
     ap.add_argument("--stress-steps", type=int, default=10000,
                     help="SB steps of the stress form (10000 is the workload's)")
+    ap.add_argument("--stress-prec", choices=["fp8", "fp32"], default=None,
+                    help="stress form: only this coupling form, without the tiled comparison "
+                         "(profiling one precision's launches)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
@@ -795,7 +802,10 @@ def main():
             form = {"plain": lambda: plain_form(sbt, tg, torch, plain_q(), args.kernel,
                                                 args.warmup, args.steps, with_ttt=False),
                     "precision": lambda: precision_form(sbt, tg, torch, np),
-                    "stress": lambda: stress_form(sbt, tg, torch, np, args.stress_steps)}[args.only]
+                    "stress": lambda: stress_form(
+                        sbt, tg, torch, np, args.stress_steps,
+                        (args.stress_prec,) if args.stress_prec else ("fp8", "fp32"),
+                        tiled=args.stress_prec is None)}[args.only]
         print(json.dumps({f"{args.only}_form": form()}), flush=True)
         return
 

@@ -184,8 +184,14 @@ typedef enum {
     SBT_KERNEL_RESIDENT = 1, /* one launch for all steps; a workgroup owns
                                 whole agents, positions live in LDS        */
     SBT_KERNEL_STREAM = 2,   /* one launch per step; state streams through
-                                HBM, lanes are agents                       */
-    SBT_KERNEL_STREAM_TILE = 3 /* bSB / aSB: the streaming step with rows in
+                                HBM, lanes are agents.  bSB / aSB with
+                                agents a multiple of 4 above 64: a wave
+                                takes four consecutive rows and gathers each
+                                distinct neighbour of the four once (lists
+                                built on the GPU once per solve; the
+                                workspace grows by about 20 bytes per
+                                coupling); otherwise one row per wave      */
+    SBT_KERNEL_STREAM_TILE = 3, /* bSB / aSB: the streaming step with rows in
                                 planned tiles -- runs of consecutive rows
                                 (within blocks of 32) whose column union
                                 fits 192 columns -- whose neighbours'
@@ -197,6 +203,11 @@ typedef enum {
                                 solve on the GPU; the workspace grows by
                                 6 bytes per padded coupling.  Only on
                                 request (AUTO never picks it)            */
+    SBT_KERNEL_STREAM_ROWS = 4 /* the streaming step one row per wave for
+                                every mode and agent count (what
+                                SBT_KERNEL_STREAM runs where it takes no
+                                quads); the same arithmetic as the quad
+                                step, bit-identical results             */
 } sbt_kernel;
 
 /* Storage precision of the couplings J.  The paper fixes no number format

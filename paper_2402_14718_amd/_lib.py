@@ -25,6 +25,7 @@ SBT_KERNEL_AUTO = 0
 SBT_KERNEL_RESIDENT = 1
 SBT_KERNEL_STREAM = 2
 SBT_KERNEL_STREAM_TILE = 3
+SBT_KERNEL_STREAM_ROWS = 4
 
 
 class SbtHit(C.Structure):

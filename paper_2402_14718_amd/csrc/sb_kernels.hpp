@@ -112,6 +112,24 @@ struct StreamArgs {
     int sign_stride;             // stream_sign_stride(M)
 };
 
+// Row quads of the streaming bSB / aSB step (sb_stream_quad.hip): each
+// quad of kQuadRows consecutive rows lists its distinct columns ascending
+// (padded to whole chunks of kStreamChunk) with one FP32 coupling per row
+// and column (0 where the row has none).
+constexpr int kQuadRows = 4;
+
+struct QuadArgs {
+    int *qcnt;                   // [nq] listed columns per quad (work array of the plan)
+    int *qoff;                   // [nq+1] first listed column of each quad
+    int *qcol;                   // [quad_cols_bound] listed columns
+    float *qJ;                   // [quad_cols_bound * kQuadRows] couplings, column-major
+};
+
+size_t quad_cols_bound(int n, int64_t nnz);
+hipError_t launch_quad_plan(int jprec, const StreamArgs &A, const QuadArgs &Q, hipStream_t st);
+hipError_t launch_stream_quad(int mode, const StreamArgs &A, const QuadArgs &Q, int k, const float *xin,
+                              float *xout, hipStream_t st);
+
 // Row tiles of the streaming bSB / aSB step (sb_stream_tile.hip): super
 // tiles of kTileSuper consecutive rows, each cut into tiles of consecutive
 // rows whose column union has at most `ucap` (<= kTileColsMax) entries and

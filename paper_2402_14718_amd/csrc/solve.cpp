@@ -24,7 +24,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t J = 0, h = 0, scal = 0, prep = 0, perm = 0, sched = 0, xa = 0, xb = 0, y = 0, epart = 0,
            etrace = 0, S0 = 0, S1 = 0, J8 = 0, rowscale = 0, prow = 0, pcol = 0, pJ = 0,
-           tile_info = 0, tile_n = 0, tile_cols = 0, ploc = 0, blkscale = 0, J2 = 0;
+           tile_info = 0, tile_n = 0, tile_cols = 0, ploc = 0, blkscale = 0, J2 = 0, qcnt = 0,
+           qoff = 0, qcol = 0, qJ = 0;
     size_t total = 0;
     int n_ckpt = 0;
 };
@@ -33,9 +34,17 @@ struct Layout {
 // the sign planes S0/S1), so the second position buffer exists for bSB
 // only; FP8 couplings add one byte per padded nonzero and a scale per row.
 // prow/pcol/pJ: the streaming kernel's row-padded copy of the couplings;
-// the tiled step (requested explicitly) adds its tile plan.
+// the tiled step (requested explicitly) adds its tile plan, the bSB / aSB
+// streaming step over row quads (four agents per lane) its quad lists.
+// bSB / aSB streaming (SBT_KERNEL_STREAM) runs over row quads when whole
+// lanes of four agents fill more than one wave; otherwise, and on request
+// (SBT_KERNEL_STREAM_ROWS), over single rows (sb_stream.hip).
+bool quad_step(sbt_mode mode, int32_t M) { return mode != SBT_DSB && M % 4 == 0 && M > 64; }
+
 Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, sbt_mode mode,
-                   int32_t prec, bool tiled) {
+                   int32_t prec, int32_t kernel_req) {
+    const bool tiled = kernel_req == SBT_KERNEL_STREAM_TILE;
+    const bool quads = quad_step(mode, M) && !tiled && kernel_req != SBT_KERNEL_STREAM_ROWS;
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -76,6 +85,14 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
         L.blkscale = take(sizeof(float) * (pnnz / sbt::kStreamChunk));
     }
     if (prec == SBT_PREC_BF16X2) L.J2 = take(sizeof(uint32_t) * pnnz);
+    if (quads) {  // the row-quad streaming step's lists
+        const size_t nq = (static_cast<size_t>(n) + sbt::kQuadRows - 1) / sbt::kQuadRows;
+        const size_t cols = sbt::quad_cols_bound(n, nnz);
+        L.qcnt = take(sizeof(int32_t) * nq);
+        L.qoff = take(sizeof(int32_t) * (nq + 1));
+        L.qcol = take(sizeof(int32_t) * cols);
+        L.qJ = take(sizeof(float) * cols * sbt::kQuadRows);
+    }
     if (tiled && mode != SBT_DSB) {  // the tiled streaming step's plan
         const size_t nsuper = (static_cast<size_t>(n) + sbt::kTileSuper - 1) / sbt::kTileSuper;
         L.tile_info = take(2 * sizeof(int32_t) * nsuper * sbt::kTileSuper);
@@ -97,7 +114,7 @@ int check_params(const sbt_solve_params &p, const char *who) {
     if (p.steps < 1) return fail(SBT_EINVAL, "%s: steps must be >= 1", who);
     if (p.energy_every < 0) return fail(SBT_EINVAL, "%s: energy_every must be >= 0", who);
     if (p.event < 0) return fail(SBT_EINVAL, "%s: event must be >= 0", who);
-    if (p.kernel < SBT_KERNEL_AUTO || p.kernel > SBT_KERNEL_STREAM_TILE)
+    if (p.kernel < SBT_KERNEL_AUTO || p.kernel > SBT_KERNEL_STREAM_ROWS)
         return fail(SBT_EINVAL, "%s: unknown kernel %d", who, p.kernel);
     if (p.tpb != 0 && p.tpb != 64 && p.tpb != 256 && p.tpb != 512 && p.tpb != 1024)
         return fail(SBT_EINVAL, "%s: tpb must be 0, 64, 256, 512 or 1024", who);
@@ -204,7 +221,9 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
                         "kernel only");
         return p.kernel == SBT_KERNEL_AUTO ? stream_kind : p.kernel;
     }
-    if (p.kernel == SBT_KERNEL_STREAM || p.kernel == SBT_KERNEL_STREAM_TILE) return p.kernel;
+    if (p.kernel == SBT_KERNEL_STREAM || p.kernel == SBT_KERNEL_STREAM_TILE ||
+        p.kernel == SBT_KERNEL_STREAM_ROWS)
+        return p.kernel;
     if (p.kernel == SBT_KERNEL_RESIDENT) {
         if (S.tpb == 0)
             return fail(SBT_EUNSUPPORTED, "resident kernel: n = %d does not fit in LDS", n);
@@ -255,7 +274,7 @@ extern "C" size_t sbt_workspace_bytes(int32_t n, int64_t nnz, sbt_mode mode,
     if (check_params(*p, "sbt_workspace_bytes") != SBT_OK) return 0;
     if (check_shape(n, nnz, p->agents, "sbt_workspace_bytes") != SBT_OK) return 0;
     return make_layout(n, nnz, p->agents, p->steps, p->energy_every, mode, p->precision,
-                       p->kernel == SBT_KERNEL_STREAM_TILE).total;
+                       p->kernel).total;
 }
 
 extern "C" int sbt_select_kernel(int32_t n, int64_t nnz, int32_t max_row_nnz, sbt_mode mode,
@@ -290,8 +309,7 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         return fail(SBT_EINVAL, "%s: result pointer is NULL", who);
     const int32_t n = q->n, M = p->agents, K = p->steps;
     const int nnz = static_cast<int>(q->nnz);
-    const Layout L = make_layout(n, q->nnz, M, K, p->energy_every, mode, p->precision,
-                                 p->kernel == SBT_KERNEL_STREAM_TILE);
+    const Layout L = make_layout(n, q->nnz, M, K, p->energy_every, mode, p->precision, p->kernel);
     if (!workspace || workspace_bytes < L.total)
         return fail(SBT_EINVAL, "%s: workspace of %zu bytes is smaller than the %zu needed", who,
                     workspace_bytes, L.total);
@@ -404,6 +422,15 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
             T.ploc = reinterpret_cast<uint16_t *>(ws + L.ploc);
             SBT_HIP(sbt::launch_tile_plan(n, prow, pcol, T, st));
         }
+        const bool quads = kernel == SBT_KERNEL_STREAM && quad_step(mode, M);
+        sbt::QuadArgs Q{};
+        if (quads) {
+            Q.qcnt = reinterpret_cast<int *>(ws + L.qcnt);
+            Q.qoff = reinterpret_cast<int *>(ws + L.qoff);
+            Q.qcol = reinterpret_cast<int *>(ws + L.qcol);
+            Q.qJ = reinterpret_cast<float *>(ws + L.qJ);
+            SBT_HIP(sbt::launch_quad_plan(jprec, A, Q, st));
+        }
         // dSB: x, y in place, signs ping-pong between S0 and S1;
         // bSB: positions ping-pong between xa and xb
         float *xin = xa, *xout = xb;
@@ -413,6 +440,8 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         for (int k = 0; k < K; ++k) {
             if (tiled)
                 SBT_HIP(sbt::launch_stream_tile(static_cast<int>(mode), jprec, A, T, k, xin, xout, st));
+            else if (quads)
+                SBT_HIP(sbt::launch_stream_quad(static_cast<int>(mode), A, Q, k, xin, xout, st));
             else
                 SBT_HIP(sbt::launch_stream2(static_cast<int>(mode), jprec, A, k, xin, xout, Sin, Sout, st));
             std::swap(xin, xout);
@@ -493,8 +522,8 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
 
     std::vector<int32_t> rp32(n + 1);
     for (int32_t i = 0; i <= n; ++i) rp32[i] = static_cast<int32_t>(q->row_ptr[i]);
-    const size_t ws_bytes = make_layout(n, nnz, M, p.steps, p.energy_every, mode, p.precision,
-                                        p.kernel == SBT_KERNEL_STREAM_TILE).total;
+    const size_t ws_bytes =
+        make_layout(n, nnz, M, p.steps, p.energy_every, mode, p.precision, p.kernel).total;
     const size_t nm = static_cast<size_t>(n) * M;
 
     DevBuf da, drp, dcol, db, dws, dT, dE, dbe, dbm, dsc, dx, dy, dtr, dat;

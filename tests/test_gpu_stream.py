@@ -276,3 +276,22 @@ def test_tiled_step_at_the_tile_limits(M, prec):
     t = sbt.solve(q, "bsb", kernel="stream_tile", **kw)
     assert np.array_equal(a["x"], t["x"]) and np.array_equal(a["y"], t["y"])
     assert np.array_equal(a["agent_energy"], t["agent_energy"])
+
+
+@pytest.mark.parametrize("mode", ["bsb", "asb"])
+@pytest.mark.parametrize("prec", ["fp32", "fp8", "fp8_block", "bf16x2"])
+@pytest.mark.parametrize("M", [68, 260, 600])
+def test_row_quad_step_bit_identical_to_row_step(mode, prec, M):
+    """The streaming step over row quads (each distinct neighbour of four
+    rows gathered once) against the one-row-per-wave step: plain event, a
+    QUBO with dense rows and empty rows, the tile-limit QUBO (n = 1013, a
+    partial last quad); agent counts with a partial 256-agent block."""
+    dt = 0.1 if mode == "asb" else 1.0
+    for q in (sbt.build_qubo(tg.generate(tg.plain_spec(), 104).hits_struct()), _dense_rows_qubo(),
+              _tile_edge_qubo()):
+        kw = dict(agents=M, steps=40, seed=3, dt=dt, precision=prec, want_state=True)
+        a = sbt.solve(q, mode, kernel="stream_rows", **kw)
+        t = sbt.solve(q, mode, kernel="stream", **kw)
+        assert a["kernel"] == "stream_rows" and t["kernel"] == "stream"
+        assert np.array_equal(a["x"], t["x"]) and np.array_equal(a["y"], t["y"])
+        assert np.array_equal(a["agent_energy"], t["agent_energy"])

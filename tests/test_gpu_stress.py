@@ -48,8 +48,8 @@ def _two_hop(b, rows):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp8"])
-@pytest.mark.parametrize("mode,kernel", [("bsb", "stream"), ("bsb", "stream_tile"),
-                                         ("dsb", "stream")])
+@pytest.mark.parametrize("mode,kernel", [("bsb", "stream"), ("bsb", "stream_rows"),
+                                         ("bsb", "stream_tile"), ("dsb", "stream")])
 def test_two_steps_on_sampled_rows(stress, mode, kernel, prec):
     q, b, isg = stress
     K = 2
@@ -102,5 +102,17 @@ def test_tiled_step_equals_untiled_on_the_stress_event(stress, prec):
     kw = dict(agents=M, steps=6, seed=SEED, precision=prec, want_state=True)
     a = sbt.solve(q, "bsb", kernel="stream", **kw)
     t = sbt.solve(q, "bsb", kernel="stream_tile", **kw)
+    assert np.array_equal(a["x"], t["x"]) and np.array_equal(a["y"], t["y"])
+    assert np.array_equal(a["agent_energy"], t["agent_energy"])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp8"])
+def test_row_quad_step_equals_row_step_on_the_stress_event(stress, prec):
+    """The bench configuration's streaming step (row quads, 512 agents)
+    against the one-row-per-wave step on the stress event, bit for bit."""
+    q, _, _ = stress
+    kw = dict(agents=M, steps=6, seed=SEED, precision=prec, want_state=True)
+    a = sbt.solve(q, "bsb", kernel="stream_rows", **kw)
+    t = sbt.solve(q, "bsb", kernel="stream", **kw)
     assert np.array_equal(a["x"], t["x"]) and np.array_equal(a["y"], t["y"])
     assert np.array_equal(a["agent_energy"], t["agent_energy"])
