@@ -8,6 +8,7 @@
 #include <cstdint>
 
 #include "sb_kernels.hpp"
+#include "sb_stream_kernels.hpp"
 
 namespace sbt {
 

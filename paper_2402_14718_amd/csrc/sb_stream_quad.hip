@@ -18,6 +18,7 @@
 
 #include "sb_device.hpp"
 #include "sb_kernels.hpp"
+#include "sb_stream_kernels.hpp"
 #include "sb_stream_chunk.hpp"
 
 namespace sbt {

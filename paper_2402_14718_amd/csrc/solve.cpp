@@ -11,6 +11,7 @@
 
 #include "common.hpp"
 #include "sb_kernels.hpp"
+#include "sb_stream_kernels.hpp"
 #include "sbtrack.h"
 
 namespace {

@@ -30,7 +30,7 @@ KERNEL_SOURCES = {
                         "csrc/sb_resident_reg_bsb.hip", "csrc/sb_resident_reg_dsb.hip",
                         "csrc/sb_resident_reg_asb.hip", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
     "sb_stream": ["csrc/sb_stream.hip", "csrc/sb_stream_quad.hip", "csrc/sb_stream_chunk.hpp",
-                  "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
+                  "csrc/sb_stream_kernels.hpp", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
     "sb_batch": ["csrc/sb_batch.hip", "csrc/sb_batch_step.hpp", "csrc/sb_batch_mode.hip",
                  "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
     "sb_batch_gang": ["csrc/sb_batch_gang.hip", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
