@@ -166,10 +166,14 @@ def test_energy_trace_is_best_so_far(kernel):
 
 @pytest.mark.parametrize("n,M,K,kernel", [
     (1, 1, 1, "resident"), (1, 3, 2, "stream"), (65, 1, 7, "resident"), (1025, 5, 3, "resident"),
-    (1025, 65, 3, "stream"), (4100, 2, 2, "resident")])
+    (1025, 65, 3, "stream"), (4100, 2, 2, "resident"),
+    (1, 68, 3, "stream"), (2, 68, 3, "stream"), (3, 260, 2, "stream"), (5, 68, 4, "stream"),
+    (1025, 68, 3, "stream"), (7, 68, 3, "stream_rows")])
 def test_edge_shapes_random_qubo(n, M, K, kernel):
     """Ragged spin and agent counts against the oracle, a chain QUBO with
-    random values (several tiles of every kernel plus a ragged tail)."""
+    random values (several tiles of every kernel plus a ragged tail); with
+    68 or 260 agents the bSB / aSB streaming step runs over row quads,
+    down to one spin (a quad of one row) and partial last quads."""
     rng = np.random.default_rng(n + M)
     rows, cols, vals = [], [], []
     for i in range(n - 1):
