@@ -45,7 +45,9 @@ bool quad_step(sbt_mode mode, int32_t M) { return mode != SBT_DSB && M % 4 == 0 
 Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, sbt_mode mode,
                    int32_t prec, int32_t kernel_req) {
     const bool tiled = kernel_req == SBT_KERNEL_STREAM_TILE;
-    const bool quads = quad_step(mode, M) && !tiled && kernel_req != SBT_KERNEL_STREAM_ROWS;
+    // (AUTO may resolve to the streaming step, so it reserves the lists too)
+    const bool quads = quad_step(mode, M) &&
+                       (kernel_req == SBT_KERNEL_STREAM || kernel_req == SBT_KERNEL_AUTO);
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
