@@ -72,7 +72,7 @@ TTT_DEFINITIONS = {
              "fraction of agents at the target, TTT = t_solve ln(0.01) / ln(1 - P) (t_solve when "
              "P >= 0.99), minimised over K in a ladder of step counts",
 }
-TTT_LADDER = (25, 50, 100, 200, 500, 1000, 2000, 5000)
+TTT_LADDER = (5, 10, 15, 25, 50, 100, 200, 500, 1000, 2000, 5000)
 
 
 def load_golden(name):
