@@ -28,13 +28,16 @@ def _capture(run):
     return g
 
 
-@pytest.mark.parametrize("kernel", ["resident", "stream"])
-def test_single_event_solve_replays_bit_identically(kernel):
+@pytest.mark.parametrize("mode,kernel", [("dsb", "resident"), ("dsb", "stream"), ("bsb", "stream"),
+                                         ("bsb", "stream_tile")])
+def test_single_event_solve_replays_bit_identically(mode, kernel):
+    """A whole solve captured in a HIP graph, its one-off preparation
+    included (bSB streaming: the row-quad lists; tiled: the tile plan)."""
     ev = tg.generate(tg.plain_spec(), 100)
     q = sbt.build_qubo(ev.hits_struct())
-    p = sbt.solve_params(agents=128, steps=400 if kernel == "stream" else 2000, seed=3,
+    p = sbt.solve_params(agents=128, steps=2000 if kernel == "resident" else 400, seed=3,
                          kernel=kernel, energy_every=100)
-    ds = sbt.DeviceSolver(q, "dsb", p, want_state=True, want_trace=True)
+    ds = sbt.DeviceSolver(q, mode, p, want_state=True, want_trace=True)
     ds.run()
     ref = ds.result()
     g = _capture(ds.run)
