@@ -203,11 +203,28 @@ typedef enum {
                                 solve on the GPU; the workspace grows by
                                 6 bytes per padded coupling.  Only on
                                 request (AUTO never picks it)            */
-    SBT_KERNEL_STREAM_ROWS = 4 /* the streaming step one row per wave for
+    SBT_KERNEL_STREAM_ROWS = 4, /* the streaming step one row per wave for
                                 every mode and agent count (what
                                 SBT_KERNEL_STREAM runs where it takes no
                                 quads); the same arithmetic as the quad
                                 step, bit-identical results             */
+    SBT_KERNEL_STREAM_MFMA = 5 /* dSB on the matrix cores (Eq. 10 as a
+                                product of a dense coupling block and
+                                +-1 signs): blocks of 16 consecutive rows
+                                list their distinct columns, padded to
+                                steps of 32, with the couplings as dense
+                                operand tiles; FP8 (per-row scale: the
+                                codes are the operand, the scale applies
+                                to the row's sum) or BF16X2 (hi and lo
+                                operands) only, other forms and modes
+                                give SBT_EUNSUPPORTED.  The products are
+                                exact; the FP32 sums are added in the
+                                instruction's order, so results differ
+                                from the CSR step by rounding.  Planned
+                                once per solve on the GPU; the workspace
+                                grows by about (nnz / 32 + n / 16) x 640
+                                bytes (FP8) or x 2176 (BF16X2).
+                                Only on request (AUTO never picks it)    */
 } sbt_kernel;
 
 /* Storage precision of the couplings J.  The paper fixes no number format

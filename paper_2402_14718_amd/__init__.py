@@ -23,7 +23,8 @@ from ._lib import (SBT_BSB, SBT_DSB, SBT_KERNEL_AUTO, SBT_KERNEL_RESIDENT, SBT_K
 
 MODES = {"bsb": SBT_BSB, "dsb": SBT_DSB, "asb": _lib.SBT_ASB}
 KERNELS = {"auto": SBT_KERNEL_AUTO, "resident": SBT_KERNEL_RESIDENT, "stream": SBT_KERNEL_STREAM,
-           "stream_tile": _lib.SBT_KERNEL_STREAM_TILE, "stream_rows": _lib.SBT_KERNEL_STREAM_ROWS}
+           "stream_tile": _lib.SBT_KERNEL_STREAM_TILE, "stream_rows": _lib.SBT_KERNEL_STREAM_ROWS,
+           "stream_mfma": _lib.SBT_KERNEL_STREAM_MFMA}
 PRECISIONS = {"fp32": _lib.SBT_PREC_FP32, "fp16": _lib.SBT_PREC_FP16, "bf16": _lib.SBT_PREC_BF16,
               "fp8": _lib.SBT_PREC_FP8, "fp8_block": _lib.SBT_PREC_FP8_BLOCK,
               "bf16x2": _lib.SBT_PREC_BF16X2}

@@ -26,6 +26,7 @@ SBT_KERNEL_RESIDENT = 1
 SBT_KERNEL_STREAM = 2
 SBT_KERNEL_STREAM_TILE = 3
 SBT_KERNEL_STREAM_ROWS = 4
+SBT_KERNEL_STREAM_MFMA = 5
 
 
 class SbtHit(C.Structure):

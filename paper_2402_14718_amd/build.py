@@ -30,7 +30,7 @@ RUNTIME_SOURCES = ["solve.cpp", "solve_batch.cpp"]
 HIP_SOURCES = ["sb_kernels.hip", "sb_resident_reg.hip", "sb_resident_reg_bsb.hip",
                "sb_resident_reg_dsb.hip", "sb_resident_reg_asb.hip", "sb_batch.hip",
                "sb_stream.hip", "build_qubo_gpu.hip", "solve_noalloc.hip", "sb_batch_gang.hip",
-               "sb_stream_tile.hip", "topk.hip", "sb_stream_quad.hip"]
+               "sb_stream_tile.hip", "topk.hip", "sb_stream_quad.hip", "sb_stream_mfma.hip"]
 # one source built several times: (source, object tag, extra flags) -- the
 # batched step kernel once per (mode, coupling format, workgroup shape), in
 # parallel

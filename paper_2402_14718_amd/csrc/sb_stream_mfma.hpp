@@ -1,0 +1,63 @@
+// Matrix-core dSB streaming step (sb_stream_mfma.hip): argument block,
+// plan and step launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sb_kernels.hpp"
+#include "sb_stream_kernels.hpp"
+
+namespace sbt {
+
+// A block is kMfmaRows consecutive rows: the M side of one 16 x 16 output
+// tile of the matrix instruction.  Its distinct columns are listed in
+// ascending order and padded to whole K-steps of kMfmaK columns (the
+// instruction's contraction length); each K-step holds the block's
+// couplings on those columns as one dense operand tile, already in the
+// instruction's register layout (lane 16 g + r holds row r's couplings on
+// listed columns 8 g .. 8 g + 7 of the step; 0 where the row has none).
+constexpr int kMfmaRows = 16;
+constexpr int kMfmaK = 32;
+
+// 64-bit words of one lane's operand per K-step: eight FP8 codes (one
+// word), or eight BF16 hi followed by eight BF16 lo (four words).
+__host__ __device__ constexpr int mfma_words(int jprec) { return jprec == kJBf16x2 ? 4 : 1; }
+
+// Coupling forms the matrix-core step takes: FP8 with one scale per row
+// (the codes are the operand, the scale applies to the row's sum) and the
+// BF16 hi + lo pair (two operands on the same signs).
+__host__ __device__ constexpr bool mfma_form(int jprec) { return jprec == kJFp8 || jprec == kJBf16x2; }
+
+struct MfmaArgs {
+    int *kcnt;       // [nb] K-steps of each block (work array of the plan)
+    int *koff;       // [nb + 1] first K-step of each block; koff[nb] = total
+    int *kcol;       // [ksteps * kMfmaK] listed columns
+    uint64_t *kA;    // [ksteps * 64 * mfma_words] operand tiles
+};
+
+// Sign records of the matrix-core step (its own layout, not the CSR step's
+// sign words): per row and group of kMfmaGroup agents 16 bytes, bit t of
+// byte c = (x of agent kMfmaGroup g + 16 t + c >= 0), 0 past the last agent.
+// A lane of the step handles agent c of each of the group's 8 tiles of 16,
+// so one byte holds all its signs of one column, and the new signs of its
+// row are one byte it writes itself.
+constexpr int kMfmaGroup = 128;
+__host__ __device__ constexpr int mfma_groups(int M) { return (M + kMfmaGroup - 1) / kMfmaGroup; }
+__host__ __device__ constexpr size_t mfma_sign_bytes(int n, int M) {
+    return static_cast<size_t>(n) * mfma_groups(M) * 16;
+}
+hipError_t launch_mfma_signs(int n, int M, const float *x, uint8_t *S, hipStream_t st);
+
+// Upper bound on the K-steps of all blocks: a block lists at most its own
+// couplings, padded by fewer than kMfmaK.
+size_t mfma_ksteps_bound(int n, int64_t nnz);
+hipError_t launch_mfma_plan(int jprec, const StreamArgs &A, const MfmaArgs &P, hipStream_t st);
+// One dSB step, x and y in place; the neighbours' signs are read from the
+// records Sin and the new signs written to Sout (mfma_sign_bytes each).
+hipError_t launch_stream_mfma(int jprec, const StreamArgs &A, const MfmaArgs &P, int k, float *x,
+                              const uint8_t *Sin, uint8_t *Sout, hipStream_t st);
+
+}  // namespace sbt

@@ -12,6 +12,7 @@
 #include "common.hpp"
 #include "sb_kernels.hpp"
 #include "sb_stream_kernels.hpp"
+#include "sb_stream_mfma.hpp"
 #include "sbtrack.h"
 
 namespace {
@@ -26,7 +27,7 @@ struct Layout {
     size_t J = 0, h = 0, scal = 0, prep = 0, perm = 0, sched = 0, xa = 0, xb = 0, y = 0, epart = 0,
            etrace = 0, S0 = 0, S1 = 0, J8 = 0, rowscale = 0, prow = 0, pcol = 0, pJ = 0,
            tile_info = 0, tile_n = 0, tile_cols = 0, ploc = 0, blkscale = 0, J2 = 0, qcnt = 0,
-           qoff = 0, qcol = 0, qJ = 0;
+           qoff = 0, qcol = 0, qJ = 0, kcnt = 0, koff = 0, kcol = 0, kA = 0;
     size_t total = 0;
     int n_ckpt = 0;
 };
@@ -39,7 +40,9 @@ struct Layout {
 // streaming step over row quads (four agents per lane) its quad lists.
 // bSB / aSB streaming (SBT_KERNEL_STREAM) runs over row quads when whole
 // lanes of four agents fill more than one wave; otherwise, and on request
-// (SBT_KERNEL_STREAM_ROWS), over single rows (sb_stream.hip).
+// (SBT_KERNEL_STREAM_ROWS), over single rows (sb_stream.hip).  The
+// matrix-core dSB step (requested explicitly) adds its block lists and
+// operand tiles.
 bool quad_step(sbt_mode mode, int32_t M) { return mode != SBT_DSB && M % 4 == 0 && M > 64; }
 
 Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, sbt_mode mode,
@@ -48,6 +51,8 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
     // (AUTO may resolve to the streaming step, so it reserves the lists too)
     const bool quads = quad_step(mode, M) &&
                        (kernel_req == SBT_KERNEL_STREAM || kernel_req == SBT_KERNEL_AUTO);
+    const bool mfma = kernel_req == SBT_KERNEL_STREAM_MFMA && mode == SBT_DSB &&
+                      (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2);
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -71,9 +76,11 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
     L.epart = take(sizeof(double) * nblk_e * M);
     L.etrace = take(sizeof(double) * static_cast<size_t>(L.n_ckpt) * M);
     if (mode == SBT_DSB) {
-        const size_t words = static_cast<size_t>(n) * sbt::stream_sign_stride(M);
-        L.S0 = take(sizeof(uint64_t) * words);
-        L.S1 = take(sizeof(uint64_t) * words);
+        // the CSR step's sign words, or the matrix-core step's sign records
+        const size_t bytes = mfma ? sbt::mfma_sign_bytes(n, M)
+                                  : sizeof(uint64_t) * static_cast<size_t>(n) * sbt::stream_sign_stride(M);
+        L.S0 = take(bytes);
+        L.S1 = take(bytes);
     }
     const size_t pnnz = static_cast<size_t>(nnz) + (sbt::kStreamChunk - 1) * static_cast<size_t>(n);
     L.prow = take(sizeof(int32_t) * (static_cast<size_t>(n) + 1));
@@ -96,6 +103,15 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
         L.qcol = take(sizeof(int32_t) * cols);
         L.qJ = take(sizeof(float) * cols * sbt::kQuadRows);
     }
+    if (mfma) {  // the matrix-core step's blocks and operand tiles
+        const size_t nb = (static_cast<size_t>(n) + sbt::kMfmaRows - 1) / sbt::kMfmaRows;
+        const size_t ks = sbt::mfma_ksteps_bound(n, nnz);
+        const int jp = prec == SBT_PREC_FP8 ? sbt::kJFp8 : sbt::kJBf16x2;
+        L.kcnt = take(sizeof(int32_t) * nb);
+        L.koff = take(sizeof(int32_t) * (nb + 1));
+        L.kcol = take(sizeof(int32_t) * ks * sbt::kMfmaK);
+        L.kA = take(sizeof(uint64_t) * ks * 64 * sbt::mfma_words(jp));
+    }
     if (tiled && mode != SBT_DSB) {  // the tiled streaming step's plan
         const size_t nsuper = (static_cast<size_t>(n) + sbt::kTileSuper - 1) / sbt::kTileSuper;
         L.tile_info = take(2 * sizeof(int32_t) * nsuper * sbt::kTileSuper);
@@ -117,7 +133,7 @@ int check_params(const sbt_solve_params &p, const char *who) {
     if (p.steps < 1) return fail(SBT_EINVAL, "%s: steps must be >= 1", who);
     if (p.energy_every < 0) return fail(SBT_EINVAL, "%s: energy_every must be >= 0", who);
     if (p.event < 0) return fail(SBT_EINVAL, "%s: event must be >= 0", who);
-    if (p.kernel < SBT_KERNEL_AUTO || p.kernel > SBT_KERNEL_STREAM_ROWS)
+    if (p.kernel < SBT_KERNEL_AUTO || p.kernel > SBT_KERNEL_STREAM_MFMA)
         return fail(SBT_EINVAL, "%s: unknown kernel %d", who, p.kernel);
     if (p.tpb != 0 && p.tpb != 64 && p.tpb != 256 && p.tpb != 512 && p.tpb != 1024)
         return fail(SBT_EINVAL, "%s: tpb must be 0, 64, 256, 512 or 1024", who);
@@ -217,6 +233,15 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
     if (p.kernel == SBT_KERNEL_STREAM_TILE && mode == SBT_DSB)
         return fail(SBT_EUNSUPPORTED, "the tiled streaming step is for bSB and aSB (dSB reads "
                     "sign planes)");
+    if (p.kernel == SBT_KERNEL_STREAM_MFMA) {
+        if (mode != SBT_DSB)
+            return fail(SBT_EUNSUPPORTED, "the matrix-core step is for dSB (bSB and aSB couple "
+                        "through continuous positions)");
+        if (p.precision != SBT_PREC_FP8 && p.precision != SBT_PREC_BF16X2)
+            return fail(SBT_EUNSUPPORTED, "the matrix-core step takes FP8 (per-row scale) or "
+                        "BF16X2 couplings");
+        return SBT_KERNEL_STREAM_MFMA;
+    }
     if (p.precision == SBT_PREC_FP8 || p.precision == SBT_PREC_FP8_BLOCK ||
         p.precision == SBT_PREC_BF16X2) {
         if (p.kernel == SBT_KERNEL_RESIDENT)
@@ -425,6 +450,15 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
             T.ploc = reinterpret_cast<uint16_t *>(ws + L.ploc);
             SBT_HIP(sbt::launch_tile_plan(n, prow, pcol, T, st));
         }
+        const bool mfma = kernel == SBT_KERNEL_STREAM_MFMA;
+        sbt::MfmaArgs P{};
+        if (mfma) {
+            P.kcnt = reinterpret_cast<int *>(ws + L.kcnt);
+            P.koff = reinterpret_cast<int *>(ws + L.koff);
+            P.kcol = reinterpret_cast<int *>(ws + L.kcol);
+            P.kA = reinterpret_cast<uint64_t *>(ws + L.kA);
+            SBT_HIP(sbt::launch_mfma_plan(jprec, A, P, st));
+        }
         const bool quads = kernel == SBT_KERNEL_STREAM && quad_step(mode, M);
         sbt::QuadArgs Q{};
         if (quads) {
@@ -438,11 +472,17 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         // bSB: positions ping-pong between xa and xb
         float *xin = xa, *xout = xb;
         uint64_t *Sin = S0, *Sout = S1;
-        if (mode == SBT_DSB) SBT_HIP(sbt::launch_sign_planes(n, M, xa, S0, st));
+        if (mfma)
+            SBT_HIP(sbt::launch_mfma_signs(n, M, xa, reinterpret_cast<uint8_t *>(S0), st));
+        else if (mode == SBT_DSB)
+            SBT_HIP(sbt::launch_sign_planes(n, M, xa, S0, st));
         int ck = 0;
         for (int k = 0; k < K; ++k) {
             if (tiled)
                 SBT_HIP(sbt::launch_stream_tile(static_cast<int>(mode), jprec, A, T, k, xin, xout, st));
+            else if (mfma)
+                SBT_HIP(sbt::launch_stream_mfma(jprec, A, P, k, xin, reinterpret_cast<const uint8_t *>(Sin),
+                                                reinterpret_cast<uint8_t *>(Sout), st));
             else if (quads)
                 SBT_HIP(sbt::launch_stream_quad(static_cast<int>(mode), A, Q, k, xin, xout, st));
             else

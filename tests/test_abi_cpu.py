@@ -158,6 +158,31 @@ def test_precision_selects_or_rejects_kernels():
         sbt.select_kernel(n, nnz, row, "bsb", p)
 
 
+def test_matrix_core_step_selection_and_workspace():
+    """The matrix-core step runs on request only, for dSB with FP8 (per-row
+    scale) or BF16X2 couplings; its block lists and operand tiles add at
+    most (nnz / 32 + n / 16 + 1) K-steps of 640 (FP8) or 2176 (BF16X2)
+    bytes, and its sign records replace the sign words."""
+    n, nnz, row = 1480, 2722, 12
+    for prec in ("fp8", "bf16x2"):
+        p = sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma")
+        assert sbt.select_kernel(n, nnz, row, "dsb", p) == "stream_mfma"
+        assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision=prec)) \
+            == "stream"
+    for mode, prec in (("bsb", "fp8"), ("asb", "bf16x2"), ("dsb", "fp32"), ("dsb", "fp8_block")):
+        with pytest.raises(sbt.SbtError) as e:
+            sbt.select_kernel(n, nnz, row, mode,
+                              sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma"))
+        assert e.value.code == _lib.SBT_EUNSUPPORTED
+    ks = nnz // 32 + (n + 15) // 16 + 1
+    for prec, per in (("fp8", 640), ("bf16x2", 2176)):
+        base = sbt.workspace_bytes(n, nnz, "dsb", sbt.solve_params(agents=256, precision=prec,
+                                                                   kernel="stream"))
+        mf = sbt.workspace_bytes(n, nnz, "dsb", sbt.solve_params(agents=256, precision=prec,
+                                                                 kernel="stream_mfma"))
+        assert base + ks * per <= mf <= base + ks * per + 4 * (n + 16) + 8 * 256
+
+
 def test_solve_rejects_malformed_qubo_before_touching_a_device():
     ev = tg.generate(tg.plain_spec(60), 1)
     q = sbt.build_qubo(ev.hits_struct())

@@ -51,6 +51,17 @@ def _two_hop(b, rows):
 @pytest.mark.parametrize("mode,kernel", [("bsb", "stream"), ("bsb", "stream_rows"),
                                          ("bsb", "stream_tile"), ("dsb", "stream")])
 def test_two_steps_on_sampled_rows(stress, mode, kernel, prec):
+    _sampled_rows_after_two_steps(stress, mode, kernel, prec)
+
+
+@pytest.mark.parametrize("prec", ["fp8", "bf16x2"])
+def test_matrix_core_dsb_two_steps_on_sampled_rows(stress, prec):
+    """The matrix-core dSB step in the benchmark's configuration (512
+    agents: two sign words per wave; 13045 blocks of 16 rows)."""
+    _sampled_rows_after_two_steps(stress, "dsb", "stream_mfma", prec)
+
+
+def _sampled_rows_after_two_steps(stress, mode, kernel, prec):
     q, b, isg = stress
     K = 2
     r = sbt.solve(q, mode, agents=M, steps=K, seed=SEED, precision=prec, kernel=kernel,
@@ -64,6 +75,8 @@ def test_two_steps_on_sampled_rows(stress, mode, kernel, prec):
     J = isg.J[s2][:, s2].tocsr()
     if prec == "fp8":
         J, _, _ = oquant.fp8_rows(J)     # per-row scales of complete rows
+    elif prec == "bf16x2":
+        J = oquant.bf16x2_couplings(J)
     x0, y0 = ophilox.initial_state(q.n, M, SEED, 0, spins=s2)
     ref = osb.run(J, isg.h[s2], isg.c0, mode, M, K, seed=SEED, x0=x0, y0=y0, margin_steps=K)
     pos = np.searchsorted(s2, rows)
