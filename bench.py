@@ -391,20 +391,44 @@ def stream_bytes(n, nnz, agents, jbytes):
     return 16.0 * n * agents + (4.0 + jbytes) * nnz + 12.0 * n
 
 
-def stream_bytes_dsb(n, nnz, agents):
+def stream_bytes_dsb(n, nnz, agents, jbytes=4):
     """Algorithmic HBM bytes of one dSB streaming launch: x, y read and
     written in place per spin update, the 64-agent sign words of every spin
     read once and written once, each coupling's column and value once, h,
     row pointers and the per-row scale once."""
     words = (agents + 63) // 64
-    return 16.0 * n * agents + 16.0 * n * words + 8.0 * nnz + 12.0 * n
+    return 16.0 * n * agents + 16.0 * n * words + (4.0 + jbytes) * nnz + 12.0 * n
 
 
-def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=True):
+def _step_ms(sbt, torch, q, mode, kernel, prec, M, K):
+    """Average time of one SB step: HIP events around the step loops of two
+    device-resident solves, K and K / 5 steps, differenced, so that one-off
+    set-up inside the loop window (the quad, tile and block plans) cancels."""
+    def loop_ms(k):
+        s = sbt.DeviceSolver(q, mode, sbt.solve_params(agents=M, steps=k, seed=0, kernel=kernel,
+                                                        precision=prec))
+        b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        b.record()
+        e.record()
+        torch.cuda.synchronize()
+        s._dr.step_begin, s._dr.step_end = b.cuda_event, e.cuda_event
+        s.run()
+        torch.cuda.synchronize()
+        ms = b.elapsed_time(e)
+        del s
+        torch.cuda.empty_cache()
+        return ms
+    k1 = max(1, K // 5)
+    return (loop_ms(K) - loop_ms(k1)) / (K - k1)
+
+
+def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=True, dsb_kernel=None):
     """5000 particles (N ~ 2.1e5), bSB, 512 agents x 10000 steps on the
     streaming kernel: FP8 couplings (the workload's storage) and FP32, spins
     in azimuth order, FP64 energies of every agent on the GPU; the tiled
-    streaming step's launch time beside them."""
+    and one-row bSB steps' launch times beside them, and the dSB step on
+    the same event, CSR (sign words as lane masks) against matrix cores.
+    With dsb_kernel set the main solves are dSB on that kernel instead."""
     ev = tg.generate(tg.stress_spec(), 300)
     hits = ev.hits_struct()
     bp = sbt.build_params_default()
@@ -423,15 +447,17 @@ def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=T
     t_order = time.perf_counter() - t0
     del q0
     M = 512
+    mode = "dsb" if dsb_kernel else "bsb"
     out = {"workload": "stress: 10-layer barrel, 5000 particles + 20% noise, |eta| < 2, event "
-                       f"seed 300, doublet |z0| <= 300 mm; bSB, 512 agents x {K} steps, "
+                       f"seed 300, doublet |z0| <= 300 mm; {mode[0]}SB, 512 agents x {K} steps, "
                        "spins in azimuth order",
            "n": q.n, "nnz": q.nnz, "host_build_s": t_build, "host_order_s": t_order,
            "gpu_build_s": t_gpu, "gpu_build_device_s": t_gpu_dev,
            "gpu_build_same_structure": same}
     for prec in precisions:
-        s = sbt.DeviceSolver(q, "bsb", sbt.solve_params(agents=M, steps=K, seed=0,
-                                                         kernel="stream", precision=prec))
+        s = sbt.DeviceSolver(q, mode, sbt.solve_params(agents=M, steps=K, seed=0,
+                                                        kernel=dsb_kernel or "stream",
+                                                        precision=prec))
         b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         b.record()
         e.record()
@@ -445,14 +471,21 @@ def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=T
         launch_s = b.elapsed_time(e) * 1e-3 / K
         best32, _ = sbt.top_k(s.agent_energy, 32)  # FP64 energies of the best 32 agents, on the GPU
         r = s.result()
-        byts = stream_bytes(q.n, q.nnz, M, 1 if prec == "fp8" else 4)
+        jb = 1 if prec == "fp8" else 4
+        if dsb_kernel:
+            byts = stream_bytes_dsb(q.n, q.nnz, M, jb)
+            kname = "sb_stream_mfma" if dsb_kernel == "stream_mfma" else "sb_stream"
+            record = f"sb_stream_mfma_stress_dsb_{prec}.md" if dsb_kernel == "stream_mfma" else None
+        else:
+            byts = stream_bytes(q.n, q.nnz, M, jb)
+            kname, record = "sb_stream_quad", f"sb_stream_stress_{prec}.md"
         achieved = byts / launch_s / 1e9
         out[prec] = {"seconds": wall, "spin_updates_per_s": q.n * M * K / wall,
                      "best": r["energy"], "mean_best_32": float(best32.mean()),
                      "roofline": {"bound": "hbm", "achieved": achieved, "peak": MI355X_HBM_GBS,
                                   "unit": "GB/s", "frac": achieved / MI355X_HBM_GBS,
-                                  "traffic": measured_traffic(f"sb_stream_stress_{prec}.md"),
-                                  "kernel": "sb_stream_quad", "launch_ms": launch_s * 1e3,
+                                  "traffic": measured_traffic(record) if record else None,
+                                  "kernel": kname, "launch_ms": launch_s * 1e3,
                                   "bytes_per_launch": byts}}
         del s
         torch.cuda.empty_cache()
@@ -463,21 +496,23 @@ def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=T
         k_cmp = min(K, 200)
         for key, kern, name in (("fp32_tiled", "stream_tile", "sb_stream_tile"),
                                 ("fp32_rows", "stream_rows", "sb_stream_v4")):
-            s = sbt.DeviceSolver(q, "bsb", sbt.solve_params(agents=M, steps=k_cmp, seed=0,
-                                                             kernel=kern))
-            b, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            b.record()
-            e.record()
-            torch.cuda.synchronize()
-            s._dr.step_begin, s._dr.step_end = b.cuda_event, e.cuda_event
-            s.run()
-            torch.cuda.synchronize()
-            launch_s = b.elapsed_time(e) * 1e-3 / k_cmp
+            ms = _step_ms(sbt, torch, q, "bsb", kern, "fp32", M, k_cmp)
             byts = stream_bytes(q.n, q.nnz, M, 4)
-            out[key] = {"kernel": name, "steps": k_cmp, "launch_ms": launch_s * 1e3,
-                        "hbm_frac": byts / launch_s / 1e9 / MI355X_HBM_GBS}
-            del s
-            torch.cuda.empty_cache()
+            out[key] = {"kernel": name, "steps": k_cmp, "launch_ms": ms,
+                        "hbm_frac": byts / ms / 1e6 / MI355X_HBM_GBS}
+        # dSB on the same event: the CSR step (64-agent sign words as lane
+        # masks) against the matrix-core step (16-row blocks as dense
+        # operands of their column union, signs as +-1 operands)
+        dsb = {"agents": M, "steps": k_cmp}
+        for prec, jb in (("fp8", 1), ("bf16x2", 4)):
+            byts = stream_bytes_dsb(q.n, q.nnz, M, jb)
+            for kern, name in (("stream", "sb_stream"), ("stream_mfma", "sb_stream_mfma")):
+                ms = _step_ms(sbt, torch, q, "dsb", kern, prec, M, k_cmp)
+                dsb[f"{kern}_{prec}"] = {"kernel": name, "launch_ms": ms,
+                                         "hbm_frac": byts / ms / 1e6 / MI355X_HBM_GBS}
+            dsb[f"mfma_speedup_{prec}"] = (dsb[f"stream_{prec}"]["launch_ms"] /
+                                           dsb[f"stream_mfma_{prec}"]["launch_ms"])
+        out["dsb_steps"] = dsb
     if "fp8" in out and "fp32" in out:
         out["fp8_rel_gap_vs_fp32"] = (out["fp8"]["best"] - out["fp32"]["best"]) / abs(out["fp32"]["best"])
     return out
@@ -758,9 +793,12 @@ def main():
                          "launches (for counter collection)")
     ap.add_argument("--stress-steps", type=int, default=10000,
                     help="SB steps of the stress form (10000 is the workload's)")
-    ap.add_argument("--stress-prec", choices=["fp8", "fp32"], default=None,
+    ap.add_argument("--stress-prec", choices=["fp8", "fp32", "bf16x2"], default=None,
                     help="stress form: only this coupling form, without the tiled comparison "
                          "(profiling one precision's launches)")
+    ap.add_argument("--stress-dsb", choices=["stream", "stream_mfma"], default=None,
+                    help="stress form: the main solves are dSB on this step kernel (profiling "
+                         "the dSB steps), without the comparisons")
     ap.add_argument("--kernel", default="auto", choices=["auto", "resident", "stream"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 256 MiB buffer 3 times (reference for HBM byte counters)")
@@ -804,8 +842,10 @@ def main():
                     "precision": lambda: precision_form(sbt, tg, torch, np),
                     "stress": lambda: stress_form(
                         sbt, tg, torch, np, args.stress_steps,
-                        (args.stress_prec,) if args.stress_prec else ("fp8", "fp32"),
-                        tiled=args.stress_prec is None)}[args.only]
+                        (args.stress_prec,) if args.stress_prec else
+                        (("fp8", "bf16x2") if args.stress_dsb == "stream_mfma" else ("fp8", "fp32")),
+                        tiled=args.stress_prec is None and args.stress_dsb is None,
+                        dsb_kernel=args.stress_dsb)}[args.only]
         print(json.dumps({f"{args.only}_form": form()}), flush=True)
         return
 

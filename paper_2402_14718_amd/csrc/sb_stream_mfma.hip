@@ -58,25 +58,28 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 // at[r] the row's entry for that column or -1.
 template <class F>
 __device__ __forceinline__ void block_union(int n, const int *prow, const int *pcol, int b, F &&f) {
-    int pos[kBR], end[kBR];
+    int pos[kBR], end[kBR], head[kBR];  // head: the row's next column (INT32_MAX: none)
 #pragma unroll
     for (int r = 0; r < kBR; ++r) {
         const int i = b * kBR + r;
         pos[r] = i < n ? prow[i] : 0;
         end[r] = i < n ? prow[i + 1] : 0;
         while (pos[r] < end[r] && pcol[end[r] - 1] == i) --end[r];  // drop the padding
+        head[r] = pos[r] < end[r] ? pcol[pos[r]] : INT32_MAX;
     }
     while (true) {
         int c = INT32_MAX;
 #pragma unroll
-        for (int r = 0; r < kBR; ++r)
-            if (pos[r] < end[r]) c = min(c, pcol[pos[r]]);
+        for (int r = 0; r < kBR; ++r) c = min(c, head[r]);
         if (c == INT32_MAX) break;
         int at[kBR];
 #pragma unroll
         for (int r = 0; r < kBR; ++r) {
             at[r] = -1;
-            if (pos[r] < end[r] && pcol[pos[r]] == c) at[r] = pos[r]++;
+            if (head[r] == c) {
+                at[r] = pos[r]++;
+                head[r] = pos[r] < end[r] ? pcol[pos[r]] : INT32_MAX;
+            }
         }
         f(c, at);
     }
@@ -117,48 +120,62 @@ __global__ __launch_bounds__(kScanThreads) void mfma_scan(int nb, const int *__r
     if (t == kScanThreads - 1) off[nb] = tot[t];
 }
 
-// Operand entry of listed column u (0-based in the block) and row r: lane
-// 16 ((u % 32) / 8) + r of K-step u / 32, element u % 8.
-__device__ __forceinline__ size_t operand_slot(int ks0, int u, int r) {
-    const int ks = ks0 + u / kBK, g = (u % kBK) / 8;
-    return (static_cast<size_t>(ks) * 64 + 16 * g + r) * 8 + (u % 8);
-}
-
-// Lists block b's columns and writes every operand element of its K-steps
-// (the codes of FP8; BF16 hi and lo), zeros where a row has no coupling and
-// in the padding, whose column repeats the last listed one.
+// Lists block b's columns and writes every operand word of its K-steps:
+// listed column u (0-based in the block) of row r is element u % 8 of lane
+// 16 ((u % 32) / 8) + r in K-step u / 32 (FP8: byte e of the lane's word;
+// BF16 pairs: hi in words 0-1, lo in words 2-3, 16 bits per element); zeros
+// where a row has no coupling and in the padding, whose column repeats the
+// last listed one.  A lane's word is assembled over 8 consecutive listed
+// columns and stored whole.
 template <int JP>
 __global__ __launch_bounds__(256) void mfma_fill(int nb, StreamArgs A, const int *__restrict__ koff,
                                                  int *__restrict__ kcol, uint64_t *__restrict__ kA) {
+    constexpr int W = mfma_words(JP);
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= nb) return;
     const int ks0 = koff[b], u1 = (koff[b + 1] - ks0) * kBK;
-    uint8_t *a8 = reinterpret_cast<uint8_t *>(kA);
-    uint16_t *a16 = reinterpret_cast<uint16_t *>(kA);
-    int u = 0, last = 0;
-    auto put = [&](int uu, int r, int p) {
-        const size_t s = operand_slot(ks0, uu, r);
-        if constexpr (JP == kJBf16x2) {
-            const uint32_t v = p >= 0 ? A.J2[p] : 0u;
-            // lane words 0-1: eight hi; 2-3: eight lo
-            const size_t lane_base = (s / 8) * 16, e = s % 8;
-            a16[lane_base + e] = static_cast<uint16_t>(v >> 16);
-            a16[lane_base + 8 + e] = static_cast<uint16_t>(v & 0xFFFFu);
-        } else {
-            a8[s] = p >= 0 ? A.J8[p] : static_cast<uint8_t>(0);
-        }
+    uint64_t buf[kBR][W];
+#pragma unroll
+    for (int r = 0; r < kBR; ++r)
+#pragma unroll
+        for (int w = 0; w < W; ++w) buf[r][w] = 0;
+    auto flush = [&](int u) {  // u: the last listed column of a group of 8
+        const size_t lane0 = static_cast<size_t>(ks0 + u / kBK) * 64 + 16 * ((u % kBK) / 8);
+#pragma unroll
+        for (int r = 0; r < kBR; ++r)
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                kA[(lane0 + r) * W + w] = buf[r][w];
+                buf[r][w] = 0;
+            }
     };
+    int u = 0, last = 0;
     block_union(A.n, A.row_ptr, A.col, b, [&](int c, const int *at) {
         kcol[static_cast<size_t>(ks0) * kBK + u] = c;
+        const int e = u % 8;
 #pragma unroll
-        for (int r = 0; r < kBR; ++r) put(u, r, at[r]);
+        for (int r = 0; r < kBR; ++r) {
+            if (at[r] < 0) continue;
+            if constexpr (JP == kJBf16x2) {
+                const uint64_t v = A.J2[at[r]];
+                const int sh = 16 * (e % 4);
+#pragma unroll
+                for (int w = 0; w < 2; ++w)
+                    if (e / 4 == w) {
+                        buf[r][w] |= (v >> 16) << sh;
+                        buf[r][2 + w] |= (v & 0xFFFFu) << sh;
+                    }
+            } else {
+                buf[r][0] |= static_cast<uint64_t>(A.J8[at[r]]) << (8 * e);
+            }
+        }
         last = c;
+        if (e == 7) flush(u);
         ++u;
     });
     for (; u < u1; ++u) {
         kcol[static_cast<size_t>(ks0) * kBK + u] = last;
-#pragma unroll
-        for (int r = 0; r < kBR; ++r) put(u, r, -1);
+        if (u % 8 == 7) flush(u);
     }
 }
 

@@ -34,6 +34,8 @@ KERNEL_SOURCES = {
     "sb_batch": ["csrc/sb_batch.hip", "csrc/sb_batch_step.hpp", "csrc/sb_batch_mode.hip",
                  "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
     "sb_batch_gang": ["csrc/sb_batch_gang.hip", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
+    "sb_stream_mfma": ["csrc/sb_stream_mfma.hip", "csrc/sb_stream_mfma.hpp", "csrc/sb_stream_kernels.hpp",
+                       "csrc/sb_stream_chunk.hpp", "csrc/sb_device.hpp", "csrc/sb_kernels.hpp"],
 }
 COPY_BYTES = 256 << 20
 
