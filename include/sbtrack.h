@@ -223,7 +223,9 @@ typedef enum {
                                 from the CSR step by rounding.  Planned
                                 once per solve on the GPU; the workspace
                                 grows by about (nnz / 32 + n / 16) x 640
-                                bytes (FP8) or x 2176 (BF16X2).
+                                bytes (FP8) or x 2176 (BF16X2), plus x
+                                and y in the step's own tiles (rows
+                                padded to 16, agents to 128).
                                 Only on request (AUTO never picks it)    */
 } sbt_kernel;
 

@@ -30,7 +30,10 @@
 // columns x rows), so the instruction pairs them; the 16 x 16 result of
 // tile t (agents x rows) holds, in lane (g, c), agents 16 t + 4 g .. + 3 of
 // row c: four consecutive agents, one 16-byte access of x and of y, and
-// the lane's 32 new signs of row c are dword g of the row's record.
+// the lane's 32 new signs of row c are dword g of the row's record.  x and
+// y are kept in this step's own tiled layout (mfma_state_floats), where a
+// wave's accesses for one t are one contiguous 1 KB run: in the spin-major
+// layout they touch 16 rows x 64 bytes and the step ran 1.4 x slower.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -211,6 +214,32 @@ __global__ __launch_bounds__(256) void mfma_signs(int n, int M, const float *__r
     S[idx] = static_cast<uint8_t>(byte);
 }
 
+// Spin-major x[i M + m] <-> the step's tiles (layout of mfma_state_floats);
+// one thread per 16-byte run of a tile.
+__global__ __launch_bounds__(256) void mfma_state(int n, int M, bool to_tiles, const float *__restrict__ src,
+                                                  float *__restrict__ dst) {
+    const int R = mfma_groups(M);
+    const int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (q >= static_cast<int64_t>(mfma_state_floats(n, M) / 4)) return;
+    const int64_t tile = q / 512;
+    const int w = static_cast<int>(q % 512), t = w / 64, lane = w % 64;
+    const int b = static_cast<int>(tile / R), ab = static_cast<int>(tile % R);
+    const int i = b * kBR + (lane & 15), m = kMfmaGroup * ab + 16 * t + 4 * (lane >> 4);
+    const size_t row = static_cast<size_t>(i) * M;
+    if (to_tiles) {
+        f32x4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (i < n && m + r < M) v[r] = src[row + m + r];
+        *reinterpret_cast<f32x4 *>(dst + 4 * q) = v;
+    } else if (i < n) {
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(src + 4 * q);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (m + r < M) dst[row + m + r] = v[r];
+    }
+}
+
 }  // namespace
 
 // One dSB step: a wave = one block of 16 rows x one group of 128 agents.
@@ -239,21 +268,15 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    // The lane's x, y (row 16 b + c, agents 128 ab + 16 t + 4 g + r) are
-    // loaded before the coupling sums, so their latency hides behind them.
-    const int i = b * kBR + c;
-    const bool vec = M % 4 == 0;   // 16-byte aligned runs of four agents
+    // The lane's x, y (row 16 b + c, agents 128 ab + 16 t + 4 g + r: 16
+    // bytes at tile + 256 t, padding included) are loaded before the
+    // coupling sums, so their latency hides behind them.
+    const size_t tile = (static_cast<size_t>(b) * R + ab) * (kBR * kMfmaGroup) + 4 * lane;
     f32x4 xp[T], yp[T];
-    if (vec && i < A.n) {
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const int m = kMfmaGroup * ab + 16 * t + 4 * g;
-            if (m < M) {
-                const size_t o = static_cast<size_t>(i) * M + m;
-                xp[t] = ld_stream<NT>(reinterpret_cast<const f32x4 *>(x + o));
-                yp[t] = ld_stream<NT>(reinterpret_cast<const f32x4 *>(y + o));
-            }
-        }
+    for (int t = 0; t < T; ++t) {
+        xp[t] = ld_stream<NT>(reinterpret_cast<const f32x4 *>(x + tile + 256 * t));
+        yp[t] = ld_stream<NT>(reinterpret_cast<const f32x4 *>(y + tile + 256 * t));
     }
 
     // The block's sign records pass through LDS, kChunkSteps K-steps at a
@@ -357,7 +380,9 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
     }
 
     // acc[t][r] = -(sum over the block's columns) for row 16 b + c, agent
-    // 128 ab + 16 t + 4 g + r
+    // 128 ab + 16 t + 4 g + r (agents past M are padding: updated, never
+    // read back, their sign bits 0)
+    const int i = b * kBR + c;
     if (i >= A.n) return;
     const float c0 = static_cast<float>(A.scal[0]);
     const float gk = A.sched[k];
@@ -367,30 +392,17 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int m = kMfmaGroup * ab + 16 * t + 4 * g;
-        const size_t o = static_cast<size_t>(i) * M + m;
-        if (vec && m < M) {
-            f32x4 xv = xp[t], yv = yp[t];
+        f32x4 xv = xp[t], yv = yp[t];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float xr = xv[r], yr = yv[r];
-                sb_update(xr, yr, __builtin_fmaf(-sc, acc[t][r], hv), c0, gk, A.dt, A.dta0);
-                xv[r] = xr;
-                yv[r] = yr;
-                if (xr >= 0.0f) word |= 1u << (8 * r + t);
-            }
-            st_stream<NT>(xv, reinterpret_cast<f32x4 *>(x + o));
-            st_stream<NT>(yv, reinterpret_cast<f32x4 *>(y + o));
-        } else if (!vec) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (m + r >= M) break;
-                float xr = ld_stream<NT>(x + o + r), yr = ld_stream<NT>(y + o + r);
-                sb_update(xr, yr, __builtin_fmaf(-sc, acc[t][r], hv), c0, gk, A.dt, A.dta0);
-                st_stream<NT>(xr, x + o + r);
-                st_stream<NT>(yr, y + o + r);
-                if (xr >= 0.0f) word |= 1u << (8 * r + t);
-            }
+        for (int r = 0; r < 4; ++r) {
+            float xr = xv[r], yr = yv[r];
+            sb_update(xr, yr, __builtin_fmaf(-sc, acc[t][r], hv), c0, gk, A.dt, A.dta0);
+            xv[r] = xr;
+            yv[r] = yr;
+            if (m + r < M && xr >= 0.0f) word |= 1u << (8 * r + t);
         }
+        st_stream<NT>(xv, reinterpret_cast<f32x4 *>(x + tile + 256 * t));
+        st_stream<NT>(yv, reinterpret_cast<f32x4 *>(y + tile + 256 * t));
     }
     reinterpret_cast<uint32_t *>(Sout)[(static_cast<size_t>(i) * R + ab) * 4 + g] = word;
 }
@@ -413,6 +425,13 @@ hipError_t launch_mfma_plan(int jprec, const StreamArgs &A, const MfmaArgs &P, h
     return hipGetLastError();
 }
 
+hipError_t launch_mfma_state(int n, int M, bool to_tiles, const float *src, float *dst, hipStream_t st) {
+    const int64_t runs = static_cast<int64_t>(mfma_state_floats(n, M) / 4);
+    if (runs > 0)
+        mfma_state<<<static_cast<unsigned>((runs + 255) / 256), 256, 0, st>>>(n, M, to_tiles, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_mfma_signs(int n, int M, const float *x, uint8_t *S, hipStream_t st) {
     const int64_t total = static_cast<int64_t>(n) * mfma_groups(M) * 16;
     if (total > 0) mfma_signs<<<static_cast<unsigned>((total + 255) / 256), 256, 0, st>>>(n, M, x, S);
@@ -422,29 +441,29 @@ hipError_t launch_mfma_signs(int n, int M, const float *x, uint8_t *S, hipStream
 namespace {
 
 template <int JP>
-hipError_t launch_mfma_form(const StreamArgs &A, const MfmaArgs &P, int k, float *x, const uint8_t *Sin,
-                            uint8_t *Sout, hipStream_t st) {
+hipError_t launch_mfma_form(const StreamArgs &A, const MfmaArgs &P, int k, float *x, float *y,
+                            const uint8_t *Sin, uint8_t *Sout, hipStream_t st) {
     const int nb = (A.n + kBR - 1) / kBR;
     const int total = (nb + 3) / 4 * mfma_groups(A.M);
     const dim3 grid((total + 7) / 8 * 8);
     // x and y, FP32, past the caches when larger than the Infinity Cache
     const bool nt = static_cast<size_t>(A.n) * A.M * sizeof(float) * 2 > (size_t(256) << 20);
     if (nt)
-        sb_stream_mfma<JP, true><<<grid, 256, 0, st>>>(A, k, P.koff, P.kcol, P.kA, A.h, A.rowscale, x, A.y,
+        sb_stream_mfma<JP, true><<<grid, 256, 0, st>>>(A, k, P.koff, P.kcol, P.kA, A.h, A.rowscale, x, y,
                                                        Sin, Sout);
     else
-        sb_stream_mfma<JP, false><<<grid, 256, 0, st>>>(A, k, P.koff, P.kcol, P.kA, A.h, A.rowscale, x, A.y,
+        sb_stream_mfma<JP, false><<<grid, 256, 0, st>>>(A, k, P.koff, P.kcol, P.kA, A.h, A.rowscale, x, y,
                                                         Sin, Sout);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_stream_mfma(int jprec, const StreamArgs &A, const MfmaArgs &P, int k, float *x,
+hipError_t launch_stream_mfma(int jprec, const StreamArgs &A, const MfmaArgs &P, int k, float *x, float *y,
                               const uint8_t *Sin, uint8_t *Sout, hipStream_t st) {
     switch (jprec) {
-        case kJFp8: return launch_mfma_form<kJFp8>(A, P, k, x, Sin, Sout, st);
-        case kJBf16x2: return launch_mfma_form<kJBf16x2>(A, P, k, x, Sin, Sout, st);
+        case kJFp8: return launch_mfma_form<kJFp8>(A, P, k, x, y, Sin, Sout, st);
+        case kJBf16x2: return launch_mfma_form<kJBf16x2>(A, P, k, x, y, Sin, Sout, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -51,13 +51,29 @@ __host__ __device__ constexpr size_t mfma_sign_bytes(int n, int M) {
 }
 hipError_t launch_mfma_signs(int n, int M, const float *x, uint8_t *S, hipStream_t st);
 
+// The step's own layout of x and y: each (block of kMfmaRows rows, group of
+// kMfmaGroup agents) is one contiguous tile of 2048 floats, in the order the
+// step's lanes touch them -- element (row 16 b + c, agent 128 a + 16 t + 4 g
+// + r) at (b R + a) 2048 + 256 t + 4 (16 g + c) + r, R = mfma_groups(M) --
+// so every 16-byte access of a wave falls in one 1 KB run.  Rows are padded
+// to whole blocks and agents to whole groups (the padding is zero and never
+// read back).  Converted from and to the spin-major layout (x[i M + m]) of
+// the other kernels at the start, at energy checkpoints and at the end.
+__host__ __device__ constexpr size_t mfma_state_floats(int n, int M) {
+    return static_cast<size_t>((n + kMfmaRows - 1) / kMfmaRows) * mfma_groups(M) * kMfmaRows * kMfmaGroup;
+}
+// to_tiles: spin-major src -> tiled dst (padding zeroed); else tiled src ->
+// spin-major dst.
+hipError_t launch_mfma_state(int n, int M, bool to_tiles, const float *src, float *dst, hipStream_t st);
+
 // Upper bound on the K-steps of all blocks: a block lists at most its own
 // couplings, padded by fewer than kMfmaK.
 size_t mfma_ksteps_bound(int n, int64_t nnz);
 hipError_t launch_mfma_plan(int jprec, const StreamArgs &A, const MfmaArgs &P, hipStream_t st);
-// One dSB step, x and y in place; the neighbours' signs are read from the
-// records Sin and the new signs written to Sout (mfma_sign_bytes each).
-hipError_t launch_stream_mfma(int jprec, const StreamArgs &A, const MfmaArgs &P, int k, float *x,
+// One dSB step on the tiled x, y (mfma_state_floats each), in place; the
+// neighbours' signs are read from the records Sin and the new signs written
+// to Sout (mfma_sign_bytes each).
+hipError_t launch_stream_mfma(int jprec, const StreamArgs &A, const MfmaArgs &P, int k, float *x, float *y,
                               const uint8_t *Sin, uint8_t *Sout, hipStream_t st);
 
 }  // namespace sbt

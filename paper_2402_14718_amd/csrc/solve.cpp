@@ -27,7 +27,7 @@ struct Layout {
     size_t J = 0, h = 0, scal = 0, prep = 0, perm = 0, sched = 0, xa = 0, xb = 0, y = 0, epart = 0,
            etrace = 0, S0 = 0, S1 = 0, J8 = 0, rowscale = 0, prow = 0, pcol = 0, pJ = 0,
            tile_info = 0, tile_n = 0, tile_cols = 0, ploc = 0, blkscale = 0, J2 = 0, qcnt = 0,
-           qoff = 0, qcol = 0, qJ = 0, kcnt = 0, koff = 0, kcol = 0, kA = 0;
+           qoff = 0, qcol = 0, qJ = 0, kcnt = 0, koff = 0, kcol = 0, kA = 0, xt = 0, yt = 0;
     size_t total = 0;
     int n_ckpt = 0;
 };
@@ -111,6 +111,8 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
         L.koff = take(sizeof(int32_t) * (nb + 1));
         L.kcol = take(sizeof(int32_t) * ks * sbt::kMfmaK);
         L.kA = take(sizeof(uint64_t) * ks * 64 * sbt::mfma_words(jp));
+        L.xt = take(sizeof(float) * sbt::mfma_state_floats(n, M));  // x, y in the step's tiles
+        L.yt = take(sizeof(float) * sbt::mfma_state_floats(n, M));
     }
     if (tiled && mode != SBT_DSB) {  // the tiled streaming step's plan
         const size_t nsuper = (static_cast<size_t>(n) + sbt::kTileSuper - 1) / sbt::kTileSuper;
@@ -472,16 +474,19 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
         // bSB: positions ping-pong between xa and xb
         float *xin = xa, *xout = xb;
         uint64_t *Sin = S0, *Sout = S1;
-        if (mfma)
+        float *xt = reinterpret_cast<float *>(ws + L.xt), *yt = reinterpret_cast<float *>(ws + L.yt);
+        if (mfma) {
             SBT_HIP(sbt::launch_mfma_signs(n, M, xa, reinterpret_cast<uint8_t *>(S0), st));
-        else if (mode == SBT_DSB)
+            SBT_HIP(sbt::launch_mfma_state(n, M, true, xa, xt, st));
+            SBT_HIP(sbt::launch_mfma_state(n, M, true, dy, yt, st));
+        } else if (mode == SBT_DSB)
             SBT_HIP(sbt::launch_sign_planes(n, M, xa, S0, st));
         int ck = 0;
         for (int k = 0; k < K; ++k) {
             if (tiled)
                 SBT_HIP(sbt::launch_stream_tile(static_cast<int>(mode), jprec, A, T, k, xin, xout, st));
             else if (mfma)
-                SBT_HIP(sbt::launch_stream_mfma(jprec, A, P, k, xin, reinterpret_cast<const uint8_t *>(Sin),
+                SBT_HIP(sbt::launch_stream_mfma(jprec, A, P, k, xt, yt, reinterpret_cast<const uint8_t *>(Sin),
                                                 reinterpret_cast<uint8_t *>(Sout), st));
             else if (quads)
                 SBT_HIP(sbt::launch_stream_quad(static_cast<int>(mode), A, Q, k, xin, xout, st));
@@ -490,10 +495,15 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
             std::swap(xin, xout);
             std::swap(Sin, Sout);
             if (p->energy_every > 0 && (k + 1) % p->energy_every == 0) {
+                if (mfma) SBT_HIP(sbt::launch_mfma_state(n, M, false, xt, xin, st));  // xin == xa (dSB)
                 SBT_HIP(sbt::launch_energy(n, M, q->a, q->row_ptr, q->col, q->b, xin, epart,
                                            etrace + static_cast<size_t>(ck) * M, st));
                 ++ck;
             }
+        }
+        if (mfma) {
+            SBT_HIP(sbt::launch_mfma_state(n, M, false, xt, xin, st));
+            SBT_HIP(sbt::launch_mfma_state(n, M, false, yt, dy, st));
         }
         xfinal = xin;
     }

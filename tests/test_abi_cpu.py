@@ -162,7 +162,9 @@ def test_matrix_core_step_selection_and_workspace():
     """The matrix-core step runs on request only, for dSB with FP8 (per-row
     scale) or BF16X2 couplings; its block lists and operand tiles add at
     most (nnz / 32 + n / 16 + 1) K-steps of 640 (FP8) or 2176 (BF16X2)
-    bytes, and its sign records replace the sign words."""
+    bytes, x and y in its tiles (rows padded to 16, agents to 128) two
+    more copies of the state, and its sign records replace the sign
+    words."""
     n, nnz, row = 1480, 2722, 12
     for prec in ("fp8", "bf16x2"):
         p = sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma")
@@ -175,12 +177,13 @@ def test_matrix_core_step_selection_and_workspace():
                               sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma"))
         assert e.value.code == _lib.SBT_EUNSUPPORTED
     ks = nnz // 32 + (n + 15) // 16 + 1
+    tiles = 2 * 4 * ((n + 15) // 16 * 16) * ((256 + 127) // 128 * 128)
     for prec, per in (("fp8", 640), ("bf16x2", 2176)):
         base = sbt.workspace_bytes(n, nnz, "dsb", sbt.solve_params(agents=256, precision=prec,
                                                                    kernel="stream"))
         mf = sbt.workspace_bytes(n, nnz, "dsb", sbt.solve_params(agents=256, precision=prec,
                                                                  kernel="stream_mfma"))
-        assert base + ks * per <= mf <= base + ks * per + 4 * (n + 16) + 8 * 256
+        assert base + ks * per + tiles <= mf <= base + ks * per + tiles + 4 * (n + 16) + 8 * 256
 
 
 def test_solve_rejects_malformed_qubo_before_touching_a_device():
