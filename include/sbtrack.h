@@ -225,8 +225,10 @@ typedef enum {
                                 grows by about (nnz / 32 + n / 16) x 640
                                 bytes (FP8) or x 2176 (BF16X2), plus x
                                 and y in the step's own tiles (rows
-                                padded to 16, agents to 128).
-                                Only on request (AUTO never picks it)    */
+                                padded to 16, agents to 128).  AUTO
+                                picks it for dSB with FP8 or BF16X2
+                                couplings when x and y together exceed
+                                256 MB (the Infinity Cache)             */
 } sbt_kernel;
 
 /* Storage precision of the couplings J.  The paper fixes no number format

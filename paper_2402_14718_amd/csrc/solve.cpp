@@ -45,14 +45,24 @@ struct Layout {
 // operand tiles.
 bool quad_step(sbt_mode mode, int32_t M) { return mode != SBT_DSB && M % 4 == 0 && M > 64; }
 
+// AUTO runs dSB with FP8 or BF16X2 couplings on the matrix-core step when x
+// and y exceed the 256 MB Infinity Cache (measured on the stress event,
+// N = 2.1e5 x 512 agents: 1.92x / 1.49x the CSR step); cache-resident
+// states keep the CSR step (not measured there).
+bool mfma_auto(sbt_mode mode, int32_t prec, int32_t n, int32_t M) {
+    return mode == SBT_DSB && (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2) &&
+           static_cast<size_t>(n) * static_cast<size_t>(M) * 2 * sizeof(float) > (size_t(256) << 20);
+}
+
 Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, sbt_mode mode,
                    int32_t prec, int32_t kernel_req) {
     const bool tiled = kernel_req == SBT_KERNEL_STREAM_TILE;
     // (AUTO may resolve to the streaming step, so it reserves the lists too)
     const bool quads = quad_step(mode, M) &&
                        (kernel_req == SBT_KERNEL_STREAM || kernel_req == SBT_KERNEL_AUTO);
-    const bool mfma = kernel_req == SBT_KERNEL_STREAM_MFMA && mode == SBT_DSB &&
-                      (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2);
+    const bool mfma = (kernel_req == SBT_KERNEL_STREAM_MFMA && mode == SBT_DSB &&
+                       (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2)) ||
+                      (kernel_req == SBT_KERNEL_AUTO && mfma_auto(mode, prec, n, M));
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -249,6 +259,8 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
         if (p.kernel == SBT_KERNEL_RESIDENT)
             return fail(SBT_EUNSUPPORTED, "FP8 and BF16-pair coupling storage run on the streaming "
                         "kernel only");
+        if (p.kernel == SBT_KERNEL_AUTO && mfma_auto(mode, p.precision, n, p.agents))
+            return SBT_KERNEL_STREAM_MFMA;
         return p.kernel == SBT_KERNEL_AUTO ? stream_kind : p.kernel;
     }
     if (p.kernel == SBT_KERNEL_STREAM || p.kernel == SBT_KERNEL_STREAM_TILE ||

@@ -171,6 +171,15 @@ def test_matrix_core_step_selection_and_workspace():
         assert sbt.select_kernel(n, nnz, row, "dsb", p) == "stream_mfma"
         assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision=prec)) \
             == "stream"
+        # AUTO: the matrix-core step once x, y exceed 256 MB (the stress event's
+        # 208710 spins x 512 agents), the CSR step just below
+        big = sbt.solve_params(agents=512, precision=prec)
+        assert sbt.select_kernel(208710, 11248462, 73, "dsb", big) == "stream_mfma"
+        assert sbt.select_kernel(65536, 3000000, 73, "dsb", big) == "stream"
+        assert sbt.select_kernel(208710, 11248462, 73, "bsb", big) == "stream"
+        assert sbt.select_kernel(208710, 11248462, 73, "dsb",
+                                 sbt.solve_params(agents=512, precision=prec, kernel="stream")) \
+            == "stream"
     for mode, prec in (("bsb", "fp8"), ("asb", "bf16x2"), ("dsb", "fp32"), ("dsb", "fp8_block")):
         with pytest.raises(sbt.SbtError) as e:
             sbt.select_kernel(n, nnz, row, mode,
