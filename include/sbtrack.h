@@ -227,8 +227,7 @@ typedef enum {
                                 and y in the step's own tiles (rows
                                 padded to 16, agents to 128).  AUTO
                                 picks it for dSB with FP8 or BF16X2
-                                couplings when x and y together exceed
-                                256 MB (the Infinity Cache)             */
+                                couplings from n x agents >= 2^23 on     */
 } sbt_kernel;
 
 /* Storage precision of the couplings J.  The paper fixes no number format

@@ -45,13 +45,14 @@ struct Layout {
 // operand tiles.
 bool quad_step(sbt_mode mode, int32_t M) { return mode != SBT_DSB && M % 4 == 0 && M > 64; }
 
-// AUTO runs dSB with FP8 or BF16X2 couplings on the matrix-core step when x
-// and y exceed the 256 MB Infinity Cache (measured on the stress event,
-// N = 2.1e5 x 512 agents: 1.92x / 1.49x the CSR step); cache-resident
-// states keep the CSR step (not measured there).
+// AUTO runs dSB with FP8 or BF16X2 couplings on the matrix-core step from
+// 2^23 spin-agent pairs on (measured, FP8 / BF16X2 against the CSR step:
+// 208710 x 512, 1.92x / 1.49x; 8493 x 1024, cache-resident, 1.33x / 1.06x;
+// 1480 x 256 is launch-bound and the matrix-core step 0.86x / 0.85x).
+constexpr size_t kMfmaAutoPairs = size_t(1) << 23;
 bool mfma_auto(sbt_mode mode, int32_t prec, int32_t n, int32_t M) {
     return mode == SBT_DSB && (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2) &&
-           static_cast<size_t>(n) * static_cast<size_t>(M) * 2 * sizeof(float) > (size_t(256) << 20);
+           static_cast<size_t>(n) * static_cast<size_t>(M) >= kMfmaAutoPairs;
 }
 
 Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, sbt_mode mode,

@@ -171,11 +171,15 @@ def test_matrix_core_step_selection_and_workspace():
         assert sbt.select_kernel(n, nnz, row, "dsb", p) == "stream_mfma"
         assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision=prec)) \
             == "stream"
-        # AUTO: the matrix-core step once x, y exceed 256 MB (the stress event's
-        # 208710 spins x 512 agents), the CSR step just below
+        # AUTO: the matrix-core step from 2^23 spin-agent pairs on (the stress
+        # event, 208710 x 512; the precision event, 8493 x 1024), the CSR
+        # step just below and for bSB
         big = sbt.solve_params(agents=512, precision=prec)
         assert sbt.select_kernel(208710, 11248462, 73, "dsb", big) == "stream_mfma"
-        assert sbt.select_kernel(65536, 3000000, 73, "dsb", big) == "stream"
+        assert sbt.select_kernel(8493, 30964, 12, "dsb",
+                                 sbt.solve_params(agents=1024, precision=prec)) == "stream_mfma"
+        assert sbt.select_kernel(16384, 60000, 12, "dsb", big) == "stream_mfma"   # 2^23 exactly
+        assert sbt.select_kernel(16383, 60000, 12, "dsb", big) == "stream"
         assert sbt.select_kernel(208710, 11248462, 73, "bsb", big) == "stream"
         assert sbt.select_kernel(208710, 11248462, 73, "dsb",
                                  sbt.solve_params(agents=512, precision=prec, kernel="stream")) \
