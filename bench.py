@@ -153,7 +153,7 @@ def precision_form(sbt, tg, torch, np):
                      "ttt_checkpoint": ttt_checkpoint(make(K, TTT_EVERY), K,
                                                       e_star + 0.005 * abs(e_star), torch,
                                                       trace_of)}
-        if name == "fp32" and out[name]["kernel"] == "stream":
+        if name == "fp32" and out[name]["kernel"] in ("stream", "stream_mfma"):
             # one streaming launch per step: its duration from the library's
             # step events, against the step's algorithmic HBM bytes
             b, ev_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -166,15 +166,16 @@ def precision_form(sbt, tg, torch, np):
             s._dr.step_begin = s._dr.step_end = None
             launch_s = b.elapsed_time(ev_) * 1e-3 / K
             byts = stream_bytes_dsb(q.n, q.nnz, M)
-            # x, y in place and the two sign planes: 8 N M + 16 N ceil(M/64)
-            # bytes, ~72 MB here, inside the 256 MB Infinity Cache, so the
-            # streamed bytes need not reach HBM: an effective rate, not an HBM
-            # fraction
+            # x, y in place and the two sign planes (sign words; the
+            # matrix-core step's records are half that): about 8 N M bytes,
+            # ~72 MB here, inside the 256 MB Infinity Cache, so the streamed
+            # bytes need not reach HBM: an effective rate, not an HBM fraction
             state_mb = (8.0 * q.n * M + 16.0 * q.n * ((M + 63) // 64)) / 1e6
+            kname = "sb_stream_mfma" if out[name]["kernel"] == "stream_mfma" else "sb_stream"
             out[name]["roofline"] = {"bound": "cache-resident",
                                      "effective_GBs": byts / launch_s / 1e9,
                                      "state_MB": state_mb, "infinity_cache_MB": 256,
-                                     "kernel": "sb_stream", "launch_ms": launch_s * 1e3,
+                                     "kernel": kname, "launch_ms": launch_s * 1e3,
                                      "bytes_per_launch_if_streamed": byts}
         del s
     e_low = min([e_star] + [out[n]["best"] for n in forms])

@@ -215,19 +215,22 @@ typedef enum {
                                 steps of 32, with the couplings as dense
                                 operand tiles; FP8 (per-row scale: the
                                 codes are the operand, the scale applies
-                                to the row's sum) or BF16X2 (hi and lo
-                                operands) only, other forms and modes
-                                give SBT_EUNSUPPORTED.  The products are
+                                to the row's sum), BF16X2 (hi and lo
+                                operands) or FP32 (split exactly into
+                                three BF16 operands); FP8_BLOCK and other
+                                modes give SBT_EUNSUPPORTED.  The products are
                                 exact; the FP32 sums are added in the
                                 instruction's order, so results differ
                                 from the CSR step by rounding.  Planned
                                 once per solve on the GPU; the workspace
                                 grows by about (nnz / 32 + n / 16) x 640
-                                bytes (FP8) or x 2176 (BF16X2), plus x
+                                bytes (FP8), x 2176 (BF16X2) or x 3200
+                                (FP32), plus x
                                 and y in the step's own tiles (rows
                                 padded to 16, agents to 128).  AUTO
-                                picks it for dSB with FP8 or BF16X2
-                                couplings from n x agents >= 2^23 on     */
+                                picks it for dSB with FP8, BF16X2 or
+                                FP32 couplings from n x agents >= 2^23
+                                on                                       */
 } sbt_kernel;
 
 /* Storage precision of the couplings J.  The paper fixes no number format

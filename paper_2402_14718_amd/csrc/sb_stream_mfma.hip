@@ -11,7 +11,9 @@
 //   FP8 (e4m3, one scale per row): the codes are the operand and the row's
 //     scale multiplies the row's sum once, F_i = h_i + s_i sum_j q_ij sgn_j;
 //   BF16 hi + lo: two products on the same signs, F_i = h_i + sum hi sgn +
-//     sum lo sgn.
+//     sum lo sgn;
+//   FP32: each coupling split exactly into three BF16 terms (8 significant
+//     bits each), three products on the same signs.
 // The positions x and momenta y update in place as in the CSR step
 // (sb_update); the signs live in this step's own records (16 bytes per row
 // and group of 128 agents, bit t of byte c = agent 16 t + c of the group).
@@ -123,10 +125,26 @@ __global__ __launch_bounds__(kScanThreads) void mfma_scan(int nb, const int *__r
     if (t == kScanThreads - 1) off[nb] = tot[t];
 }
 
+// FP32 -> BF16, round to nearest even (finite values).
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+    const uint32_t u = __float_as_uint(v);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+
+// An FP32 coupling as BF16 terms hi + mid + lo, exactly: each residual is
+// exact in FP32 (Sterbenz), the last one has at most 8 significant bits.
+__device__ __forceinline__ void bf16_triple(float v, uint32_t (&t)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        t[k] = bf16_bits(v);
+        v -= __uint_as_float(t[k] << 16);
+    }
+}
+
 // Lists block b's columns and writes every operand word of its K-steps:
 // listed column u (0-based in the block) of row r is element u % 8 of lane
 // 16 ((u % 32) / 8) + r in K-step u / 32 (FP8: byte e of the lane's word;
-// BF16 pairs: hi in words 0-1, lo in words 2-3, 16 bits per element); zeros
+// BF16 terms: term k in words 2 k and 2 k + 1, 16 bits per element); zeros
 // where a row has no coupling and in the padding, whose column repeats the
 // last listed one.  A lane's word is assembled over 8 consecutive listed
 // columns and stored whole.
@@ -159,15 +177,20 @@ __global__ __launch_bounds__(256) void mfma_fill(int nb, StreamArgs A, const int
 #pragma unroll
         for (int r = 0; r < kBR; ++r) {
             if (at[r] < 0) continue;
-            if constexpr (JP == kJBf16x2) {
-                const uint64_t v = A.J2[at[r]];
+            if constexpr (JP == kJBf16x2 || JP == kJFp32) {
+                uint32_t term[3] = {0u, 0u, 0u};
+                if constexpr (JP == kJBf16x2) {
+                    term[0] = A.J2[at[r]] >> 16;
+                    term[1] = A.J2[at[r]] & 0xFFFFu;
+                } else {
+                    bf16_triple(A.J[at[r]], term);
+                }
                 const int sh = 16 * (e % 4);
 #pragma unroll
-                for (int w = 0; w < 2; ++w)
-                    if (e / 4 == w) {
-                        buf[r][w] |= (v >> 16) << sh;
-                        buf[r][2 + w] |= (v & 0xFFFFu) << sh;
-                    }
+                for (int k = 0; k < W / 2; ++k)
+#pragma unroll
+                    for (int w = 0; w < 2; ++w)
+                        if (e / 4 == w) buf[r][2 * k + w] |= static_cast<uint64_t>(term[k]) << sh;
             } else {
                 buf[r][0] |= static_cast<uint64_t>(A.J8[at[r]]) << (8 * e);
             }
@@ -344,24 +367,27 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
             for (int w = 0; w < W; ++w) a8[w] = an[w];
             if (ks + 1 < ks1) load_operand(ks + 1);
             // -sgn(x_j): a set sign bit (x >= 0) gives -1
-            if constexpr (JP == kJBf16x2) {
+            if constexpr (JP == kJBf16x2 || JP == kJFp32) {
                 uint32_t yq[4];  // columns 2q, 2q+1 at bits 0 and 16
 #pragma unroll
                 for (int q = 0; q < 4; ++q) yq[q] = s8[2 * q] | (s8[2 * q + 1] << 16);
-                const u32x4 ahi = {static_cast<uint32_t>(a8[0]), static_cast<uint32_t>(a8[0] >> 32),
-                                   static_cast<uint32_t>(a8[1]), static_cast<uint32_t>(a8[1] >> 32)};
-                const u32x4 alo = {static_cast<uint32_t>(a8[2]), static_cast<uint32_t>(a8[2] >> 32),
-                                   static_cast<uint32_t>(a8[3]), static_cast<uint32_t>(a8[3] >> 32)};
+                bf16x8 aop[W / 2];  // the BF16 terms, largest first
+#pragma unroll
+                for (int k = 0; k < W / 2; ++k) {
+                    const u32x4 a = {static_cast<uint32_t>(a8[2 * k]), static_cast<uint32_t>(a8[2 * k] >> 32),
+                                     static_cast<uint32_t>(a8[2 * k + 1]),
+                                     static_cast<uint32_t>(a8[2 * k + 1] >> 32)};
+                    aop[k] = __builtin_bit_cast(bf16x8, a);
+                }
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
                     u32x4 bv;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) bv[q] = ((yq[q] << (15 - t)) & 0x80008000u) | 0x3F803F80u;
                     const bf16x8 bop = __builtin_bit_cast(bf16x8, bv);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bop, __builtin_bit_cast(bf16x8, ahi),
-                                                                     acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bop, __builtin_bit_cast(bf16x8, alo),
-                                                                     acc[t], 0, 0, 0);
+#pragma unroll
+                    for (int k = 0; k < W / 2; ++k)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bop, aop[k], acc[t], 0, 0, 0);
                 }
             } else {
                 // byte e of xl / xh: the sign byte of column e / e + 4
@@ -420,6 +446,7 @@ hipError_t launch_mfma_plan(int jprec, const StreamArgs &A, const MfmaArgs &P, h
     switch (jprec) {
         case kJFp8: mfma_fill<kJFp8><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
         case kJBf16x2: mfma_fill<kJBf16x2><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
+        case kJFp32: mfma_fill<kJFp32><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -464,6 +491,7 @@ hipError_t launch_stream_mfma(int jprec, const StreamArgs &A, const MfmaArgs &P,
     switch (jprec) {
         case kJFp8: return launch_mfma_form<kJFp8>(A, P, k, x, y, Sin, Sout, st);
         case kJBf16x2: return launch_mfma_form<kJBf16x2>(A, P, k, x, y, Sin, Sout, st);
+        case kJFp32: return launch_mfma_form<kJFp32>(A, P, k, x, y, Sin, Sout, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -19,17 +19,24 @@ namespace sbt {
 // couplings on those columns as one dense operand tile, already in the
 // instruction's register layout (lane 16 g + r holds row r's couplings on
 // listed columns 8 g .. 8 g + 7 of the step; 0 where the row has none).
+// FP32 couplings are split exactly into three BF16 terms, J = hi + mid + lo
+// (8 significant bits each), three operands on the same signs.
 constexpr int kMfmaRows = 16;
 constexpr int kMfmaK = 32;
 
 // 64-bit words of one lane's operand per K-step: eight FP8 codes (one
-// word), or eight BF16 hi followed by eight BF16 lo (four words).
-__host__ __device__ constexpr int mfma_words(int jprec) { return jprec == kJBf16x2 ? 4 : 1; }
+// word), eight BF16 hi then eight BF16 lo (four words), or eight BF16 hi,
+// mid and lo of FP32 couplings (six words).
+__host__ __device__ constexpr int mfma_words(int jprec) {
+    return jprec == kJBf16x2 ? 4 : (jprec == kJFp32 ? 6 : 1);
+}
 
 // Coupling forms the matrix-core step takes: FP8 with one scale per row
-// (the codes are the operand, the scale applies to the row's sum) and the
-// BF16 hi + lo pair (two operands on the same signs).
-__host__ __device__ constexpr bool mfma_form(int jprec) { return jprec == kJFp8 || jprec == kJBf16x2; }
+// (the codes are the operand, the scale applies to the row's sum), the
+// BF16 hi + lo pair and FP32 (two or three BF16 operands on the same signs).
+__host__ __device__ constexpr bool mfma_form(int jprec) {
+    return jprec == kJFp8 || jprec == kJBf16x2 || jprec == kJFp32;
+}
 
 struct MfmaArgs {
     int *kcnt;       // [nb] K-steps of each block (work array of the plan)

@@ -166,11 +166,11 @@ def test_matrix_core_step_selection_and_workspace():
     more copies of the state, and its sign records replace the sign
     words."""
     n, nnz, row = 1480, 2722, 12
-    for prec in ("fp8", "bf16x2"):
+    for prec in ("fp8", "bf16x2", "fp32"):
         p = sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma")
         assert sbt.select_kernel(n, nnz, row, "dsb", p) == "stream_mfma"
         assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision=prec)) \
-            == "stream"
+            in (("stream", "resident") if prec == "fp32" else ("stream",))
         # AUTO: the matrix-core step from 2^23 spin-agent pairs on (the stress
         # event, 208710 x 512; the precision event, 8493 x 1024), the CSR
         # step just below and for bSB
@@ -179,19 +179,21 @@ def test_matrix_core_step_selection_and_workspace():
         assert sbt.select_kernel(8493, 30964, 12, "dsb",
                                  sbt.solve_params(agents=1024, precision=prec)) == "stream_mfma"
         assert sbt.select_kernel(16384, 60000, 12, "dsb", big) == "stream_mfma"   # 2^23 exactly
-        assert sbt.select_kernel(16383, 60000, 12, "dsb", big) == "stream"
+        assert sbt.select_kernel(16383, 60000, 12, "dsb", big) in ("stream", "resident")
         assert sbt.select_kernel(208710, 11248462, 73, "bsb", big) == "stream"
         assert sbt.select_kernel(208710, 11248462, 73, "dsb",
                                  sbt.solve_params(agents=512, precision=prec, kernel="stream")) \
             == "stream"
-    for mode, prec in (("bsb", "fp8"), ("asb", "bf16x2"), ("dsb", "fp32"), ("dsb", "fp8_block")):
+    assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision="fp32",
+                                                                   kernel="stream_mfma")) == "stream_mfma"
+    for mode, prec in (("bsb", "fp8"), ("asb", "bf16x2"), ("bsb", "fp32"), ("dsb", "fp8_block")):
         with pytest.raises(sbt.SbtError) as e:
             sbt.select_kernel(n, nnz, row, mode,
                               sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma"))
         assert e.value.code == _lib.SBT_EUNSUPPORTED
     ks = nnz // 32 + (n + 15) // 16 + 1
     tiles = 2 * 4 * ((n + 15) // 16 * 16) * ((256 + 127) // 128 * 128)
-    for prec, per in (("fp8", 640), ("bf16x2", 2176)):
+    for prec, per in (("fp8", 640), ("bf16x2", 2176), ("fp32", 3200)):
         base = sbt.workspace_bytes(n, nnz, "dsb", sbt.solve_params(agents=256, precision=prec,
                                                                    kernel="stream"))
         mf = sbt.workspace_bytes(n, nnz, "dsb", sbt.solve_params(agents=256, precision=prec,

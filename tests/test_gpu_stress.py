@@ -54,7 +54,7 @@ def test_two_steps_on_sampled_rows(stress, mode, kernel, prec):
     _sampled_rows_after_two_steps(stress, mode, kernel, prec)
 
 
-@pytest.mark.parametrize("prec", ["fp8", "bf16x2"])
+@pytest.mark.parametrize("prec", ["fp8", "bf16x2", "fp32"])
 def test_matrix_core_dsb_two_steps_on_sampled_rows(stress, prec):
     """The matrix-core dSB step in the benchmark's configuration (512
     agents: two sign words per wave; 13045 blocks of 16 rows)."""
