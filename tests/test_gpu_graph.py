@@ -29,10 +29,12 @@ def _capture(run):
 
 
 @pytest.mark.parametrize("mode,kernel", [("dsb", "resident"), ("dsb", "stream"), ("bsb", "stream"),
-                                         ("bsb", "stream_tile")])
+                                         ("bsb", "stream_tile"), ("dsb", "stream_mfma")])
 def test_single_event_solve_replays_bit_identically(mode, kernel):
     """A whole solve captured in a HIP graph, its one-off preparation
-    included (bSB streaming: the row-quad lists; tiled: the tile plan)."""
+    included (bSB streaming: the row-quad lists; tiled: the tile plan;
+    matrix cores: the block plan and the conversions to and from the step's
+    tiled state, FP32 couplings as three BF16 terms)."""
     ev = tg.generate(tg.plain_spec(), 100)
     q = sbt.build_qubo(ev.hits_struct())
     p = sbt.solve_params(agents=128, steps=2000 if kernel == "resident" else 400, seed=3,

@@ -47,8 +47,10 @@ def test_noalloc_equals_workspace_solve_twice_second_smaller():
         r1 = _pair(big, mode, agents=256, steps=400, seed=3, energy_every=50)
         r2 = _pair(small, mode, agents=40, steps=300, seed=5, energy_every=30)
         assert r1["x"].shape == (big.n, 256) and r2["x"].shape == (small.n, 40)
-    # the streaming kernel through the same array
+    # the streaming kernel and the matrix-core step through the same array
     _pair(small, "dsb", agents=96, steps=200, seed=7, kernel="stream")
+    _pair(small, "dsb", agents=96, steps=200, seed=7, kernel="stream_mfma", precision="fp8",
+          energy_every=50)
 
 
 def test_noalloc_refuses_shapes_beyond_its_array():
