@@ -296,6 +296,8 @@ typedef struct {
                           /*   O(T) of every agent at every checkpoint        */
                           /*   (checkpoint-major; checkpoint c is the state   */
                           /*   after (c+1) * energy_every steps)              */
+    int32_t trace_len;    /* out: checkpoints written to trace and            */
+                          /*   agent_trace, steps / energy_every (0 without)  */
 } sbt_result;
 
 /* Solve one QUBO held in host memory: upload, run every step on the GPU,

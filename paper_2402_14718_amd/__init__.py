@@ -216,7 +216,8 @@ def solve(q: Qubo, mode: str, agents: int = 32, steps: int = 2000, dt: float = 1
     return {"T": T, "agent_energy": E, "energy": r.energy, "best_agent": int(r.best_agent),
             "c0": r.c0, "ising_offset": r.ising_offset, "trace": trace, "agent_trace": atrace,
             "x": xf, "y": yf,
-            "kernel": KERNEL_NAMES[int(r.kernel_used)], "elapsed_s": r.elapsed_s}
+            "kernel": KERNEL_NAMES[int(r.kernel_used)], "elapsed_s": r.elapsed_s,
+            "trace_len": int(r.trace_len)}
 
 
 def workspace_bytes(n: int, nnz: int, mode: str, params: _lib.SbtSolveParams) -> int:

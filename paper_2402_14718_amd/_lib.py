@@ -67,7 +67,7 @@ class SbtResult(C.Structure):
                 ("y_final", C.POINTER(C.c_float)), ("energy", C.c_double),
                 ("ising_offset", C.c_double), ("c0", C.c_double), ("best_agent", C.c_int32),
                 ("kernel_used", C.c_int32), ("elapsed_s", C.c_double),
-                ("agent_trace", C.POINTER(C.c_double))]
+                ("agent_trace", C.POINTER(C.c_double)), ("trace_len", C.c_int32)]
 
 
 class SbtDevQubo(C.Structure):

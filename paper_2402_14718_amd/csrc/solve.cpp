@@ -663,5 +663,6 @@ extern "C" int sbt_solve(const sbt_qubo *q, sbt_mode mode, const sbt_solve_param
     out->ising_offset = scal[1];
     out->kernel_used = kernel;
     out->elapsed_s = 1e-3 * ms;
+    out->trace_len = n_ckpt;
     return SBT_OK;
 }

@@ -157,7 +157,7 @@ def test_energy_trace_is_best_so_far(kernel):
     r = sbt.solve(q, "bsb", agents=64, steps=600, seed=1, kernel=kernel, energy_every=50,
                   want_trace=True)
     tr = r["trace"]
-    assert tr.shape == (12,)
+    assert tr.shape == (12,) and r["trace_len"] == 12
     assert np.all(np.diff(tr) <= 0)
     assert abs(tr[-1] - min(r["energy"], tr[-2])) <= 1e-9 * abs(tr[-1])
     b, _ = _oracle_views(q)
