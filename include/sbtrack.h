@@ -216,20 +216,20 @@ typedef enum {
                                 operand tiles; FP8 (per-row scale: the
                                 codes are the operand, the scale applies
                                 to the row's sum), BF16X2 (hi and lo
-                                operands) or FP32 (split exactly into
-                                three BF16 operands); FP8_BLOCK and other
-                                modes give SBT_EUNSUPPORTED.  The products are
+                                operands), FP32 (split exactly into
+                                three BF16 operands) or FP8_BLOCK (each
+                                coupling's FP32 value split the same
+                                way); bSB and aSB give SBT_EUNSUPPORTED.  The products are
                                 exact; the FP32 sums are added in the
                                 instruction's order, so results differ
                                 from the CSR step by rounding.  Planned
                                 once per solve on the GPU; the workspace
                                 grows by about (nnz / 32 + n / 16) x 640
                                 bytes (FP8), x 2176 (BF16X2) or x 3200
-                                (FP32), plus x
+                                (FP32, FP8_BLOCK), plus x
                                 and y in the step's own tiles (rows
                                 padded to 16, agents to 128).  AUTO
-                                picks it for dSB with FP8, BF16X2 or
-                                FP32 couplings from n x agents >= 2^23
+                                picks it for dSB from n x agents >= 2^23
                                 on                                       */
 } sbt_kernel;
 

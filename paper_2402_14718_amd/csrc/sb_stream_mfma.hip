@@ -13,7 +13,8 @@
 //   BF16 hi + lo: two products on the same signs, F_i = h_i + sum hi sgn +
 //     sum lo sgn;
 //   FP32: each coupling split exactly into three BF16 terms (8 significant
-//     bits each), three products on the same signs.
+//     bits each), three products on the same signs; FP8 with a scale per
+//     block of 8 couplings: the FP32 value scale x code, split the same way.
 // The positions x and momenta y update in place as in the CSR step
 // (sb_update); the signs live in this step's own records (16 bytes per row
 // and group of 128 agents, bit t of byte c = agent 16 t + c of the group).
@@ -177,11 +178,13 @@ __global__ __launch_bounds__(256) void mfma_fill(int nb, StreamArgs A, const int
 #pragma unroll
         for (int r = 0; r < kBR; ++r) {
             if (at[r] < 0) continue;
-            if constexpr (JP == kJBf16x2 || JP == kJFp32) {
+            if constexpr (JP == kJBf16x2 || JP == kJFp32 || JP == kJFp8Blk) {
                 uint32_t term[3] = {0u, 0u, 0u};
                 if constexpr (JP == kJBf16x2) {
                     term[0] = A.J2[at[r]] >> 16;
                     term[1] = A.J2[at[r]] & 0xFFFFu;
+                } else if constexpr (JP == kJFp8Blk) {  // the CSR step's decoded value
+                    bf16_triple(A.blkscale[at[r] / kStreamChunk] * e4m3_to_f32<0>(A.J8[at[r]]), term);
                 } else {
                     bf16_triple(A.J[at[r]], term);
                 }
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
             for (int w = 0; w < W; ++w) a8[w] = an[w];
             if (ks + 1 < ks1) load_operand(ks + 1);
             // -sgn(x_j): a set sign bit (x >= 0) gives -1
-            if constexpr (JP == kJBf16x2 || JP == kJFp32) {
+            if constexpr (JP == kJBf16x2 || JP == kJFp32 || JP == kJFp8Blk) {
                 uint32_t yq[4];  // columns 2q, 2q+1 at bits 0 and 16
 #pragma unroll
                 for (int q = 0; q < 4; ++q) yq[q] = s8[2 * q] | (s8[2 * q + 1] << 16);
@@ -447,6 +450,7 @@ hipError_t launch_mfma_plan(int jprec, const StreamArgs &A, const MfmaArgs &P, h
         case kJFp8: mfma_fill<kJFp8><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
         case kJBf16x2: mfma_fill<kJBf16x2><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
         case kJFp32: mfma_fill<kJFp32><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
+        case kJFp8Blk: mfma_fill<kJFp8Blk><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -492,6 +496,7 @@ hipError_t launch_stream_mfma(int jprec, const StreamArgs &A, const MfmaArgs &P,
         case kJFp8: return launch_mfma_form<kJFp8>(A, P, k, x, y, Sin, Sout, st);
         case kJBf16x2: return launch_mfma_form<kJBf16x2>(A, P, k, x, y, Sin, Sout, st);
         case kJFp32: return launch_mfma_form<kJFp32>(A, P, k, x, y, Sin, Sout, st);
+        case kJFp8Blk: return launch_mfma_form<kJFp8Blk>(A, P, k, x, y, Sin, Sout, st);
         default: return hipErrorInvalidValue;
     }
 }

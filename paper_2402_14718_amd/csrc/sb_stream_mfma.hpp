@@ -20,22 +20,25 @@ namespace sbt {
 // instruction's register layout (lane 16 g + r holds row r's couplings on
 // listed columns 8 g .. 8 g + 7 of the step; 0 where the row has none).
 // FP32 couplings are split exactly into three BF16 terms, J = hi + mid + lo
-// (8 significant bits each), three operands on the same signs.
+// (8 significant bits each), three operands on the same signs; FP8 with a
+// scale per block of 8 couplings is decoded to the FP32 value the CSR step
+// uses (scale x code) and split the same way.
 constexpr int kMfmaRows = 16;
 constexpr int kMfmaK = 32;
 
 // 64-bit words of one lane's operand per K-step: eight FP8 codes (one
 // word), eight BF16 hi then eight BF16 lo (four words), or eight BF16 hi,
-// mid and lo of FP32 couplings (six words).
+// mid and lo of FP32 (or block-scaled FP8) couplings (six words).
 __host__ __device__ constexpr int mfma_words(int jprec) {
-    return jprec == kJBf16x2 ? 4 : (jprec == kJFp32 ? 6 : 1);
+    return jprec == kJBf16x2 ? 4 : (jprec == kJFp32 || jprec == kJFp8Blk ? 6 : 1);
 }
 
 // Coupling forms the matrix-core step takes: FP8 with one scale per row
 // (the codes are the operand, the scale applies to the row's sum), the
-// BF16 hi + lo pair and FP32 (two or three BF16 operands on the same signs).
+// BF16 hi + lo pair, FP32 and FP8 with a scale per block of 8 (two or three
+// BF16 operands on the same signs).
 __host__ __device__ constexpr bool mfma_form(int jprec) {
-    return jprec == kJFp8 || jprec == kJBf16x2 || jprec == kJFp32;
+    return jprec == kJFp8 || jprec == kJBf16x2 || jprec == kJFp32 || jprec == kJFp8Blk;
 }
 
 struct MfmaArgs {

@@ -45,15 +45,16 @@ struct Layout {
 // operand tiles.
 bool quad_step(sbt_mode mode, int32_t M) { return mode != SBT_DSB && M % 4 == 0 && M > 64; }
 
-// AUTO runs dSB with FP8, BF16X2 or FP32 couplings on the matrix-core step
-// from 2^23 spin-agent pairs on (measured, FP8 / BF16X2 / FP32 against the
-// CSR step: 208710 x 512, 1.92x / 1.49x / 1.32x; 8493 x 1024, cache-resident,
-// 1.33x / 1.06x / 1.09x; 1480 x 256 is launch-bound and the matrix-core step
-// 0.86x / 0.85x / 0.84x).
+// AUTO runs dSB on the matrix-core step from 2^23 spin-agent pairs on, for
+// every streaming coupling form (measured against the CSR step, FP8 /
+// BF16X2 / FP32 / FP8_BLOCK: 208710 x 512, 1.92x / 1.49x / 1.32x / 1.43x;
+// 8493 x 1024, cache-resident, 1.33x / 1.06x / 1.09x / 1.24x; 1480 x 256
+// is launch-bound and the matrix-core step 0.86x / 0.85x / 0.84x / 0.82x).
 constexpr size_t kMfmaAutoPairs = size_t(1) << 23;
 bool mfma_auto(sbt_mode mode, int32_t prec, int32_t n, int32_t M) {
     return mode == SBT_DSB &&
-           (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2 || prec == SBT_PREC_FP32) &&
+           (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2 || prec == SBT_PREC_FP32 ||
+            prec == SBT_PREC_FP8_BLOCK) &&
            static_cast<size_t>(n) * static_cast<size_t>(M) >= kMfmaAutoPairs;
 }
 
@@ -64,7 +65,8 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
     const bool quads = quad_step(mode, M) &&
                        (kernel_req == SBT_KERNEL_STREAM || kernel_req == SBT_KERNEL_AUTO);
     const bool mfma = (kernel_req == SBT_KERNEL_STREAM_MFMA && mode == SBT_DSB &&
-                       (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2 || prec == SBT_PREC_FP32)) ||
+                       (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2 || prec == SBT_PREC_FP32 ||
+                        prec == SBT_PREC_FP8_BLOCK)) ||
                       (kernel_req == SBT_KERNEL_AUTO && mfma_auto(mode, prec, n, M));
     Layout L;
     size_t off = 0;
@@ -119,7 +121,10 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
     if (mfma) {  // the matrix-core step's blocks and operand tiles
         const size_t nb = (static_cast<size_t>(n) + sbt::kMfmaRows - 1) / sbt::kMfmaRows;
         const size_t ks = sbt::mfma_ksteps_bound(n, nnz);
-        const int jp = prec == SBT_PREC_FP8 ? sbt::kJFp8 : (prec == SBT_PREC_BF16X2 ? sbt::kJBf16x2 : sbt::kJFp32);
+        const int jp = prec == SBT_PREC_FP8         ? sbt::kJFp8
+                       : prec == SBT_PREC_BF16X2    ? sbt::kJBf16x2
+                       : prec == SBT_PREC_FP8_BLOCK ? sbt::kJFp8Blk
+                                                    : sbt::kJFp32;
         L.kcnt = take(sizeof(int32_t) * nb);
         L.koff = take(sizeof(int32_t) * (nb + 1));
         L.kcol = take(sizeof(int32_t) * ks * sbt::kMfmaK);
@@ -252,10 +257,6 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
         if (mode != SBT_DSB)
             return fail(SBT_EUNSUPPORTED, "the matrix-core step is for dSB (bSB and aSB couple "
                         "through continuous positions)");
-        if (p.precision != SBT_PREC_FP8 && p.precision != SBT_PREC_BF16X2 &&
-            p.precision != SBT_PREC_FP32)
-            return fail(SBT_EUNSUPPORTED, "the matrix-core step takes FP8 (per-row scale), BF16X2 "
-                        "or FP32 couplings");
         return SBT_KERNEL_STREAM_MFMA;
     }
     if (p.precision == SBT_PREC_FP8 || p.precision == SBT_PREC_FP8_BLOCK ||

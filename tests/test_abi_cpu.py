@@ -166,7 +166,7 @@ def test_matrix_core_step_selection_and_workspace():
     more copies of the state, and its sign records replace the sign
     words."""
     n, nnz, row = 1480, 2722, 12
-    for prec in ("fp8", "bf16x2", "fp32"):
+    for prec in ("fp8", "bf16x2", "fp32", "fp8_block"):
         p = sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma")
         assert sbt.select_kernel(n, nnz, row, "dsb", p) == "stream_mfma"
         assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision=prec)) \
@@ -186,14 +186,16 @@ def test_matrix_core_step_selection_and_workspace():
             == "stream"
     assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision="fp32",
                                                                    kernel="stream_mfma")) == "stream_mfma"
-    for mode, prec in (("bsb", "fp8"), ("asb", "bf16x2"), ("bsb", "fp32"), ("dsb", "fp8_block")):
+    assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(
+        agents=256, precision="fp8_block", kernel="stream_mfma")) == "stream_mfma"
+    for mode, prec in (("bsb", "fp8"), ("asb", "bf16x2"), ("bsb", "fp32"), ("asb", "fp8_block")):
         with pytest.raises(sbt.SbtError) as e:
             sbt.select_kernel(n, nnz, row, mode,
                               sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma"))
         assert e.value.code == _lib.SBT_EUNSUPPORTED
     ks = nnz // 32 + (n + 15) // 16 + 1
     tiles = 2 * 4 * ((n + 15) // 16 * 16) * ((256 + 127) // 128 * 128)
-    for prec, per in (("fp8", 640), ("bf16x2", 2176), ("fp32", 3200)):
+    for prec, per in (("fp8", 640), ("bf16x2", 2176), ("fp32", 3200), ("fp8_block", 3200)):
         base = sbt.workspace_bytes(n, nnz, "dsb", sbt.solve_params(agents=256, precision=prec,
                                                                    kernel="stream"))
         mf = sbt.workspace_bytes(n, nnz, "dsb", sbt.solve_params(agents=256, precision=prec,
