@@ -121,7 +121,10 @@ def ttt99(make, target, M, torch, energies_of=lambda s: s.result()["agent_energy
 
 def precision_form(sbt, tg, torch, np):
     """1000 particles (N ~ 8.5e3), dSB, 1024 agents x 5000 steps: plain FP32
-    against the 16-bit-coupling forms (one-event batch), with the energy gap
+    against the 16-bit-coupling forms (one-event batch) and the matrix-core
+    streaming step with BF16 couplings and with BF16 hi + lo pairs (16-row
+    blocks of the builder's spin order as dense operands of their column
+    union, signs exact +-1 in BF16, FP32 accumulation), with the energy gap
     to the FP64 oracle (its best over the same 1024 agents) and both
     time-to-target definitions."""
     ref = load_golden("oracle_best_precision.json")
@@ -138,6 +141,13 @@ def precision_form(sbt, tg, torch, np):
                                                      want_trace=every > 0),
                  lambda r: r["energy"], lambda r: r["trace"], lambda r: r["agent_energy"]),
     }
+    for prec in ("bf16", "bf16x2"):
+        forms[f"{prec}_matrix_cores"] = (
+            lambda k, every=0, prec=prec: sbt.DeviceSolver(
+                q, "dsb", sbt.solve_params(agents=M, steps=k, seed=0, energy_every=every,
+                                           kernel="stream_mfma", precision=prec),
+                want_trace=every > 0),
+            lambda r: r["energy"], lambda r: r["trace"], lambda r: r["agent_energy"])
     for prec in ("fp16", "bf16"):
         forms[prec] = (lambda k, every=0, prec=prec: sbt.DeviceBatchSolver(
                            [q], "dsb", prec, prm(k, every), want_agent_energy=True,

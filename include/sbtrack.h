@@ -217,16 +217,18 @@ typedef enum {
                                 codes are the operand, the scale applies
                                 to the row's sum), BF16X2 (hi and lo
                                 operands), FP32 (split exactly into
-                                three BF16 operands) or FP8_BLOCK (each
+                                three BF16 operands), FP8_BLOCK (each
                                 coupling's FP32 value split the same
-                                way); bSB and aSB give SBT_EUNSUPPORTED.  The products are
+                                way), BF16 or FP16 (one operand); bSB
+                                and aSB give SBT_EUNSUPPORTED.  The products are
                                 exact; the FP32 sums are added in the
                                 instruction's order, so results differ
                                 from the CSR step by rounding.  Planned
                                 once per solve on the GPU; the workspace
                                 grows by about (nnz / 32 + n / 16) x 640
-                                bytes (FP8), x 2176 (BF16X2) or x 3200
-                                (FP32, FP8_BLOCK), plus x
+                                bytes (FP8), x 1152 (BF16, FP16), x 2176
+                                (BF16X2) or x 3200 (FP32, FP8_BLOCK),
+                                plus x
                                 and y in the step's own tiles (rows
                                 padded to 16, agents to 128).  AUTO
                                 picks it for dSB from n x agents >= 2^23
@@ -242,8 +244,9 @@ typedef enum {
  * couplings of a row (the last block of a row may be shorter);
  * BF16X2 stores each FP32 coupling as a BF16 pair hi = bf16(J),
  * lo = bf16(J - hi), used as hi + lo (16 significant bits).
- * FP16 and BF16 are the batch functions' forms; FP8, FP8_BLOCK and BF16X2
- * run on the streaming kernel. */
+ * FP16 and BF16 (J rounded once) are the batch functions' forms, and for
+ * dSB the matrix-core streaming step's; FP8, FP8_BLOCK and BF16X2 run on
+ * the streaming kernels. */
 typedef enum {
     SBT_PREC_FP32 = 0,
     SBT_PREC_FP16 = 1,

@@ -14,7 +14,8 @@
 //     sum lo sgn;
 //   FP32: each coupling split exactly into three BF16 terms (8 significant
 //     bits each), three products on the same signs; FP8 with a scale per
-//     block of 8 couplings: the FP32 value scale x code, split the same way.
+//     block of 8 couplings: the FP32 value scale x code, split the same way;
+//   BF16 or FP16 (the FP32 coupling rounded once): one product.
 // The positions x and momenta y update in place as in the CSR step
 // (sb_update); the signs live in this step's own records (16 bytes per row
 // and group of 128 agents, bit t of byte c = agent 16 t + c of the group).
@@ -57,6 +58,7 @@ constexpr int kChunkSteps = 4;   // K-steps whose sign records are staged in LDS
 constexpr int kScanThreads = 1024;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Walks the union of block b's rows (padded CSR; a row's own column marks
@@ -178,9 +180,13 @@ __global__ __launch_bounds__(256) void mfma_fill(int nb, StreamArgs A, const int
 #pragma unroll
         for (int r = 0; r < kBR; ++r) {
             if (at[r] < 0) continue;
-            if constexpr (JP == kJBf16x2 || JP == kJFp32 || JP == kJFp8Blk) {
+            if constexpr (JP != kJFp8) {
                 uint32_t term[3] = {0u, 0u, 0u};
-                if constexpr (JP == kJBf16x2) {
+                if constexpr (JP == kJBf16) {
+                    term[0] = bf16_bits(A.J[at[r]]);
+                } else if constexpr (JP == kJFp16) {
+                    term[0] = __builtin_bit_cast(uint16_t, static_cast<_Float16>(A.J[at[r]]));
+                } else if constexpr (JP == kJBf16x2) {
                     term[0] = A.J2[at[r]] >> 16;
                     term[1] = A.J2[at[r]] & 0xFFFFu;
                 } else if constexpr (JP == kJFp8Blk) {  // the CSR step's decoded value
@@ -370,27 +376,31 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
             for (int w = 0; w < W; ++w) a8[w] = an[w];
             if (ks + 1 < ks1) load_operand(ks + 1);
             // -sgn(x_j): a set sign bit (x >= 0) gives -1
-            if constexpr (JP == kJBf16x2 || JP == kJFp32 || JP == kJFp8Blk) {
+            if constexpr (JP != kJFp8) {
+                // 16-bit operands: +-1 is 0x3F80 | sign in BF16, 0x3C00 | sign in FP16
+                constexpr uint32_t kOne = JP == kJFp16 ? 0x3C003C00u : 0x3F803F80u;
                 uint32_t yq[4];  // columns 2q, 2q+1 at bits 0 and 16
 #pragma unroll
                 for (int q = 0; q < 4; ++q) yq[q] = s8[2 * q] | (s8[2 * q + 1] << 16);
-                bf16x8 aop[W / 2];  // the BF16 terms, largest first
+                u32x4 aop[W / 2];  // the terms, largest first
 #pragma unroll
-                for (int k = 0; k < W / 2; ++k) {
-                    const u32x4 a = {static_cast<uint32_t>(a8[2 * k]), static_cast<uint32_t>(a8[2 * k] >> 32),
-                                     static_cast<uint32_t>(a8[2 * k + 1]),
-                                     static_cast<uint32_t>(a8[2 * k + 1] >> 32)};
-                    aop[k] = __builtin_bit_cast(bf16x8, a);
-                }
+                for (int k = 0; k < W / 2; ++k)
+                    aop[k] = u32x4{static_cast<uint32_t>(a8[2 * k]), static_cast<uint32_t>(a8[2 * k] >> 32),
+                                   static_cast<uint32_t>(a8[2 * k + 1]), static_cast<uint32_t>(a8[2 * k + 1] >> 32)};
 #pragma unroll
                 for (int t = 0; t < T; ++t) {
                     u32x4 bv;
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) bv[q] = ((yq[q] << (15 - t)) & 0x80008000u) | 0x3F803F80u;
-                    const bf16x8 bop = __builtin_bit_cast(bf16x8, bv);
+                    for (int q = 0; q < 4; ++q) bv[q] = ((yq[q] << (15 - t)) & 0x80008000u) | kOne;
 #pragma unroll
-                    for (int k = 0; k < W / 2; ++k)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bop, aop[k], acc[t], 0, 0, 0);
+                    for (int k = 0; k < W / 2; ++k) {
+                        if constexpr (JP == kJFp16)
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                                __builtin_bit_cast(f16x8, bv), __builtin_bit_cast(f16x8, aop[k]), acc[t], 0, 0, 0);
+                        else
+                            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf16x8, bv), __builtin_bit_cast(bf16x8, aop[k]), acc[t], 0, 0, 0);
+                    }
                 }
             } else {
                 // byte e of xl / xh: the sign byte of column e / e + 4
@@ -451,6 +461,8 @@ hipError_t launch_mfma_plan(int jprec, const StreamArgs &A, const MfmaArgs &P, h
         case kJBf16x2: mfma_fill<kJBf16x2><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
         case kJFp32: mfma_fill<kJFp32><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
         case kJFp8Blk: mfma_fill<kJFp8Blk><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
+        case kJBf16: mfma_fill<kJBf16><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
+        case kJFp16: mfma_fill<kJFp16><<<gr, 256, 0, st>>>(nb, A, P.koff, P.kcol, P.kA); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -497,6 +509,8 @@ hipError_t launch_stream_mfma(int jprec, const StreamArgs &A, const MfmaArgs &P,
         case kJBf16x2: return launch_mfma_form<kJBf16x2>(A, P, k, x, y, Sin, Sout, st);
         case kJFp32: return launch_mfma_form<kJFp32>(A, P, k, x, y, Sin, Sout, st);
         case kJFp8Blk: return launch_mfma_form<kJFp8Blk>(A, P, k, x, y, Sin, Sout, st);
+        case kJBf16: return launch_mfma_form<kJBf16>(A, P, k, x, y, Sin, Sout, st);
+        case kJFp16: return launch_mfma_form<kJFp16>(A, P, k, x, y, Sin, Sout, st);
         default: return hipErrorInvalidValue;
     }
 }

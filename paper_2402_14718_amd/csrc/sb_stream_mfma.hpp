@@ -22,7 +22,8 @@ namespace sbt {
 // FP32 couplings are split exactly into three BF16 terms, J = hi + mid + lo
 // (8 significant bits each), three operands on the same signs; FP8 with a
 // scale per block of 8 couplings is decoded to the FP32 value the CSR step
-// uses (scale x code) and split the same way.
+// uses (scale x code) and split the same way.  BF16 and FP16 couplings
+// (the batch functions' forms) are one operand each.
 constexpr int kMfmaRows = 16;
 constexpr int kMfmaK = 32;
 
@@ -30,15 +31,19 @@ constexpr int kMfmaK = 32;
 // word), eight BF16 hi then eight BF16 lo (four words), or eight BF16 hi,
 // mid and lo of FP32 (or block-scaled FP8) couplings (six words).
 __host__ __device__ constexpr int mfma_words(int jprec) {
-    return jprec == kJBf16x2 ? 4 : (jprec == kJFp32 || jprec == kJFp8Blk ? 6 : 1);
+    return jprec == kJBf16x2 ? 4
+           : (jprec == kJFp32 || jprec == kJFp8Blk) ? 6
+           : (jprec == kJBf16 || jprec == kJFp16) ? 2
+                                                   : 1;
 }
 
 // Coupling forms the matrix-core step takes: FP8 with one scale per row
 // (the codes are the operand, the scale applies to the row's sum), the
 // BF16 hi + lo pair, FP32 and FP8 with a scale per block of 8 (two or three
-// BF16 operands on the same signs).
+// BF16 operands on the same signs), BF16 and FP16 (one operand).
 __host__ __device__ constexpr bool mfma_form(int jprec) {
-    return jprec == kJFp8 || jprec == kJBf16x2 || jprec == kJFp32 || jprec == kJFp8Blk;
+    return jprec == kJFp8 || jprec == kJBf16x2 || jprec == kJFp32 || jprec == kJFp8Blk ||
+           jprec == kJBf16 || jprec == kJFp16;
 }
 
 struct MfmaArgs {

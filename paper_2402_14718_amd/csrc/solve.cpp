@@ -50,12 +50,11 @@ bool quad_step(sbt_mode mode, int32_t M) { return mode != SBT_DSB && M % 4 == 0 
 // BF16X2 / FP32 / FP8_BLOCK: 208710 x 512, 1.92x / 1.49x / 1.32x / 1.43x;
 // 8493 x 1024, cache-resident, 1.33x / 1.06x / 1.09x / 1.24x; 1480 x 256
 // is launch-bound and the matrix-core step 0.86x / 0.85x / 0.84x / 0.82x).
+// FP16 and BF16 single solves run only there (the CSR steps do not take
+// them; the batch functions do).
 constexpr size_t kMfmaAutoPairs = size_t(1) << 23;
 bool mfma_auto(sbt_mode mode, int32_t prec, int32_t n, int32_t M) {
-    return mode == SBT_DSB &&
-           (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2 || prec == SBT_PREC_FP32 ||
-            prec == SBT_PREC_FP8_BLOCK) &&
-           static_cast<size_t>(n) * static_cast<size_t>(M) >= kMfmaAutoPairs;
+    return mode == SBT_DSB && static_cast<size_t>(n) * static_cast<size_t>(M) >= kMfmaAutoPairs;
 }
 
 Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, sbt_mode mode,
@@ -64,9 +63,7 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
     // (AUTO may resolve to the streaming step, so it reserves the lists too)
     const bool quads = quad_step(mode, M) &&
                        (kernel_req == SBT_KERNEL_STREAM || kernel_req == SBT_KERNEL_AUTO);
-    const bool mfma = (kernel_req == SBT_KERNEL_STREAM_MFMA && mode == SBT_DSB &&
-                       (prec == SBT_PREC_FP8 || prec == SBT_PREC_BF16X2 || prec == SBT_PREC_FP32 ||
-                        prec == SBT_PREC_FP8_BLOCK)) ||
+    const bool mfma = (kernel_req == SBT_KERNEL_STREAM_MFMA && mode == SBT_DSB) ||
                       (kernel_req == SBT_KERNEL_AUTO && mfma_auto(mode, prec, n, M));
     Layout L;
     size_t off = 0;
@@ -124,6 +121,8 @@ Layout make_layout(int32_t n, int64_t nnz, int32_t M, int32_t K, int32_t every, 
         const int jp = prec == SBT_PREC_FP8         ? sbt::kJFp8
                        : prec == SBT_PREC_BF16X2    ? sbt::kJBf16x2
                        : prec == SBT_PREC_FP8_BLOCK ? sbt::kJFp8Blk
+                       : prec == SBT_PREC_BF16      ? sbt::kJBf16
+                       : prec == SBT_PREC_FP16      ? sbt::kJFp16
                                                     : sbt::kJFp32;
         L.kcnt = take(sizeof(int32_t) * nb);
         L.koff = take(sizeof(int32_t) * (nb + 1));
@@ -246,9 +245,14 @@ int pick_kernel(int32_t n, int64_t nnz, int32_t max_row, sbt_mode mode, const sb
                 sbt::ResidentShape *shape) {
     sbt::ResidentShape S = resident_shape(n, nnz, max_row, p.tpb, lds_limit);
     if (shape) *shape = S;
-    if (p.precision == SBT_PREC_FP16 || p.precision == SBT_PREC_BF16)
+    if (p.precision == SBT_PREC_FP16 || p.precision == SBT_PREC_BF16) {
+        if (mode == SBT_DSB && (p.kernel == SBT_KERNEL_STREAM_MFMA ||
+                                (p.kernel == SBT_KERNEL_AUTO && mfma_auto(mode, p.precision, n, p.agents))))
+            return SBT_KERNEL_STREAM_MFMA;
         return fail(SBT_EUNSUPPORTED,
-                    "16-bit couplings are solved by the batch functions (sbt_solve_batch)");
+                    "16-bit couplings are solved by the batch functions (sbt_solve_batch) and, for "
+                    "dSB, by the matrix-core streaming step");
+    }
     const int stream_kind = SBT_KERNEL_STREAM;
     if (p.kernel == SBT_KERNEL_STREAM_TILE && mode == SBT_DSB)
         return fail(SBT_EUNSUPPORTED, "the tiled streaming step is for bSB and aSB (dSB reads "
@@ -455,6 +459,9 @@ extern "C" int sbt_solve_dev(const sbt_dev_qubo *q, int32_t max_row_nnz, sbt_mod
             A.J8 = J8;
             A.blkscale = blk;
             jprec = sbt::kJFp8Blk;
+        } else if (p->precision == SBT_PREC_BF16 || p->precision == SBT_PREC_FP16) {
+            // the matrix-core step rounds the FP32 couplings itself
+            jprec = p->precision == SBT_PREC_BF16 ? sbt::kJBf16 : sbt::kJFp16;
         } else if (p->precision == SBT_PREC_BF16X2) {
             uint32_t *J2 = reinterpret_cast<uint32_t *>(ws + L.J2);
             SBT_HIP(sbt::launch_split_bf16x2(n, prow, static_cast<int64_t>(pnnz), pJ, J2, st));

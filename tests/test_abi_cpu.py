@@ -166,9 +166,14 @@ def test_matrix_core_step_selection_and_workspace():
     more copies of the state, and its sign records replace the sign
     words."""
     n, nnz, row = 1480, 2722, 12
-    for prec in ("fp8", "bf16x2", "fp32", "fp8_block"):
+    for prec in ("fp8", "bf16x2", "fp32", "fp8_block", "bf16", "fp16"):
         p = sbt.solve_params(agents=256, precision=prec, kernel="stream_mfma")
         assert sbt.select_kernel(n, nnz, row, "dsb", p) == "stream_mfma"
+        if prec in ("bf16", "fp16"):   # below the threshold: the batch functions' forms
+            with pytest.raises(sbt.SbtError) as e:
+                sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision=prec))
+            assert e.value.code == _lib.SBT_EUNSUPPORTED
+            continue
         assert sbt.select_kernel(n, nnz, row, "dsb", sbt.solve_params(agents=256, precision=prec)) \
             in (("stream", "resident") if prec == "fp32" else ("stream",))
         # AUTO: the matrix-core step from 2^23 spin-agent pairs on (the stress

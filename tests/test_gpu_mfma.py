@@ -10,7 +10,8 @@ of agents within it.  Energies are FP64 of the true QUBO.  Shapes cover one
 and two 64-agent sign words per wave, ragged agent counts, partial last
 blocks of 16 rows, rows much longer than one K-step of 32 listed columns,
 empty rows and a single spin.  FP32 couplings run as three exact BF16
-terms, and so do block-scaled FP8 couplings, from their FP32 values."""
+terms, and so do block-scaled FP8 couplings, from their FP32 values;
+BF16 and FP16 couplings (the batch functions' forms) are one operand."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -32,7 +33,8 @@ import paper_2402_14718_amd as sbt  # noqa: E402
 # FP32: the oracle keeps FP64 couplings (the kernel's FP32 rounding of J is
 # inside the bar, as for every FP32 path)
 FORMS = {"fp8": lambda J: oquant.fp8_rows(J)[0], "bf16x2": oquant.bf16x2_couplings,
-         "fp32": lambda J: J, "fp8_block": lambda J: oquant.fp8_blocks(J)[0]}
+         "fp32": lambda J: J, "fp8_block": lambda J: oquant.fp8_blocks(J)[0],
+         "bf16": oquant.bf16_couplings, "fp16": oquant.fp16_couplings}
 
 
 def _random_qubo(n, rows_deg, seed, empty=()):
@@ -84,7 +86,7 @@ def _check(q, prec, M, K, dt, seed):
     return r
 
 
-@pytest.mark.parametrize("prec", ["fp8", "bf16x2", "fp32", "fp8_block"])
+@pytest.mark.parametrize("prec", ["fp8", "bf16x2", "fp32", "fp8_block", "bf16", "fp16"])
 @pytest.mark.parametrize("name", ["plain", "dense"])
 @pytest.mark.parametrize("dt,K,M", [(1.0, 50, 70), (0.1, 20, 96), (0.1, 10, 600), (0.1, 20, 130),
                                     (0.1, 20, 40), (1.0, 30, 64), (0.1, 10, 1)])
