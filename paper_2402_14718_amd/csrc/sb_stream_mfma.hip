@@ -290,11 +290,29 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
     const int lane = threadIdx.x & 63;
     const int M = A.M, R = mfma_groups(M);
     const int nb = (A.n + kBR - 1) / kBR;
-    const int ngb = (nb + 3) / 4;
-    int gb, ab;
-    if (!mfma_block(ngb, R, gb, ab)) return;
-    const int b = __builtin_amdgcn_readfirstlane(gb * 4 + wave);
-    if (b >= nb) return;
+    // When the state streams from HBM (NT), operands wider than one word per
+    // lane (the 16-bit forms) are shared: a workgroup takes one block and up
+    // to four agent groups (one per wave) and stages each chunk's operand
+    // tiles in LDS once for all of them (measured on the stress event: BF16
+    // pairs 0.452 -> 0.400 ms, FP32 0.490 -> 0.434).  Otherwise workgroups
+    // take four blocks of one agent group, with no barriers and a third wave
+    // per SIMD (cache-resident precision event, FP32: 23.6 against 27.8 us
+    // with sharing).
+    constexpr bool kShare = W > 1 && NT;
+    int b, ab;
+    bool active = true;   // the wave has an agent group (shared form: ab < R)
+    if constexpr (kShare) {
+        int ac;
+        if (!mfma_block(nb, (R + 3) / 4, b, ac)) return;
+        b = __builtin_amdgcn_readfirstlane(b);
+        ab = __builtin_amdgcn_readfirstlane(ac * 4 + wave);
+        active = ab < R;
+    } else {
+        int gb;
+        if (!mfma_block((nb + 3) / 4, R, gb, ab)) return;
+        b = __builtin_amdgcn_readfirstlane(gb * 4 + wave);
+        if (b >= nb) return;
+    }
     const int g = lane >> 4, c = lane & 15;
     f32x4 acc[T];
 #pragma unroll
@@ -305,10 +323,12 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
     // coupling sums, so their latency hides behind them.
     const size_t tile = (static_cast<size_t>(b) * R + ab) * (kBR * kMfmaGroup) + 4 * lane;
     f32x4 xp[T], yp[T];
+    if (active) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-        xp[t] = ld_stream<NT>(reinterpret_cast<const f32x4 *>(x + tile + 256 * t));
-        yp[t] = ld_stream<NT>(reinterpret_cast<const f32x4 *>(y + tile + 256 * t));
+        for (int t = 0; t < T; ++t) {
+            xp[t] = ld_stream<NT>(reinterpret_cast<const f32x4 *>(x + tile + 256 * t));
+            yp[t] = ld_stream<NT>(reinterpret_cast<const f32x4 *>(y + tile + 256 * t));
+        }
     }
 
     // The block's sign records pass through LDS, kChunkSteps K-steps at a
@@ -317,7 +337,8 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
     // cost is per instruction), and the K-steps read their sign bytes from
     // LDS.  A 16-byte pad after every 8 slots puts the four lane groups'
     // records on different banks.  Columns are fetched two chunks ahead,
-    // records one chunk ahead, the operand one K-step ahead.
+    // records one chunk ahead; FP8 operands one K-step ahead, shared
+    // operands one chunk ahead (wave w fetches K-step w of the chunk).
     constexpr int kSlots = kChunkSteps * kBK;
     __shared__ uint4 rec_lds[4][kSlots + kSlots / 8];
     uint4 *lds = rec_lds[wave];
@@ -326,6 +347,7 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
     int cn[2];
     uint4 rn[2];
     uint64_t an[W];
+    __shared__ uint64_t op_lds[kShare ? kChunkSteps * 64 * W : 1];
     auto load_cols = [&](int j) {
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
@@ -344,24 +366,47 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
 #pragma unroll
         for (int w = 0; w < W; ++w) an[w] = kA[(static_cast<size_t>(ks) * 64 + lane) * W + w];
     };
+    // shared forms: this wave's K-step of chunk j (kept in `an` until stored)
+    auto load_chunk_operand = [&](int j) {
+        if (j * kChunkSteps + wave < nk) load_operand(ks0 + j * kChunkSteps + wave);
+    };
     if (nch > 0) {
-        load_cols(0);
-        load_recs();
-        if (nch > 1) load_cols(1);
-        load_operand(ks0);
+        if (active) {
+            load_cols(0);
+            load_recs();
+            if (nch > 1) load_cols(1);
+        }
+        if constexpr (kShare)
+            load_chunk_operand(0);
+        else
+            load_operand(ks0);
     }
     for (int j = 0; j < nch; ++j) {
         __builtin_amdgcn_wave_barrier();    // the previous chunk's LDS reads come first
+        if (active) {
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            const int sl = lane + 64 * hh;
-            lds[sl + sl / 8] = rn[hh];
+            for (int hh = 0; hh < 2; ++hh) {
+                const int sl = lane + 64 * hh;
+                lds[sl + sl / 8] = rn[hh];
+            }
+        }
+        if constexpr (kShare) {
+            __syncthreads();                // every wave is done with the previous chunk's operands
+            if (j * kChunkSteps + wave < nk) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) op_lds[(wave * 64 + lane) * W + w] = an[w];
+            }
+            __syncthreads();
         }
         __builtin_amdgcn_wave_barrier();
         if (j + 1 < nch) {
-            load_recs();
-            if (j + 2 < nch) load_cols(j + 2);
+            if (active) {
+                load_recs();
+                if (j + 2 < nch) load_cols(j + 2);
+            }
+            if constexpr (kShare) load_chunk_operand(j + 1);
         }
+        if (!active) continue;
         const int kend = min(kChunkSteps, nk - j * kChunkSteps);
         for (int kk = 0; kk < kend; ++kk) {
             const int ks = ks0 + j * kChunkSteps + kk;
@@ -372,9 +417,14 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
                 const int sl = kk * kBK + 8 * g + e;
                 s8[e] = reinterpret_cast<const uint8_t *>(lds + sl + sl / 8)[c];
             }
+            if constexpr (kShare) {
 #pragma unroll
-            for (int w = 0; w < W; ++w) a8[w] = an[w];
-            if (ks + 1 < ks1) load_operand(ks + 1);
+                for (int w = 0; w < W; ++w) a8[w] = op_lds[(kk * 64 + lane) * W + w];
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w) a8[w] = an[w];
+                if (ks + 1 < ks1) load_operand(ks + 1);
+            }
             // -sgn(x_j): a set sign bit (x >= 0) gives -1
             if constexpr (JP != kJFp8) {
                 // 16-bit operands: +-1 is 0x3F80 | sign in BF16, 0x3C00 | sign in FP16
@@ -422,7 +472,7 @@ __global__ __launch_bounds__(256) void sb_stream_mfma(StreamArgs A, int k, const
     // 128 ab + 16 t + 4 g + r (agents past M are padding: updated, never
     // read back, their sign bits 0)
     const int i = b * kBR + c;
-    if (i >= A.n) return;
+    if (!active || i >= A.n) return;
     const float c0 = static_cast<float>(A.scal[0]);
     const float gk = A.sched[k];
     const float hv = h[i];
@@ -487,10 +537,11 @@ template <int JP>
 hipError_t launch_mfma_form(const StreamArgs &A, const MfmaArgs &P, int k, float *x, float *y,
                             const uint8_t *Sin, uint8_t *Sout, hipStream_t st) {
     const int nb = (A.n + kBR - 1) / kBR;
-    const int total = (nb + 3) / 4 * mfma_groups(A.M);
-    const dim3 grid((total + 7) / 8 * 8);
     // x and y, FP32, past the caches when larger than the Infinity Cache
     const bool nt = static_cast<size_t>(A.n) * A.M * sizeof(float) * 2 > (size_t(256) << 20);
+    const int total = mfma_words(JP) > 1 && nt ? nb * ((mfma_groups(A.M) + 3) / 4)   // shared operands
+                                               : (nb + 3) / 4 * mfma_groups(A.M);
+    const dim3 grid((total + 7) / 8 * 8);
     if (nt)
         sb_stream_mfma<JP, true><<<grid, 256, 0, st>>>(A, k, P.koff, P.kcol, P.kA, A.h, A.rowscale, x, y,
                                                        Sin, Sout);

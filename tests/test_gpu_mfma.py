@@ -19,6 +19,7 @@ import scipy.sparse as sp
 import trackgen as tg
 from oracle import energy as oenergy
 from oracle import ising as oising
+from oracle import philox as ophilox
 from oracle import quant as oquant
 from oracle import sb as osb
 
@@ -49,6 +50,21 @@ def _random_qubo(n, rows_deg, seed, empty=()):
         rows += [i] * len(js)
         cols += list(js)
     B = sp.coo_matrix((rng.uniform(-1, 1, len(rows)), (rows, cols)), shape=(n, n)).tocsr()
+    B = sp.triu(B + B.T, k=1)
+    B = (B + B.T).tocsr()
+    B.sort_indices()
+    return sbt.Qubo(n, rng.uniform(0, 0.7, n), B.indptr.astype(np.int64), B.indices.astype(np.int32),
+                    B.data.astype(np.float64), np.zeros((n, 3), np.int64))
+
+
+def _random_qubo_large(n, deg, seed):
+    """Symmetric random QUBO, about 2 deg couplings per row (vectorised)."""
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), deg)
+    cols = rng.integers(0, n, rows.size)
+    keep = rows != cols
+    B = sp.coo_matrix((rng.uniform(-1, 1, int(keep.sum())), (rows[keep], cols[keep])),
+                      shape=(n, n)).tocsr()
     B = sp.triu(B + B.T, k=1)
     B = (B + B.T).tocsr()
     B.sort_indices()
@@ -131,6 +147,36 @@ def test_matrix_core_dsb_full_length_quality():
     tr = a["trace"]
     assert tr.shape == (10,) and np.all(np.diff(tr) <= 0)
     assert abs(tr[-1] - min(a["energy"], tr[-2])) <= 1e-9 * abs(tr[-1])
+
+
+@pytest.mark.parametrize("prec", ["bf16x2", "fp32"])
+def test_matrix_core_streamed_state_with_a_partial_agent_group(prec):
+    """A state larger than the Infinity Cache (66000 spins x 520 agents,
+    274.6 MB of x, y) takes the streamed path, where workgroups share the
+    wide operands across four agent groups; 520 agents are five groups, so
+    the second workgroup of every block has three idle waves.  Two steps on
+    32 sampled rows against the oracle on their 2-hop neighbourhood (from
+    the same Philox start), as on the stress event."""
+    n, M, K, seed = 66000, 520, 2, 9
+    q = _random_qubo_large(n, 2, 21)
+    assert 8 * n * M > 256 << 20
+    b = sp.csr_matrix((q.b, q.col, q.row_ptr), shape=(n, n))
+    isg = oising.from_qubo(q.a, b)
+    r = sbt.solve(q, "dsb", agents=M, steps=K, seed=seed, precision=prec, kernel="stream_mfma",
+                  want_state=True)
+    rows = np.sort(np.random.default_rng(4).choice(n, 32, replace=False))
+    s1 = np.union1d(rows, b[rows].indices)
+    s2 = np.union1d(s1, b[s1].indices)
+    J = FORMS[prec](isg.J[s2][:, s2].tocsr())
+    x0, y0 = ophilox.initial_state(n, M, seed, 0, spins=s2)
+    ref = osb.run(J, isg.h[s2], isg.c0, "dsb", M, K, seed=seed, x0=x0, y0=y0, margin_steps=K)
+    pos = np.searchsorted(s2, rows)
+    xr, xg = ref.x[pos], r["x"][rows].astype(np.float64)
+    err = np.linalg.norm(xg - xr, axis=0) / np.maximum(np.linalg.norm(xr, axis=0), 1e-30)
+    close = (ref.wall_margin < 1e-6) | (ref.sign_margin < 1e-6)
+    ok = err <= 1e-5
+    assert np.all(ok | close), (err.max(), np.nonzero(~ok & ~close)[0][:5])
+    assert np.mean(ok) >= 0.9
 
 
 @pytest.mark.parametrize("mode,prec", [("bsb", "fp8"), ("asb", "bf16x2"), ("bsb", "fp32"),
