@@ -47,7 +47,7 @@ bool quad_step(sbt_mode mode, int32_t M) { return mode != SBT_DSB && M % 4 == 0 
 
 // AUTO runs dSB on the matrix-core step from 2^23 spin-agent pairs on, for
 // every streaming coupling form (measured against the CSR step, FP8 /
-// BF16X2 / FP32 / FP8_BLOCK: 208710 x 512, 1.92x / 1.49x / 1.32x / 1.43x;
+// BF16X2 / FP32 / FP8_BLOCK: 208710 x 512, 1.92x / 1.68x / 1.46x / 1.43x;
 // 8493 x 1024, cache-resident, 1.33x / 1.06x / 1.09x / 1.24x; 1480 x 256
 // is launch-bound and the matrix-core step 0.86x / 0.85x / 0.84x / 0.82x).
 // FP16 and BF16 single solves run only there (the CSR steps do not take
