@@ -433,9 +433,11 @@ def _step_ms(sbt, torch, q, mode, kernel, prec, M, K):
     return (loop_ms(K) - loop_ms(k1)) / (K - k1)
 
 
-def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=True, dsb_kernel=None):
+def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp8_block", "fp32"), tiled=True,
+                dsb_kernel=None):
     """5000 particles (N ~ 2.1e5), bSB, 512 agents x 10000 steps on the
-    streaming kernel: FP8 couplings (the workload's storage) and FP32, spins
+    streaming kernel: FP8 couplings with a scale per block of 8 (the
+    workload's storage) and per row, and FP32, spins
     in azimuth order, FP64 energies of every agent on the GPU; the tiled
     and one-row bSB steps' launch times beside them, and the dSB step on
     the same event, CSR (sign words as lane masks) against matrix cores.
@@ -482,7 +484,7 @@ def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=T
         launch_s = b.elapsed_time(e) * 1e-3 / K
         best32, _ = sbt.top_k(s.agent_energy, 32)  # FP64 energies of the best 32 agents, on the GPU
         r = s.result()
-        jb = 1 if prec == "fp8" else 4
+        jb = {"fp8": 1, "fp8_block": 1.5}.get(prec, 4)   # stored bytes per coupling (block: + scale / 8)
         if dsb_kernel:
             byts = stream_bytes_dsb(q.n, q.nnz, M, jb)
             kname = "sb_stream_mfma" if dsb_kernel == "stream_mfma" else "sb_stream"
@@ -526,6 +528,9 @@ def stress_form(sbt, tg, torch, np, K=10000, precisions=("fp8", "fp32"), tiled=T
         out["dsb_steps"] = dsb
     if "fp8" in out and "fp32" in out:
         out["fp8_rel_gap_vs_fp32"] = (out["fp8"]["best"] - out["fp32"]["best"]) / abs(out["fp32"]["best"])
+    if "fp8_block" in out and "fp32" in out:
+        out["fp8_block_rel_gap_vs_fp32"] = ((out["fp8_block"]["best"] - out["fp32"]["best"]) /
+                                            abs(out["fp32"]["best"]))
     return out
 
 
@@ -804,7 +809,7 @@ def main():
                          "launches (for counter collection)")
     ap.add_argument("--stress-steps", type=int, default=10000,
                     help="SB steps of the stress form (10000 is the workload's)")
-    ap.add_argument("--stress-prec", choices=["fp8", "fp32", "bf16x2"], default=None,
+    ap.add_argument("--stress-prec", choices=["fp8", "fp8_block", "fp32", "bf16x2"], default=None,
                     help="stress form: only this coupling form, without the tiled comparison "
                          "(profiling one precision's launches)")
     ap.add_argument("--stress-dsb", choices=["stream", "stream_mfma"], default=None,
@@ -854,7 +859,8 @@ def main():
                     "stress": lambda: stress_form(
                         sbt, tg, torch, np, args.stress_steps,
                         (args.stress_prec,) if args.stress_prec else
-                        (("fp8", "bf16x2") if args.stress_dsb == "stream_mfma" else ("fp8", "fp32")),
+                        (("fp8", "bf16x2") if args.stress_dsb == "stream_mfma" else
+                         ("fp8", "fp8_block", "fp32")),
                         tiled=args.stress_prec is None and args.stress_dsb is None,
                         dsb_kernel=args.stress_dsb)}[args.only]
         print(json.dumps({f"{args.only}_form": form()}), flush=True)
