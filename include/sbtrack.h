@@ -173,9 +173,9 @@ int sbt_energy(const sbt_qubo *q, const int8_t *T, double *energy);
  * ---------------------------------------------------------------------- */
 
 /* bSB (Eq. 5-8), dSB (Eq. 9-12), aSB (Eq. 1-4: the quartic potential, no
- * walls; every kernel runs it, and its explicit steps need a dt small
- * enough for the cubic force -- the paper defines it but reports bSB and
- * dSB). */
+ * walls; every kernel but the matrix-core dSB step runs it, and its
+ * explicit steps need a dt small enough for the cubic force -- the paper
+ * defines it but reports bSB and dSB). */
 typedef enum { SBT_BSB = 0, SBT_DSB = 1, SBT_ASB = 2 } sbt_mode;
 
 /* Which step kernel runs.  AUTO picks by problem shape. */
