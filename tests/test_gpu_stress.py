@@ -54,7 +54,7 @@ def test_two_steps_on_sampled_rows(stress, mode, kernel, prec):
     _sampled_rows_after_two_steps(stress, mode, kernel, prec)
 
 
-@pytest.mark.parametrize("prec", ["fp8", "bf16x2", "fp32"])
+@pytest.mark.parametrize("prec", ["fp8", "bf16x2", "fp32", "fp8_block", "bf16"])
 def test_matrix_core_dsb_two_steps_on_sampled_rows(stress, prec):
     """The matrix-core dSB step in the benchmark's configuration (512
     agents: two sign words per wave; 13045 blocks of 16 rows)."""
@@ -77,6 +77,10 @@ def _sampled_rows_after_two_steps(stress, mode, kernel, prec):
         J, _, _ = oquant.fp8_rows(J)     # per-row scales of complete rows
     elif prec == "bf16x2":
         J = oquant.bf16x2_couplings(J)
+    elif prec == "fp8_block":
+        J = oquant.fp8_blocks(J)[0]      # blocks of 8 within complete rows
+    elif prec == "bf16":
+        J = oquant.bf16_couplings(J)
     x0, y0 = ophilox.initial_state(q.n, M, SEED, 0, spins=s2)
     ref = osb.run(J, isg.h[s2], isg.c0, mode, M, K, seed=SEED, x0=x0, y0=y0, margin_steps=K)
     pos = np.searchsorted(s2, rows)
